@@ -1,0 +1,263 @@
+"""CPU oracle for the HashGPU hashing path (test infrastructure).
+
+This package is a plain, single-threaded C implementation (``oracle.c``) of
+what the GPU library computes, wrapped with ctypes.  It is NOT part of the
+product: only the test suite, the smoke check and the benchmark's CPU-baseline
+leg may import it, and it shares no code with the GPU library.
+
+Every routine follows a passage of "GPUs as Storage System Accelerators":
+
+* ``hash``            MD5 (RFC 1321) / SHA-1 (FIPS 180-4), the sequential
+                      building block of Sec. 3.2.2 ("Direct Hashing").
+* ``leaves``/``root`` parallel Merkle-Damgard direct hash, Sec. 3.2.2: segment
+                      digests in one buffer, then the hash of that buffer.
+* ``window_scan``     sliding-window hashing with a boundary predicate,
+                      Sec. 2.1 ("Content-based chunking") and Sec. 3.2.2.
+* ``chunk_select``    boundary decision with a minimum chunk size (Sec. 3.2.2
+                      last stage; min/max chunk sizes of Sec. 4.3).
+* ``chunk_digests``   direct hash of each chunk (Fig. 3 legend, Sec. 3.2.4).
+* ``similarity``      block-map lookup of Sec. 3.2.1 (similarity % of Sec. 4.3).
+
+``map_ranges`` shards independent units (segments, windows) over threads and
+concatenates the per-range results in order; the result is identical to the
+single call by construction.  It exists so that full-size checks and the CPU
+baseline can use the host's cores.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+MD5 = 0
+SHA1 = 1
+DIGEST_SIZE = {MD5: 16, SHA1: 20}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_int = ctypes.c_int
+_vp = ctypes.c_void_p
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (plain C11, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-o", tmp, _SRC, "-lm"],
+            check=True,
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    lib.oracle_init.argtypes = []
+    lib.oracle_init.restype = None
+    lib.oracle_digest_size.argtypes = [_int]
+    lib.oracle_digest_size.restype = _int
+    lib.oracle_hash.argtypes = [_int, _vp, _u64, _vp]
+    lib.oracle_hash.restype = _int
+    lib.oracle_leaf_count.argtypes = [_u64, _u64]
+    lib.oracle_leaf_count.restype = _u64
+    lib.oracle_leaves_range.argtypes = [_int, _vp, _u64, _u64, _u64, _u64, _vp]
+    lib.oracle_leaves_range.restype = _int
+    lib.oracle_root.argtypes = [_int, _vp, _u64, _vp]
+    lib.oracle_root.restype = _int
+    lib.oracle_window_count.argtypes = [_u64, _u64, _u64]
+    lib.oracle_window_count.restype = _u64
+    lib.oracle_window_scan_range.argtypes = [_int, _vp, _u64, _u64, _u64, _u32, _u32,
+                                             _u64, _u64, _vp, _u64]
+    lib.oracle_window_scan_range.restype = _u64
+    lib.oracle_chunk_select.argtypes = [_vp, _u64, _u64, _u64, _u64, _vp, _u64]
+    lib.oracle_chunk_select.restype = _u64
+    lib.oracle_chunk_digests.argtypes = [_int, _vp, _vp, _u64, _vp]
+    lib.oracle_chunk_digests.restype = _int
+    lib.oracle_similarity.argtypes = [_int, _vp, _u64, _vp, _vp, _u64, _vp]
+    lib.oracle_similarity.restype = _u64
+    lib.oracle_init()  # fill the constant tables once, before any threads
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = _bind(_LIB)
+    return _lib
+
+
+def _swap_library(path: str | None):
+    """Bind the wrappers to another build of the oracle (``None`` restores the
+    default).  Used only by the tests that plant a mistake in a copy of
+    ``oracle.c`` and check that the pins catch it."""
+    global _lib
+    _lib = None if path is None else _bind(path)
+
+
+def _bytes_view(data) -> np.ndarray:
+    if isinstance(data, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(data), dtype=np.uint8)
+    arr = np.ascontiguousarray(data, dtype=np.uint8).reshape(-1)
+    return arr
+
+
+def _ptr(arr: np.ndarray) -> int:
+    return arr.ctypes.data if arr.size else 0
+
+
+def digest_size(kind: int) -> int:
+    return DIGEST_SIZE[kind]
+
+
+def hash(kind: int, data) -> bytes:  # noqa: A001 - mirrors the paper's "hash"
+    """Standard MD5 or SHA-1 digest of ``data``."""
+    lib = _load()
+    buf = _bytes_view(data)
+    out = np.zeros(DIGEST_SIZE[kind], dtype=np.uint8)
+    if lib.oracle_hash(kind, _ptr(buf), buf.size, _ptr(out)) != 0:
+        raise ValueError("unknown digest kind")
+    return out.tobytes()
+
+
+def leaf_count(length: int, block: int) -> int:
+    return int(_load().oracle_leaf_count(length, block))
+
+
+def leaves(kind: int, data, block: int, k0: int = 0, k1: int | None = None) -> np.ndarray:
+    """Segment digests (n x d uint8) of segments [k0, k1) (Sec. 3.2.2)."""
+    lib = _load()
+    buf = _bytes_view(data)
+    n = leaf_count(buf.size, block)
+    k1 = n if k1 is None else min(k1, n)
+    d = DIGEST_SIZE[kind]
+    out = np.zeros((max(k1 - k0, 0), d), dtype=np.uint8)
+    if k1 > k0:
+        if lib.oracle_leaves_range(kind, _ptr(buf), buf.size, block, k0, k1, _ptr(out)) != 0:
+            raise ValueError("bad arguments")
+    return out
+
+
+def root(kind: int, leaf_digests: np.ndarray) -> bytes:
+    """Second level of the direct hash: hash of the concatenated digests."""
+    lib = _load()
+    arr = np.ascontiguousarray(leaf_digests, dtype=np.uint8).reshape(-1)
+    d = DIGEST_SIZE[kind]
+    out = np.zeros(d, dtype=np.uint8)
+    lib.oracle_root(kind, _ptr(arr), arr.size // d, _ptr(out))
+    return out.tobytes()
+
+
+def direct_hash(kind: int, data, block: int):
+    lv = leaves(kind, data, block)
+    return lv, root(kind, lv)
+
+
+def window_count(length: int, window: int, stride: int) -> int:
+    return int(_load().oracle_window_count(length, window, stride))
+
+
+def window_scan(kind: int, data, window: int, stride: int, mask: int, target: int,
+                k0: int = 0, k1: int | None = None) -> np.ndarray:
+    """Ascending uint64 start offsets of candidate windows k in [k0, k1)."""
+    lib = _load()
+    buf = _bytes_view(data)
+    nwin = window_count(buf.size, window, stride)
+    k1 = nwin if k1 is None else min(k1, nwin)
+    if k1 <= k0:
+        return np.zeros(0, dtype=np.uint64)
+    cap = min(k1 - k0, 4096 + (k1 - k0) // 256)
+    out = np.zeros(cap, dtype=np.uint64)
+    total = lib.oracle_window_scan_range(kind, _ptr(buf), buf.size, window, stride, mask,
+                                         target, k0, k1, _ptr(out), cap)
+    if total > cap:  # denser than expected: scan again with room for all
+        out = np.zeros(total, dtype=np.uint64)
+        lib.oracle_window_scan_range(kind, _ptr(buf), buf.size, window, stride, mask, target,
+                                     k0, k1, _ptr(out), total)
+    return out[:total].copy()
+
+
+def chunk_select(starts: np.ndarray, window: int, length: int, min_chunk: int) -> np.ndarray:
+    """Chunk end offsets (uint64, last == length) from ascending candidates."""
+    lib = _load()
+    st = np.ascontiguousarray(starts, dtype=np.uint64)
+    cap = st.size + 1
+    out = np.zeros(cap, dtype=np.uint64)
+    m = lib.oracle_chunk_select(_ptr(st), st.size, window, length, min_chunk, _ptr(out), cap)
+    return out[:m].copy()
+
+
+def chunk_digests(kind: int, data, ends: np.ndarray) -> np.ndarray:
+    lib = _load()
+    buf = _bytes_view(data)
+    e = np.ascontiguousarray(ends, dtype=np.uint64)
+    d = DIGEST_SIZE[kind]
+    out = np.zeros((e.size, d), dtype=np.uint8)
+    if e.size:
+        lib.oracle_chunk_digests(kind, _ptr(buf), _ptr(e), e.size, _ptr(out))
+    return out
+
+
+def similarity(kind: int, dig_a: np.ndarray, dig_b: np.ndarray, len_b=None):
+    """(matched, matched_bytes): B chunks, with multiplicity, found in A."""
+    lib = _load()
+    d = DIGEST_SIZE[kind]
+    a = np.ascontiguousarray(dig_a, dtype=np.uint8).reshape(-1, d)
+    b = np.ascontiguousarray(dig_b, dtype=np.uint8).reshape(-1, d)
+    lb = None if len_b is None else np.ascontiguousarray(len_b, dtype=np.uint64)
+    mb = ctypes.c_uint64(0)
+    m = lib.oracle_similarity(kind, _ptr(a), a.shape[0], _ptr(b),
+                              None if lb is None else _ptr(lb), b.shape[0],
+                              ctypes.addressof(mb))
+    return int(m), int(mb.value)
+
+
+def chunk(kind_window: int, kind_chunk: int, data, window: int, stride: int, mask: int,
+          target: int, min_chunk: int, threads: int = 1):
+    """Whole content-based chunking path: candidates, ends, chunk digests."""
+    buf = _bytes_view(data)
+    starts = window_scan_sharded(kind_window, buf, window, stride, mask, target, threads)
+    ends = chunk_select(starts, window, buf.size, min_chunk)
+    return starts, ends, chunk_digests(kind_chunk, buf, ends)
+
+
+def map_ranges(fn, n: int, threads: int, min_per_range: int = 1):
+    """Run ``fn(k0, k1)`` over ``threads`` contiguous ranges of [0, n) and
+    return the per-range results in order (independent units only)."""
+    threads = max(1, int(threads))
+    parts = max(1, min(threads * 4, n // max(min_per_range, 1) or 1))
+    bounds = [n * i // parts for i in range(parts + 1)]
+    ranges = [(bounds[i], bounds[i + 1]) for i in range(parts) if bounds[i + 1] > bounds[i]]
+    if threads == 1 or len(ranges) <= 1:
+        return [fn(a, b) for a, b in ranges]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda r: fn(*r), ranges))
+
+
+def window_scan_sharded(kind, data, window, stride, mask, target, threads=1):
+    buf = _bytes_view(data)
+    nwin = window_count(buf.size, window, stride)
+    parts = map_ranges(lambda a, b: window_scan(kind, buf, window, stride, mask, target, a, b),
+                       nwin, threads, 4096)
+    return np.concatenate(parts) if parts else np.zeros(0, dtype=np.uint64)
+
+
+def leaves_sharded(kind, data, block, threads=1):
+    buf = _bytes_view(data)
+    n = leaf_count(buf.size, block)
+    parts = map_ranges(lambda a, b: leaves(kind, buf, block, a, b), n, threads)
+    d = DIGEST_SIZE[kind]
+    return np.concatenate(parts) if parts else np.zeros((0, d), dtype=np.uint8)
