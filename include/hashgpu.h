@@ -1,0 +1,180 @@
+/*
+ * hashgpu.h -- C ABI of the MI355X (gfx950) HashGPU hashing library.
+ *
+ * The library implements the two hashing primitives of "GPUs as Storage
+ * System Accelerators" (Al-Kiswany, Gharaibeh, Ripeanu), Sec. 2.1 and
+ * Sec. 3.2.2:
+ *   - direct hashing of a large block with the parallel Merkle-Damgard
+ *     construction (segment digests, then the hash of the digest buffer);
+ *   - content-based chunking: sliding-window hashing at every stride-aligned
+ *     offset, boundary detection, per-chunk digests, and the similarity of
+ *     two versions' chunk digests (the block-map comparison of Sec. 3.2.1).
+ * Every step runs in the library's HIP kernels on the GPU.
+ *
+ * Conventions for every entry point
+ *   - Return value: HG_OK (0) or a negative HG_E* status; nothing throws
+ *     across the ABI.  hg_last_error() gives the text of the last failure.
+ *   - Pointers: `in`-type arguments are device pointers when `flags` has
+ *     HG_IN_DEVICE, host pointers otherwise; output arguments (digests,
+ *     offsets, counts) are device pointers when `flags` has HG_OUT_DEVICE,
+ *     host pointers otherwise.  Host input is copied to device memory owned
+ *     by the context; host output is copied back before the call returns.
+ *   - Stream: `stream` is a hipStream_t (NULL = the default stream).  All
+ *     GPU work of the call is ordered on it.
+ *   - Synchrony: without HG_ASYNC the call returns when its results are in
+ *     the caller's memory.  HG_ASYNC (valid only with HG_IN_DEVICE and
+ *     HG_OUT_DEVICE, and only for hg_block_hash, hg_window_scan and
+ *     hg_similarity) returns after enqueueing; results are valid once the
+ *     stream has completed, and truncation can then only be seen by comparing
+ *     the written count with the capacity.
+ *   - Ownership: the caller owns every buffer it passes and keeps it alive
+ *     until the results are valid; the library retains no caller pointer
+ *     after that.  A context owns its device scratch, pinned staging memory
+ *     and helper streams.
+ *   - Concurrency: one context serves one caller thread and one stream at a
+ *     time (its scratch is reused from call to call); use one context per
+ *     concurrent stream.
+ *   - Digest bytes are in the standard byte order of each hash (MD5 words
+ *     little-endian, SHA-1 words big-endian), i.e. exactly the bytes a
+ *     sequential implementation prints.
+ */
+#ifndef HASHGPU_H
+#define HASHGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hg_ctx hg_ctx;
+
+/* Digest types (the paper's experiments use MD5; SHA-1 is the second
+ * standard sequential hash offered). */
+enum { HG_MD5 = 0, HG_SHA1 = 1 };
+
+/* Status codes. */
+enum {
+    HG_OK = 0,
+    HG_EINVAL = -1,  /* bad argument: NULL required pointer, zero size, unknown digest, flag misuse */
+    HG_ENOMEM = -2,  /* device or pinned allocation failed */
+    HG_EDEVICE = -3, /* no usable gfx950 device, or a HIP runtime error (see hg_last_error) */
+    HG_ETRUNC = -4,  /* output capacity too small; counts hold the full size, outputs the first
+                        `capacity` entries */
+    HG_EBUSY = -5    /* resource temporarily unavailable */
+};
+
+/* Flags. */
+enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u };
+
+/* Limits of the sliding-window primitive. */
+enum { HG_MAX_WINDOW = 4096 };
+
+/* ------------------------------------------------------------- context -- */
+
+/* Creates a context on HIP device `device` (that device becomes current for
+ * the calling thread).  Returns HG_EDEVICE if the device does not exist or
+ * is not a gfx950 GPU.  *out receives the context. */
+int hg_create(int device, hg_ctx **out);
+
+/* Synchronizes the context's work and frees everything it owns.  NULL is a
+ * no-op. */
+void hg_destroy(hg_ctx *ctx);
+
+/* Static text of a status code. */
+const char *hg_strerror(int status);
+
+/* Copies the text of the context's last failure (NUL-terminated, truncated
+ * to n bytes) into buf; returns the status of that failure (HG_OK if none). */
+int hg_last_error(const hg_ctx *ctx, char *buf, size_t n);
+
+/* Digest size in bytes: 16 for HG_MD5, 20 for HG_SHA1, HG_EINVAL otherwise. */
+int hg_digest_size(int digest);
+
+/* Pinned (page-locked) host memory from the context, for one-copy transfers
+ * (Sec. 3.1: data handed to the GPU should already sit in non-pageable
+ * memory, and such buffers should be allocated once and reused).  Freed by
+ * hg_host_free or by hg_destroy. */
+int hg_host_alloc(hg_ctx *ctx, size_t bytes, void **out);
+int hg_host_free(hg_ctx *ctx, void *p);
+
+/* ------------------------------------------------------ direct hashing -- */
+
+/* Direct hash with the parallel Merkle-Damgard construction (Sec. 3.2.2,
+ * "Direct Hashing").
+ *   in, len     the block (len may be 0; in may then be NULL).
+ *   block_size  segment size B >= 1.  Segment k covers
+ *               [k*B, min((k+1)*B, len)); a short last segment is hashed as
+ *               it is, with the standard padding.  n = ceil(len / B).
+ *   digest      HG_MD5 or HG_SHA1 (used for both levels).
+ *   leaf_out    n * digest_size bytes: segment digests in segment order; may
+ *               be NULL when only the root is wanted.
+ *   root_out    digest_size bytes: digest of the concatenated segment
+ *               digests (for len = 0, the digest of the empty string); may be
+ *               NULL.  At least one of leaf_out, root_out is required.
+ * With a host `in` the block is streamed to the GPU in pieces through pinned
+ * staging buffers, overlapping copies with hashing. */
+int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, int digest,
+                  void *leaf_out, void *root_out, uint32_t flags, void *stream);
+
+/* ---------------------------------------------- content-based chunking -- */
+
+/* Sliding-window hashing (Sec. 2.1, "Content-based chunking"; Sec. 3.2.2).
+ *   window      w, 1 <= w <= HG_MAX_WINDOW bytes.
+ *   stride      s >= 1.  Windows start at i = k*s (k >= 0) and satisfy
+ *               i + w <= len, so there are floor((len - w)/s) + 1 windows
+ *               when len >= w and none otherwise (not an error).
+ *   mask,target a window is a boundary candidate iff
+ *               (u32le(D[0..3]) & mask) == target, where D is the standard
+ *               digest (`digest`) of the w window bytes and u32le reads its
+ *               first four bytes as a little-endian integer.
+ *   starts      capacity entries of uint64: ascending start offsets of the
+ *               candidates (may be NULL when capacity is 0).
+ *   count       one uint64: the number of candidates (always the full number).
+ * Returns HG_ETRUNC (after writing the first `capacity` starts) when more
+ * candidates exist than fit. */
+int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, uint32_t stride,
+                   uint32_t mask, uint32_t target, int digest, uint64_t *starts,
+                   uint64_t capacity, uint64_t *count, uint32_t flags, void *stream);
+
+typedef struct {
+    uint32_t window, stride, mask, target; /* as for hg_window_scan */
+    uint64_t min_chunk;   /* minimum chunk size in bytes (0 = none) */
+    uint64_t max_chunk;   /* must be 0: forced cuts are not supported */
+    int32_t window_digest; /* digest of the sliding windows */
+    int32_t chunk_digest;  /* digest of each chunk */
+} hg_chunk_params;
+
+/* Content-based chunking of one block: window scan, boundary decision and
+ * chunk digests (Fig. 3 legend; Sec. 3.2.4).
+ * Boundary decision: a candidate window starting at i proposes the cut
+ * e = i + w; scanning candidates in ascending order, e becomes a cut iff
+ * e < len and e - last >= max(min_chunk, 1), where last is the previous cut
+ * (initially 0).  The final chunk ends at len.  len = 0 gives no chunks.
+ *   ends           capacity entries of uint64: ascending chunk end offsets
+ *                  (the last one is len).  Chunk j is [ends[j-1], ends[j])
+ *                  with ends[-1] = 0.
+ *   n_chunks       one uint64: the number of chunks (always the full number).
+ *   chunk_digests  capacity * digest_size(chunk_digest) bytes, or NULL.
+ * Returns HG_ETRUNC when n_chunks > capacity (outputs hold the first
+ * `capacity` chunks).  HG_ASYNC is not accepted. */
+int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *params,
+             uint64_t *ends, uint64_t capacity, uint64_t *n_chunks, void *chunk_digests,
+             uint32_t flags, void *stream);
+
+/* Similarity of two versions' chunk digests (the block-map comparison of
+ * Sec. 3.2.1): *matched = number of B's chunks, counted with multiplicity,
+ * whose digest occurs among A's n_a digests; *matched_bytes = sum of len_b
+ * over those chunks (0 when len_b is NULL).  dig_a, dig_b, len_b are inputs
+ * (HG_IN_DEVICE); matched, matched_bytes are outputs (HG_OUT_DEVICE).
+ * matched_bytes may be NULL. */
+int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b,
+                  const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
+                  uint64_t *matched_bytes, uint32_t flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HASHGPU_H */

@@ -1,0 +1,416 @@
+// window_scan.hip -- sliding-window hashing for content-based chunking
+// (paper Sec. 2.1 "Content-based chunking" and Sec. 3.2.2): every window of
+// w bytes that starts at a multiple of the stride is hashed with the
+// standard hash, and a window whose digest matches the predefined value
+// ((u32le(D[0..3]) & mask) == target) is a boundary candidate.
+//
+// gfx950 design.  The paper's GPU kept every window hash in one output
+// buffer and let the CPU scan it; here the test runs in the kernel and only
+// candidates leave the chip, in ascending order, through three passes:
+//   1. count: each 256-lane workgroup owns a tile of consecutive windows;
+//      lanes hash their windows, a wavefront scan (DPP/ds_bpermute
+//      shuffles) plus an LDS combine ranks the candidates, the tile count is
+//      stored and up to WS_CAP tile-local indices go to a per-tile bucket;
+//   2. scan: one workgroup turns tile counts into tile offsets and a total,
+//      and lists tiles whose count exceeded WS_CAP;
+//   3. emit: buckets are copied to their offsets; listed (dense) tiles are
+//      hashed again and written directly.
+// Two window-loading variants:
+//   * registers (w = 20, stride 1 or 4): a lane owns 16 consecutive windows
+//     and loads the bytes they span once with 16-byte vector loads; the 16
+//     windows are cut out of those registers with v_alignbyte_b32.  The
+//     message words past the window are compile-time constants, so their
+//     steps fold to a single add of a constant.
+//   * LDS (any w up to 4096, any stride, MD5 or SHA-1): the tile's bytes are
+//     staged once in LDS and each lane reads its windows from there.
+#include "hg_device.hpp"
+#include "hg_internal.hpp"
+
+namespace hg {
+
+constexpr int WS_G = 16;                  // windows per lane in the register variants
+constexpr uint32_t WS_LDS_MAX = 48 * 1024;  // LDS budget of the generic variant
+
+// -------------------------------------------------------- block ranking --
+// Exclusive prefix of v over the workgroup and the workgroup total.  Must be
+// reached by every lane of the workgroup.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t &total) {
+    __shared__ uint32_t wave_sum[WS_TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sum[wid] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < WS_TPB / 64; i++) {
+        uint32_t c = wave_sum[i];
+        base += i < wid ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+// ---------------------------------------------- register variant (w=20) --
+// Message word j of the single padded MD5 block of the window that starts
+// `off` bytes into the lane's dword array dw (all indices compile-time).
+template <int W, int ND>
+__device__ __forceinline__ uint32_t win_word(const uint32_t (&dw)[ND], const int off, const int j) {
+    if (4 * j < W) {
+        const int o = off + 4 * j, q = o >> 2, sh = o & 3;
+        const int valid = W - 4 * j < 4 ? W - 4 * j : 4;
+        uint32_t lo = dw[q];
+        uint32_t hi = (q + 1 < ND) ? dw[q + 1] : 0u;
+        uint32_t v = sh ? __builtin_amdgcn_alignbyte(hi, lo, sh) : lo;
+        if (valid < 4) v = (v & ((1u << (8 * valid)) - 1u)) | (0x80u << (8 * valid));
+        return v;
+    }
+    if (4 * j == W) return 0x80u;
+    if (j == 14) return (uint32_t)W * 8u;
+    return 0u;
+}
+
+// Candidate bits of the lane's WS_G windows (bit g = window k0 + g).
+template <int W, int S>
+__device__ __forceinline__ uint32_t ws_reg_bits(const uint8_t *__restrict__ in, uint64_t len,
+                                                uint64_t nwin, uint32_t mask, uint32_t target,
+                                                uint64_t tile) {
+    constexpr int SPAN = (WS_G - 1) * S + W;
+    constexpr int ND = (SPAN + 3) / 4;
+    const uint64_t k0 = tile * (uint64_t)(WS_TPB * WS_G) + (uint64_t)threadIdx.x * WS_G;
+    if (k0 >= nwin) return 0;
+    const uint64_t b0 = k0 * S;  // multiple of 16 * S: 16-byte aligned
+    uint32_t dw[ND];
+    if (b0 + 4 * ND <= len) {
+        __builtin_memcpy(dw, in + b0, 4 * ND);
+    } else {
+        // Last lanes of the buffer: dword-wise, and only dwords that start
+        // before len (each such aligned dword holds at least one byte of
+        // the buffer).  Bytes past len only feed windows k >= nwin.
+#pragma unroll
+        for (int j = 0; j < ND; j++) {
+            uint32_t v = 0;
+            if (b0 + 4 * j < len) __builtin_memcpy(&v, in + b0 + 4 * j, 4);
+            dw[j] = v;
+        }
+    }
+    const uint32_t st[4] = {MD5_IV0, MD5_IV1, MD5_IV2, MD5_IV3};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int g = 0; g < WS_G; g++) {
+        uint32_t X[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) X[j] = win_word<W, ND>(dw, g * S, j);
+        uint32_t a0 = md5_compress_word0(st, X);
+        bool hit = ((a0 & mask) == target) && (k0 + g < nwin);
+        bits |= (uint32_t)hit << g;
+    }
+    return bits;
+}
+
+template <int W, int S>
+__global__ __launch_bounds__(WS_TPB) void ws_reg_count(const uint8_t *__restrict__ in, uint64_t len,
+                                                       uint64_t nwin, uint32_t mask, uint32_t target,
+                                                       uint32_t *__restrict__ tile_count,
+                                                       uint32_t *__restrict__ bucket) {
+    const uint64_t tile = blockIdx.x;
+    uint32_t bits = ws_reg_bits<W, S>(in, len, nwin, mask, target, tile);
+    uint32_t total;
+    uint32_t pre = block_exclusive(__popc(bits), total);
+    if (threadIdx.x == 0) tile_count[tile] = total;
+    if (total <= WS_CAP) {
+        uint32_t *bk = bucket + tile * WS_CAP + pre;
+        while (bits) {
+            int g = __ffs(bits) - 1;
+            bits &= bits - 1;
+            *bk++ = threadIdx.x * WS_G + g;
+        }
+    }
+}
+
+template <int W, int S>
+__global__ __launch_bounds__(WS_TPB) void ws_reg_direct(const uint8_t *__restrict__ in, uint64_t len,
+                                                        uint64_t nwin, uint32_t mask, uint32_t target,
+                                                        const uint32_t *__restrict__ ovf_list,
+                                                        const uint32_t *__restrict__ ovf_count,
+                                                        const uint64_t *__restrict__ tile_off,
+                                                        uint64_t *__restrict__ out, uint64_t cap) {
+    const uint32_t n_ovf = *ovf_count;
+    for (uint32_t i = blockIdx.x; i < n_ovf; i += gridDim.x) {
+        const uint64_t tile = ovf_list[i];
+        uint32_t bits = ws_reg_bits<W, S>(in, len, nwin, mask, target, tile);
+        uint32_t total;
+        uint32_t pre = block_exclusive(__popc(bits), total);
+        uint64_t pos = tile_off[tile] + pre;
+        const uint64_t k0 = tile * (uint64_t)(WS_TPB * WS_G) + (uint64_t)threadIdx.x * WS_G;
+        while (bits) {
+            int g = __ffs(bits) - 1;
+            bits &= bits - 1;
+            if (pos < cap) out[pos] = (k0 + g) * S;
+            pos++;
+        }
+    }
+}
+
+// ------------------------------------------------------ generic variant --
+// Reads the 32-bit little-endian word at byte offset o of the LDS tile.
+__device__ __forceinline__ uint32_t lds_word(const uint32_t *lds, uint32_t o) {
+    const uint32_t q = o >> 2, sh = o & 3;
+    return __builtin_amdgcn_alignbyte(lds[q + 1], lds[q], sh);
+}
+
+// Digest bytes 0..3 (little-endian) of the standard hash of the w bytes at
+// LDS byte offset o.
+template <int KIND>
+__device__ __forceinline__ uint32_t lds_hash_word0(const uint32_t *lds, uint32_t o, uint32_t w) {
+    uint32_t st[5];
+    Hash<KIND>::init(st);
+    uint32_t X[16];
+    const uint32_t full = w >> 6;
+    for (uint32_t b = 0; b < full; b++) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) X[j] = lds_word(lds, o + 64 * b + 4 * j);
+        Hash<KIND>::block(st, X);
+    }
+    const int rem = (int)(w & 63);
+    const uint32_t ot = o + 64 * full;
+#pragma unroll
+    for (int j = 0; j < 16; j++) X[j] = (4 * j < rem) ? lds_word(lds, ot + 4 * j) : 0u;
+    finish_tail<KIND>(st, X, rem, w);
+    return Hash<KIND>::word0(st);
+}
+
+struct GenArgs {
+    const uint8_t *in;
+    uint64_t len, nwin, tile_windows;
+    uint32_t w, s, mask, target;
+};
+
+// One tile: stage its bytes in LDS, hash its windows in rounds of WS_TPB
+// consecutive windows (lane i takes window round*WS_TPB + i), rank
+// candidates in window order.  EMIT = false: count + bucket; EMIT = true:
+// write offsets at tile_off[tile] onward.
+template <int KIND, bool EMIT>
+__device__ __forceinline__ void ws_gen_tile(const GenArgs &a, uint64_t tile, uint32_t *lds,
+                                            uint32_t *tile_count, uint32_t *bucket,
+                                            const uint64_t *tile_off, uint64_t *out, uint64_t cap) {
+    const uint64_t kf = tile * a.tile_windows;
+    const uint64_t ke = kf + a.tile_windows < a.nwin ? kf + a.tile_windows : a.nwin;
+    const uint8_t *src = a.in + kf * a.s;
+    const uintptr_t base = (uintptr_t)src & ~(uintptr_t)3;
+    const uint32_t delta = (uint32_t)((uintptr_t)src - base);
+    const uint64_t nbytes = (ke - 1) * a.s + a.w - kf * a.s + delta;
+    const uint32_t ndw = (uint32_t)((nbytes + 3) >> 2);
+    const uintptr_t end = (uintptr_t)(a.in + a.len);
+    for (uint32_t i = threadIdx.x; i <= ndw; i += WS_TPB) {
+        const uintptr_t addr = base + 4ull * i;
+        // An aligned dword that starts before the buffer end holds at least
+        // one byte of the buffer; the pad dword at index ndw is zero.
+        lds[i] = (i < ndw && addr < end) ? *(const uint32_t *)addr : 0u;
+    }
+    __syncthreads();
+    uint32_t done = 0;
+    const uint64_t pos0 = EMIT ? tile_off[tile] : 0;
+    for (uint64_t r0 = 0; r0 < ke - kf; r0 += WS_TPB) {
+        const uint64_t k = kf + r0 + threadIdx.x;
+        bool hit = false;
+        if (k < ke) {
+            const uint32_t o = delta + (uint32_t)((r0 + threadIdx.x) * a.s);
+            hit = (lds_hash_word0<KIND>(lds, o, a.w) & a.mask) == a.target;
+        }
+        uint32_t total;
+        const uint32_t pre = block_exclusive(hit ? 1u : 0u, total);
+        if (hit) {
+            const uint32_t rank = done + pre;
+            if (EMIT) {
+                if (pos0 + rank < cap) out[pos0 + rank] = k * a.s;
+            } else if (rank < (uint32_t)WS_CAP) {
+                bucket[tile * WS_CAP + rank] = (uint32_t)(r0 + threadIdx.x);
+            }
+        }
+        done += total;
+    }
+    if (!EMIT && threadIdx.x == 0) tile_count[tile] = done;
+    __syncthreads();  // the LDS tile may be restaged by the next tile
+}
+
+template <int KIND>
+__global__ __launch_bounds__(WS_TPB) void ws_gen_count(GenArgs a, uint32_t *__restrict__ tile_count,
+                                                       uint32_t *__restrict__ bucket) {
+    extern __shared__ uint32_t lds[];
+    ws_gen_tile<KIND, false>(a, blockIdx.x, lds, tile_count, bucket, nullptr, nullptr, 0);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(WS_TPB) void ws_gen_direct(GenArgs a, const uint32_t *__restrict__ ovf_list,
+                                                        const uint32_t *__restrict__ ovf_count,
+                                                        const uint64_t *__restrict__ tile_off,
+                                                        uint64_t *__restrict__ out, uint64_t cap) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t n_ovf = *ovf_count;
+    for (uint32_t i = blockIdx.x; i < n_ovf; i += gridDim.x)
+        ws_gen_tile<KIND, true>(a, ovf_list[i], lds, nullptr, nullptr, tile_off, out, cap);
+}
+
+// ------------------------------------------------- scan and emit passes --
+constexpr int SCAN_TPB = 1024;
+
+__global__ __launch_bounds__(SCAN_TPB) void ws_scan_tiles(const uint32_t *__restrict__ tile_count,
+                                                          uint64_t n_tiles, uint64_t *__restrict__ tile_off,
+                                                          uint64_t *__restrict__ total_out,
+                                                          uint32_t *__restrict__ ovf_list,
+                                                          uint32_t *__restrict__ ovf_count) {
+    __shared__ uint64_t part[SCAN_TPB];
+    const uint32_t t = threadIdx.x;
+    if (t == 0) *ovf_count = 0;
+    const uint64_t per = (n_tiles + SCAN_TPB - 1) / SCAN_TPB;
+    const uint64_t lo = t * per < n_tiles ? t * per : n_tiles;
+    const uint64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
+    uint64_t sum = 0;
+    for (uint64_t i = lo; i < hi; i++) sum += tile_count[i];
+    part[t] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the per-thread sums.
+    for (int off = 1; off < SCAN_TPB; off <<= 1) {
+        uint64_t v = t >= (uint32_t)off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint64_t base = part[t] - sum;
+    for (uint64_t i = lo; i < hi; i++) {
+        const uint32_t c = tile_count[i];
+        tile_off[i] = base;
+        base += c;
+        if (c > (uint32_t)WS_CAP) ovf_list[atomicAdd(ovf_count, 1u)] = (uint32_t)i;
+    }
+    if (t == SCAN_TPB - 1) *total_out = part[t];
+}
+
+__global__ __launch_bounds__(256) void ws_gather(const uint32_t *__restrict__ tile_count,
+                                                 const uint32_t *__restrict__ bucket,
+                                                 const uint64_t *__restrict__ tile_off, uint64_t n_tiles,
+                                                 uint64_t tile_windows, uint32_t s,
+                                                 uint64_t *__restrict__ out, uint64_t cap) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t c = tile_count[t];
+    if (c == 0 || c > (uint32_t)WS_CAP) return;
+    const uint64_t off = tile_off[t];
+    for (uint32_t i = 0; i < c; i++) {
+        if (off + i < cap) out[off + i] = (t * tile_windows + bucket[t * WS_CAP + i]) * s;
+    }
+}
+
+__global__ void ws_zero_u64(uint64_t *p) { *p = 0; }
+
+// ----------------------------------------------------------------- host --
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsScratch {
+    uint32_t *tile_count, *bucket, *ovf_list, *ovf_count;
+    uint64_t *tile_off;
+};
+
+static WsScratch carve(const WsPlan &p, void *scratch) {
+    uint8_t *q = (uint8_t *)scratch;
+    WsScratch s;
+    s.tile_off = (uint64_t *)q;  q += align256(p.n_tiles * 8);
+    s.tile_count = (uint32_t *)q; q += align256(p.n_tiles * 4);
+    s.bucket = (uint32_t *)q;    q += align256(p.n_tiles * 4 * WS_CAP);
+    s.ovf_list = (uint32_t *)q;  q += align256(p.n_tiles * 4);
+    s.ovf_count = (uint32_t *)q; q += 256;
+    return s;
+}
+
+size_t window_scan_scratch_bytes(const WsPlan &p) {
+    return align256(p.n_tiles * 8) + align256(p.n_tiles * 4) + align256(p.n_tiles * 4 * WS_CAP) +
+           align256(p.n_tiles * 4) + 256;
+}
+
+WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s, int kind) {
+    WsPlan p{};
+    p.kind = kind;
+    p.nwin = (w == 0 || s == 0 || len < w) ? 0 : (len - w) / s + 1;
+    const bool aligned16 = ((uintptr_t)in & 15) == 0;
+    if (kind == KIND_MD5 && w == 20 && (s == 1 || s == 4) && aligned16) {
+        p.variant = s == 1 ? 1 : 2;
+        p.tile_windows = (uint64_t)WS_TPB * WS_G;
+        p.lds_bytes = 0;
+    } else {
+        p.variant = 0;
+        // Largest tile whose bytes fit the LDS budget, capped at 2048 windows
+        // and rounded to whole rounds of WS_TPB windows when possible.
+        uint64_t t = ((uint64_t)WS_LDS_MAX - w - 8) / s + 1;
+        if (t > 2048) t = 2048;
+        if (t >= WS_TPB) t -= t % WS_TPB;
+        if (t == 0) t = 1;
+        p.tile_windows = t;
+        p.lds_bytes = (uint32_t)((((t - 1) * s + w + 3 + 3) / 4 + 1) * 4);
+    }
+    p.n_tiles = p.nwin ? (p.nwin + p.tile_windows - 1) / p.tile_windows : 0;
+    return p;
+}
+
+hipError_t launch_window_scan_count(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
+                                    uint64_t *total_dev, hipStream_t st) {
+    if (p.n_tiles == 0) {
+        ws_zero_u64<<<1, 1, 0, st>>>(total_dev);
+        return hipGetLastError();
+    }
+    WsScratch sc = carve(p, scratch);
+    const dim3 grid((unsigned)p.n_tiles), blk(WS_TPB);
+    if (p.variant == 1) {
+        ws_reg_count<20, 1><<<grid, blk, 0, st>>>(in, len, p.nwin, mask, target, sc.tile_count, sc.bucket);
+    } else if (p.variant == 2) {
+        ws_reg_count<20, 4><<<grid, blk, 0, st>>>(in, len, p.nwin, mask, target, sc.tile_count, sc.bucket);
+    } else {
+        GenArgs a{in, len, p.nwin, p.tile_windows, w, s, mask, target};
+        if (p.kind == KIND_MD5)
+            ws_gen_count<KIND_MD5><<<grid, blk, p.lds_bytes, st>>>(a, sc.tile_count, sc.bucket);
+        else
+            ws_gen_count<KIND_SHA1><<<grid, blk, p.lds_bytes, st>>>(a, sc.tile_count, sc.bucket);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ws_scan_tiles<<<1, SCAN_TPB, 0, st>>>(sc.tile_count, p.n_tiles, sc.tile_off, total_dev, sc.ovf_list,
+                                          sc.ovf_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+                                   uint32_t s, uint32_t mask, uint32_t target, void *scratch,
+                                   uint64_t *out, uint64_t cap, hipStream_t st) {
+    if (p.n_tiles == 0 || cap == 0 || out == nullptr) return hipSuccess;
+    WsScratch sc = carve(p, scratch);
+    ws_gather<<<dim3((unsigned)((p.n_tiles + 255) / 256)), dim3(256), 0, st>>>(
+        sc.tile_count, sc.bucket, sc.tile_off, p.n_tiles, p.tile_windows, s, out, cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned dgrid = (unsigned)(p.n_tiles < 1024 ? p.n_tiles : 1024);
+    if (p.variant == 1) {
+        ws_reg_direct<20, 1><<<dgrid, WS_TPB, 0, st>>>(in, len, p.nwin, mask, target, sc.ovf_list,
+                                                      sc.ovf_count, sc.tile_off, out, cap);
+    } else if (p.variant == 2) {
+        ws_reg_direct<20, 4><<<dgrid, WS_TPB, 0, st>>>(in, len, p.nwin, mask, target, sc.ovf_list,
+                                                      sc.ovf_count, sc.tile_off, out, cap);
+    } else {
+        GenArgs a{in, len, p.nwin, p.tile_windows, w, s, mask, target};
+        if (p.kind == KIND_MD5)
+            ws_gen_direct<KIND_MD5><<<dgrid, WS_TPB, p.lds_bytes, st>>>(a, sc.ovf_list, sc.ovf_count,
+                                                                       sc.tile_off, out, cap);
+        else
+            ws_gen_direct<KIND_SHA1><<<dgrid, WS_TPB, p.lds_bytes, st>>>(a, sc.ovf_list, sc.ovf_count,
+                                                                        sc.tile_off, out, cap);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hg

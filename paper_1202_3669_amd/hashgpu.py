@@ -1,0 +1,213 @@
+"""ctypes binding of ``libhashgpu.so``, the C ABI declared in
+``include/hashgpu.h``.
+
+The ``hg_*`` functions mirror the C entry points one to one (same names,
+same arguments, raw pointers and integers).  ``Context`` adds torch-tensor
+marshalling on top: it passes ``tensor.data_ptr()`` and the current torch
+stream and allocates result tensors; every hashing step runs in the
+library's kernels.  Importing this module raises ImportError when the library
+has not been built (``python -m paper_1202_3669_amd.build``); there is no
+other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhashgpu.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1202_3669_amd.build`")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+HG_MD5, HG_SHA1 = 0, 1
+HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
+HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC = 1, 2, 4
+HG_MAX_WINDOW = 4096
+DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_int = ctypes.c_int
+_p_u64 = ctypes.POINTER(ctypes.c_uint64)
+
+
+class hg_chunk_params(ctypes.Structure):
+    _fields_ = [("window", _u32), ("stride", _u32), ("mask", _u32), ("target", _u32),
+                ("min_chunk", _u64), ("max_chunk", _u64),
+                ("window_digest", ctypes.c_int32), ("chunk_digest", ctypes.c_int32)]
+
+
+def _declare(name, restype, argtypes):
+    fn = getattr(_lib, name)
+    fn.restype = restype
+    fn.argtypes = argtypes
+    return fn
+
+
+hg_create = _declare("hg_create", _int, [_int, ctypes.POINTER(_vp)])
+hg_destroy = _declare("hg_destroy", None, [_vp])
+hg_strerror = _declare("hg_strerror", ctypes.c_char_p, [_int])
+hg_last_error = _declare("hg_last_error", _int, [_vp, ctypes.c_char_p, ctypes.c_size_t])
+hg_digest_size = _declare("hg_digest_size", _int, [_int])
+hg_host_alloc = _declare("hg_host_alloc", _int, [_vp, ctypes.c_size_t, ctypes.POINTER(_vp)])
+hg_host_free = _declare("hg_host_free", _int, [_vp, _vp])
+hg_block_hash = _declare("hg_block_hash", _int, [_vp, _vp, _u64, _u64, _int, _vp, _vp, _u32, _vp])
+hg_window_scan = _declare("hg_window_scan", _int,
+                          [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _int, _vp, _u64, _vp, _u32, _vp])
+hg_chunk = _declare("hg_chunk", _int,
+                    [_vp, _vp, _u64, ctypes.POINTER(hg_chunk_params), _vp, _u64, _vp, _vp, _u32, _vp])
+hg_similarity = _declare("hg_similarity", _int,
+                         [_vp, _vp, _u64, _vp, _vp, _u64, _int, _vp, _vp, _u32, _vp])
+
+EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_digest_size",
+            "hg_host_alloc", "hg_host_free", "hg_block_hash", "hg_window_scan", "hg_chunk",
+            "hg_similarity"]
+
+
+class HashGpuError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{hg_strerror(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _torch():
+    import torch  # torch provides device memory and streams only
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Context:
+    """One hg_ctx on one device, used from one stream at a time."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        st = hg_create(device, ctypes.byref(h))
+        if st != HG_OK:
+            raise HashGpuError(st, f"hg_create({device}) failed")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            hg_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_trunc=False):
+        if st == HG_OK or (allow_trunc and st == HG_ETRUNC):
+            return st
+        buf = ctypes.create_string_buffer(512)
+        hg_last_error(self.handle, buf, 512)
+        raise HashGpuError(st, buf.value.decode(errors="replace"))
+
+    # ------------------------------------------------------------ direct --
+    def block_hash(self, data, block_size: int, digest: int, leaves: bool = True,
+                   root: bool = True, stream=None, flags_extra: int = 0):
+        """Segment digests (n, d) uint8 and/or root (d,) uint8 of a uint8
+        tensor.  A CUDA tensor is hashed in place; a CPU tensor is streamed
+        through the context's pinned staging (host-to-device included)."""
+        torch = _torch()
+        d = DIGEST_SIZE[digest]
+        n = (data.numel() + block_size - 1) // block_size if data.numel() else 0
+        dev = torch.device("cuda", self.device)
+        lv = torch.empty((n, d), dtype=torch.uint8, device=dev) if leaves else None
+        rt = torch.empty((d,), dtype=torch.uint8, device=dev) if root else None
+        flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0) | flags_extra
+        st = hg_block_hash(self.handle, data.data_ptr() if data.numel() else None, data.numel(),
+                           block_size, digest, lv.data_ptr() if lv is not None and n else None,
+                           rt.data_ptr() if rt is not None else None, flags,
+                           _stream_handle(stream))
+        self._check(st)
+        return lv, rt
+
+    # ----------------------------------------------------- sliding window --
+    def window_scan(self, data, window: int, stride: int, mask: int, target: int,
+                    digest: int = HG_MD5, capacity: int | None = None, stream=None):
+        """Ascending candidate start offsets (int64 CUDA tensor)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        n = data.numel()
+        nwin = (n - window) // stride + 1 if n >= window else 0
+        if capacity is None:
+            capacity = min(nwin, 4096 + nwin // 1024)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        for _ in range(2):
+            out = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+            flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+            st = hg_window_scan(self.handle, data.data_ptr() if n else None, n, window, stride,
+                                mask, target, digest, out.data_ptr(), capacity, cnt.data_ptr(),
+                                flags, _stream_handle(stream))
+            self._check(st, allow_trunc=True)
+            total = int(cnt.item())
+            if total <= capacity:
+                return out[:total]
+            capacity = total
+        raise HashGpuError(HG_ETRUNC, "candidate count changed between calls")
+
+    def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
+              window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
+              capacity: int | None = None, stream=None):
+        """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        n = data.numel()
+        p = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
+        d = DIGEST_SIZE[chunk_digest]
+        if capacity is None:
+            nwin = (n - window) // stride + 1 if n >= window else 0
+            capacity = 1 + min(nwin, 4096 + nwin // 1024)
+            if min_chunk:
+                capacity = min(capacity, n // min_chunk + 1)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        for _ in range(2):
+            ends = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+            dig = torch.empty((max(capacity, 1), d), dtype=torch.uint8, device=dev) if digests else None
+            flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+            st = hg_chunk(self.handle, data.data_ptr() if n else None, n, ctypes.byref(p),
+                          ends.data_ptr(), capacity, cnt.data_ptr(),
+                          dig.data_ptr() if dig is not None else None, flags,
+                          _stream_handle(stream))
+            self._check(st, allow_trunc=True)
+            total = int(cnt.item())
+            if total <= capacity:
+                return ends[:total], (dig[:total] if dig is not None else None)
+            capacity = total
+        raise HashGpuError(HG_ETRUNC, "chunk count changed between calls")
+
+    def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None):
+        """(matched, matched_bytes) of B's chunk digests against A's."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        d = DIGEST_SIZE[digest]
+        a = dig_a.reshape(-1, d)
+        b = dig_b.reshape(-1, d)
+        res = torch.zeros(2, dtype=torch.int64, device=dev)
+        st = hg_similarity(self.handle, a.data_ptr() if a.numel() else None, a.shape[0],
+                           b.data_ptr() if b.numel() else None,
+                           len_b.data_ptr() if len_b is not None and len_b.numel() else None,
+                           b.shape[0], digest, res.data_ptr(), res[1:].data_ptr(),
+                           HG_IN_DEVICE | HG_OUT_DEVICE, _stream_handle(stream))
+        self._check(st)
+        r = res.cpu()
+        return int(r[0]), int(r[1])

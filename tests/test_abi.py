@@ -1,0 +1,70 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+``include/hashgpu.h`` declares, and reports missing devices and bad handles
+with the documented status codes."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hashgpu.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ["hg_create", "hg_destroy", "hg_block_hash", "hg_window_scan", "hg_chunk",
+                     "hg_similarity"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1202_3669_amd import hashgpu
+    out = subprocess.run(["nm", "-D", "--defined-only", hashgpu.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(hg_\w+)", out))
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+    assert sorted(hashgpu.EXPORTED) == sorted(_declared_functions())
+
+
+def test_status_text_and_digest_sizes():
+    from paper_1202_3669_amd import hashgpu as hg
+    assert hg.hg_strerror(hg.HG_OK) == b"ok"
+    assert hg.hg_strerror(hg.HG_ETRUNC) == b"output truncated"
+    assert hg.hg_digest_size(hg.HG_MD5) == 16
+    assert hg.hg_digest_size(hg.HG_SHA1) == 20
+    assert hg.hg_digest_size(7) == hg.HG_EINVAL
+
+
+def test_null_context_is_rejected():
+    from paper_1202_3669_amd import hashgpu as hg
+    cnt = ctypes.c_uint64(0)
+    assert hg.hg_block_hash(None, None, 0, 64, hg.HG_MD5, None, None, 0, None) == hg.HG_EINVAL
+    assert hg.hg_window_scan(None, None, 0, 20, 1, 0, 0, hg.HG_MD5, None, 0,
+                             ctypes.addressof(cnt), 0, None) == hg.HG_EINVAL
+    assert hg.hg_last_error(None, None, 0) == hg.HG_EINVAL
+    hg.hg_destroy(None)  # no-op
+
+
+def test_create_without_gpu_reports_edevice():
+    # Runs in a child so that the HIP runtime of this process stays untouched.
+    code = (
+        "import ctypes, sys\n"
+        "from paper_1202_3669_amd import hashgpu as hg\n"
+        "import torch\n"
+        "if torch.cuda.device_count() > 0: sys.exit(3)\n"
+        "h = ctypes.c_void_p()\n"
+        "sys.exit(0 if hg.hg_create(0, ctypes.byref(h)) == hg.HG_EDEVICE else 1)\n"
+    )
+    r = subprocess.run(["python", "-c", code], cwd=ROOT, capture_output=True, text=True)
+    if r.returncode == 3:
+        pytest.skip("a GPU is present")
+    assert r.returncode == 0, r.stderr

@@ -1,0 +1,379 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Everything here is integer and byte work, so every comparison is bit-exact.
+Inputs are seeded synthetic bytes with the shapes of the paper's workloads:
+  * small: 4 MiB uniform bytes (seed 1), 64 KiB segments, w = 20, stride 1,
+    boundary when the low 12 bits of the window digest are 0;
+  * large: 1 GiB uniform bytes (seed 2), segments of 4 KiB / 64 KiB / 1 MiB;
+  * similarity: 256 MiB version A (seed 3), version B from seeded edits
+    (seed 4, 1-4 KiB insert/delete/overwrite, one per MiB), stride 1 and 4,
+    minimum chunk 2 KiB, SHA-1 chunk digests;
+plus edge cases: empty and tiny inputs, ragged tails, odd segment sizes,
+unaligned base pointers, dense boundary masks (the overflow path), window
+sizes that need one and several MD5 blocks, and truncated outputs.
+"""
+import ctypes
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_3669_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+THREADS = max(1, min(16, os.cpu_count() or 1))
+KINDS = [0, 1]  # MD5, SHA-1 in both numberings
+MiB = 1 << 20
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hg():
+    from paper_1202_3669_amd import hashgpu
+    return hashgpu
+
+
+@pytest.fixture(scope="module")
+def ctx(hg):
+    c = hg.Context(0)
+    yield c
+    c.close()
+
+
+def dev(arr: np.ndarray, offset: int = 0):
+    """Device copy of a uint8 array whose first byte sits `offset` bytes past
+    a 256-byte aligned allocation (offset != 0 gives an unaligned base)."""
+    t = torch.zeros(arr.size + offset + 16, dtype=torch.uint8, device="cuda")
+    if arr.size:
+        t[offset:offset + arr.size] = torch.from_numpy(arr).cuda()
+    return t[offset:offset + arr.size]
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------ direct hash --
+@pytest.mark.parametrize("kind", KINDS)
+def test_block_hash_small_workload(ctx, kind):
+    data = inputs.uniform_bytes(1, 4 * MiB)
+    note(f"block_hash small kind={kind}")
+    lv, rt = ctx.block_hash(dev(data), 64 * 1024, kind)
+    torch.cuda.synchronize()
+    exp_lv = oracle.leaves(kind, data, 64 * 1024)
+    assert lv.shape == (64, oracle.digest_size(kind))
+    assert np.array_equal(host(lv), exp_lv)
+    assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+
+
+EDGE = [(0, 64, 0), (1, 64, 0), (55, 64, 0), (56, 64, 0), (63, 64, 0), (64, 64, 0), (65, 64, 0),
+        (119, 64, 0), (120, 64, 0), (1000, 1, 0), (1000, 7, 3), (5000, 100, 1), (4097, 4096, 0),
+        (65536 * 3 + 17, 65536, 2), (100_000, 1000, 1), (12345, 1 << 20, 0),
+        ((1 << 20) + 13, 4096, 0), ((1 << 20) + 13, 4096, 5), (300_001, 64 * 3, 7)]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("length,block,offset", EDGE)
+def test_block_hash_edge_cases(ctx, kind, length, block, offset):
+    data = inputs.uniform_bytes(100 + length % 97, length)
+    note(f"block_hash edge kind={kind} len={length} B={block} off={offset}")
+    lv, rt = ctx.block_hash(dev(data, offset), block, kind)
+    torch.cuda.synchronize()
+    exp_lv = oracle.leaves(kind, data, block)
+    assert np.array_equal(host(lv), exp_lv)
+    assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_block_hash_root_only_and_leaves_only(ctx, kind):
+    data = inputs.uniform_bytes(7, 300_000)
+    note(f"block_hash root-only kind={kind}")
+    d = dev(data)
+    lv, rt = ctx.block_hash(d, 4096, kind, leaves=False)
+    assert lv is None
+    exp_lv = oracle.leaves(kind, data, 4096)
+    assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+    lv, rt = ctx.block_hash(d, 4096, kind, root=False)
+    assert rt is None and np.array_equal(host(lv), exp_lv)
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+def test_block_hash_streams_host_input(ctx, pinned):
+    # Larger than two 64 MiB staging pieces, with a ragged tail.
+    data = inputs.uniform_bytes(8, 150 * MiB + 1234)
+    note(f"block_hash host input pinned={pinned}")
+    t = torch.from_numpy(data)
+    if pinned:
+        t = t.pin_memory()
+    lv, rt = ctx.block_hash(t, 64 * 1024, 0)
+    torch.cuda.synchronize()
+    exp_lv = oracle.leaves_sharded(0, data, 64 * 1024, THREADS)
+    assert np.array_equal(host(lv), exp_lv)
+    assert bytes(host(rt)) == oracle.root(0, exp_lv)
+
+
+# ----------------------------------------------------------- window scan --
+def test_window_scan_small_workload(ctx):
+    data = inputs.uniform_bytes(1, 4 * MiB)
+    note("window_scan small w=20 s=1 mask=0xfff")
+    got = host(ctx.window_scan(dev(data), 20, 1, 0xFFF, 0))
+    exp = oracle.window_scan_sharded(0, data, 20, 1, 0xFFF, 0, THREADS)
+    assert got.dtype == np.int64
+    assert np.array_equal(got.astype(np.uint64), exp)
+
+
+WS_CASES = []
+for _w in [1, 20, 55, 56, 64, 100]:
+    for _s in [1, 2, 3, 4, 7]:
+        WS_CASES.append((_w, _s, 0xF, 3))
+WS_CASES += [(20, 1, 0xFF, 0), (20, 4, 0xFF, 0x11), (20, 1, 0, 0), (20, 4, 0, 0), (33, 5, 1, 1),
+             (4096, 1, 0x3, 0), (4096, 4096, 0, 0), (200, 1000, 0, 0)]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("w,s,mask,target", WS_CASES)
+def test_window_scan_cases(ctx, kind, w, s, mask, target):
+    length = 20_000 + 7 * w + s
+    data = inputs.uniform_bytes(200 + w + s, length)
+    for off in (0, 3):
+        note(f"window_scan kind={kind} w={w} s={s} mask={mask:#x} off={off}")
+        got = host(ctx.window_scan(dev(data, off), w, s, mask, target, kind))
+        exp = oracle.window_scan(kind, data, w, s, mask, target)
+        assert np.array_equal(got.astype(np.uint64), exp)
+
+
+@pytest.mark.parametrize("length", [0, 1, 19, 20, 21, 4095, 4096 * 16 + 3, 65537])
+def test_window_scan_short_and_ragged(ctx, length):
+    data = inputs.uniform_bytes(300, length)
+    for s in (1, 4):
+        note(f"window_scan ragged len={length} s={s}")
+        got = host(ctx.window_scan(dev(data), 20, s, 0x7, 0))
+        exp = oracle.window_scan(0, data, 20, s, 0x7, 0)
+        assert np.array_equal(got.astype(np.uint64), exp)
+
+
+@pytest.mark.parametrize("s", [1, 4])
+def test_window_scan_dense_mask_uses_overflow_path(ctx, s):
+    # mask 0: every window is a candidate, far beyond the per-tile bucket.
+    data = inputs.uniform_bytes(301, 300_000)
+    note(f"window_scan dense s={s}")
+    got = host(ctx.window_scan(dev(data), 20, s, 0, 0))
+    n = oracle.window_count(data.size, 20, s)
+    assert np.array_equal(got, np.arange(n, dtype=np.int64) * s)
+    # Mixed density: some tiles overflow, others use their bucket.
+    got = host(ctx.window_scan(dev(data), 20, s, 0x3, 2))
+    exp = oracle.window_scan(0, data, 20, s, 0x3, 2)
+    assert np.array_equal(got.astype(np.uint64), exp)
+
+
+def test_window_scan_truncation_reports_full_count(ctx, hg):
+    data = inputs.uniform_bytes(302, 200_000)
+    exp = oracle.window_scan(0, data, 20, 1, 0xFF, 0)
+    assert exp.size > 10
+    note("window_scan truncation")
+    d = dev(data)
+    out = torch.zeros(10, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = hg.hg_window_scan(ctx.handle, d.data_ptr(), d.numel(), 20, 1, 0xFF, 0, hg.HG_MD5,
+                           out.data_ptr(), 10, cnt.data_ptr(), hg.HG_IN_DEVICE | hg.HG_OUT_DEVICE,
+                           torch.cuda.current_stream().cuda_stream)
+    assert st == hg.HG_ETRUNC
+    assert int(cnt.item()) == exp.size
+    assert np.array_equal(host(out).astype(np.uint64), exp[:10])
+    # Host outputs: the same status, count and prefix.
+    out_h = (ctypes.c_uint64 * 10)()
+    cnt_h = ctypes.c_uint64(0)
+    st = hg.hg_window_scan(ctx.handle, d.data_ptr(), d.numel(), 20, 1, 0xFF, 0, hg.HG_MD5,
+                           ctypes.addressof(out_h), 10, ctypes.addressof(cnt_h), hg.HG_IN_DEVICE,
+                           torch.cuda.current_stream().cuda_stream)
+    assert st == hg.HG_ETRUNC and cnt_h.value == exp.size
+    assert list(out_h) == exp[:10].tolist()
+
+
+# ---------------------------------------------------------------- chunks --
+def _oracle_chunks(data, w, s, mask, target, min_chunk, wk=0, ck=1):
+    starts = oracle.window_scan_sharded(wk, data, w, s, mask, target, THREADS)
+    ends = oracle.chunk_select(starts, w, data.size, min_chunk)
+    return ends, oracle.chunk_digests(ck, data, ends)
+
+
+def test_chunk_small_workload(ctx):
+    data = inputs.uniform_bytes(1, 4 * MiB)
+    note("chunk small")
+    ends, dig = ctx.chunk(dev(data), 20, 1, 0xFFF, 0, 2048)
+    exp_ends, exp_dig = _oracle_chunks(data, 20, 1, 0xFFF, 0, 2048)
+    assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+    assert np.array_equal(host(dig), exp_dig)
+
+
+CHUNK_CASES = [(0, 20, 1, 0xFF, 0, 2048, 0, 1), (10, 20, 1, 0xFF, 0, 2048, 0, 1),
+               (5000, 20, 1, 0x3F, 0, 0, 0, 1), (5000, 20, 1, 0, 0, 0, 0, 1),
+               (70_000, 20, 4, 0x3F, 1, 300, 0, 0), (70_000, 48, 3, 0x1F, 2, 500, 1, 1),
+               (200_003, 20, 1, 0xFF, 0, 2048, 0, 1), (200_003, 64, 1, 0x7F, 5, 1000, 0, 1),
+               (100_000, 20, 1, 0xFF, 0, 10 ** 9, 0, 1)]
+
+
+@pytest.mark.parametrize("case", CHUNK_CASES)
+def test_chunk_cases(ctx, case):
+    length, w, s, mask, target, mn, wk, ck = case
+    data = inputs.uniform_bytes(400 + length % 101, length)
+    for off in (0, 1):
+        note(f"chunk case={case} off={off}")
+        ends, dig = ctx.chunk(dev(data, off), w, s, mask, target, mn, wk, ck)
+        exp_ends, exp_dig = _oracle_chunks(data, w, s, mask, target, mn, wk, ck)
+        assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+        assert np.array_equal(host(dig), exp_dig)
+
+
+def test_chunk_truncation(ctx, hg):
+    data = inputs.uniform_bytes(402, 300_000)
+    exp_ends, exp_dig = _oracle_chunks(data, 20, 1, 0xFF, 0, 1024)
+    assert exp_ends.size > 5
+    note("chunk truncation")
+    ends, dig = ctx.chunk(dev(data), 20, 1, 0xFF, 0, 1024, capacity=5)  # retried with the full size
+    assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+    d = dev(data)
+    p = hg.hg_chunk_params(20, 1, 0xFF, 0, 1024, 0, 0, 1)
+    e = torch.zeros(5, dtype=torch.int64, device="cuda")
+    dg = torch.zeros((5, 20), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = hg.hg_chunk(ctx.handle, d.data_ptr(), d.numel(), ctypes.byref(p), e.data_ptr(), 5,
+                     cnt.data_ptr(), dg.data_ptr(), hg.HG_IN_DEVICE | hg.HG_OUT_DEVICE,
+                     torch.cuda.current_stream().cuda_stream)
+    assert st == hg.HG_ETRUNC and int(cnt.item()) == exp_ends.size
+    assert np.array_equal(host(e).astype(np.uint64), exp_ends[:5])
+    assert np.array_equal(host(dg), exp_dig[:5])
+
+
+# ------------------------------------------------------------ similarity --
+@pytest.mark.parametrize("kind", KINDS)
+def test_similarity_constructed(ctx, kind):
+    d = oracle.digest_size(kind)
+    rng = np.random.default_rng(500 + kind)
+    a = rng.integers(0, 256, size=(3000, d), dtype=np.uint8)
+    b = np.concatenate([a[rng.permutation(3000)[:1500]], a[:100],
+                        rng.integers(0, 256, size=(700, d), dtype=np.uint8)])
+    lens = rng.integers(1, 100_000, size=b.shape[0]).astype(np.int64)
+    note(f"similarity constructed kind={kind}")
+    m, mb = ctx.similarity(dev(a.reshape(-1)), dev(b.reshape(-1)),
+                           torch.from_numpy(lens).cuda(), kind)
+    em, emb = oracle.similarity(kind, a, b, lens.astype(np.uint64))
+    assert (m, mb) == (em, emb)
+    assert ctx.similarity(dev(a.reshape(-1)), dev(a.reshape(-1)), None, kind)[0] == 3000
+    assert ctx.similarity(dev(a[:0].reshape(-1)), dev(b.reshape(-1)), None, kind)[0] == 0
+
+
+def _versions(size, n_edits):
+    a = inputs.uniform_bytes(3, size)
+    b, _ = inputs.edited_version(a, 4, n_edits)
+    return a, b
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_similarity_of_versions_small(ctx, stride):
+    a, b = _versions(16 * MiB, 16)
+    note(f"similarity versions 16MiB s={stride}")
+    ea, da = ctx.chunk(dev(a), 20, stride, 0xFFF, 0, 2048)
+    eb, db = ctx.chunk(dev(b), 20, stride, 0xFFF, 0, 2048)
+    lb = torch.diff(eb, prepend=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    m, mb = ctx.similarity(da, db, lb, 1)
+    xa, xda = _oracle_chunks(a, 20, stride, 0xFFF, 0, 2048)
+    xb, xdb = _oracle_chunks(b, 20, stride, 0xFFF, 0, 2048)
+    assert np.array_equal(host(ea).astype(np.uint64), xa)
+    assert np.array_equal(host(eb).astype(np.uint64), xb)
+    assert np.array_equal(host(db), xdb)
+    xlb = np.diff(xb, prepend=np.uint64(0))
+    assert (m, mb) == oracle.similarity(1, xda, xdb, xlb)
+
+
+# ------------------------------------------------------ full-size checks --
+@pytest.mark.parametrize("block", [4096, 64 * 1024, 1 << 20])
+def test_block_hash_large_workload(ctx, block):
+    data = _large()
+    d = _large_dev()
+    for kind in KINDS:
+        note(f"block_hash 1GiB kind={kind} B={block}")
+        lv, rt = ctx.block_hash(d, block, kind)
+        torch.cuda.synchronize()
+        exp_lv = oracle.leaves_sharded(kind, data, block, THREADS)
+        assert np.array_equal(host(lv), exp_lv)
+        assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+
+
+_LARGE = {}
+
+
+def _large():
+    if "h" not in _LARGE:
+        _LARGE["h"] = inputs.uniform_bytes(2, 1 << 30)
+    return _LARGE["h"]
+
+
+def _large_dev():
+    if "d" not in _LARGE:
+        _LARGE["d"] = torch.from_numpy(_large()).cuda()
+    return _LARGE["d"]
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_similarity_workload_full_size(ctx, stride):
+    _LARGE.clear()
+    a, b = _versions(256 * MiB, 256)
+    note(f"similarity 256MiB s={stride}")
+    ea, da = ctx.chunk(dev(a), 20, stride, 0xFFF, 0, 2048)
+    eb, db = ctx.chunk(dev(b), 20, stride, 0xFFF, 0, 2048)
+    lb = torch.diff(eb, prepend=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    m, mb = ctx.similarity(da, db, lb, 1)
+    xa, xda = _oracle_chunks(a, 20, stride, 0xFFF, 0, 2048)
+    xb, xdb = _oracle_chunks(b, 20, stride, 0xFFF, 0, 2048)
+    assert np.array_equal(host(ea).astype(np.uint64), xa)
+    assert np.array_equal(host(da), xda)
+    assert np.array_equal(host(eb).astype(np.uint64), xb)
+    assert np.array_equal(host(db), xdb)
+    xlb = np.diff(xb, prepend=np.uint64(0))
+    assert (m, mb) == oracle.similarity(1, xda, xdb, xlb)
+    note(f"similarity s={stride}: {m}/{xb.size} chunks, {mb}/{b.size} bytes")
+
+
+# ------------------------------------------------------- misc behaviour --
+def test_results_are_deterministic(ctx):
+    data = inputs.uniform_bytes(600, 3 * MiB + 5)
+    d = dev(data, 1)
+    note("determinism")
+    r1 = [host(x) for x in ctx.chunk(d, 20, 1, 0x3FF, 0, 1024)]
+    r2 = [host(x) for x in ctx.chunk(d, 20, 1, 0x3FF, 0, 1024)]
+    assert all(np.array_equal(x, y) for x, y in zip(r1, r2))
+
+
+def test_invalid_arguments(ctx, hg):
+    d = dev(inputs.uniform_bytes(601, 1000))
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    fl = hg.HG_IN_DEVICE | hg.HG_OUT_DEVICE
+    note("invalid arguments")
+    assert hg.hg_block_hash(ctx.handle, d.data_ptr(), 1000, 0, 0, cnt.data_ptr(), None, fl, s) == hg.HG_EINVAL
+    assert hg.hg_block_hash(ctx.handle, d.data_ptr(), 1000, 64, 9, cnt.data_ptr(), None, fl, s) == hg.HG_EINVAL
+    assert hg.hg_block_hash(ctx.handle, d.data_ptr(), 1000, 64, 0, None, None, fl, s) == hg.HG_EINVAL
+    for w, st_ in [(0, 1), (hg.HG_MAX_WINDOW + 1, 1), (20, 0)]:
+        assert hg.hg_window_scan(ctx.handle, d.data_ptr(), 1000, w, st_, 0, 0, 0, None, 0,
+                                 cnt.data_ptr(), fl, s) == hg.HG_EINVAL
+    assert hg.hg_window_scan(ctx.handle, d.data_ptr(), 1000, 20, 1, 0, 0, 0, None, 0, None, fl,
+                             s) == hg.HG_EINVAL
+    assert hg.hg_window_scan(ctx.handle, d.data_ptr(), 1000, 20, 1, 0, 0, 0, None, 0,
+                             cnt.data_ptr(), hg.HG_ASYNC, s) == hg.HG_EINVAL
+    p = hg.hg_chunk_params(20, 1, 0, 0, 0, 4096, 0, 1)  # max_chunk unsupported
+    assert hg.hg_chunk(ctx.handle, d.data_ptr(), 1000, ctypes.byref(p), None, 0, cnt.data_ptr(),
+                       None, fl, s) == hg.HG_EINVAL
+    buf = ctypes.create_string_buffer(256)
+    assert hg.hg_last_error(ctx.handle, buf, 256) == hg.HG_EINVAL
+    assert b"max_chunk" in buf.value
+    h = ctypes.c_void_p()
+    assert hg.hg_create(99, ctypes.byref(h)) == hg.HG_EDEVICE
