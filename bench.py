@@ -1,0 +1,345 @@
+#!/usr/bin/env python3
+"""Benchmark of the HashGPU hashing path on one MI355X (gfx950).
+
+Workload (one step = one pass of the whole path over one input):
+  a new 1 GiB version of a file (uniform random bytes, seed 2) is hashed the
+  way a content-addressable store hashes a written file (paper Sec. 3.2.1,
+  Sec. 3.2.4):
+    * fixed-size blocks: direct hash with MD5 and with SHA-1 at segment sizes
+      4 KiB, 64 KiB and 1 MiB, each with its second level (6 jobs);
+    * content-based chunking: MD5 sliding windows (w = 20, stride 1, boundary
+      when the low 12 bits of the window digest are 0), minimum chunk 2 KiB,
+      SHA-1 chunk digests;
+    * similarity of the new chunk digests against the previous version's
+      block-map (the previous version differs by 1024 seeded 1-4 KiB edits),
+      counted by chunks and by bytes.
+  Input bytes are resident in HBM when the timed region starts.
+
+Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1): the
+second-level hash of a job is one sequential chain (for 4 KiB SHA-1 segments
+of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
+sequential chains per job.  Short work of each step runs on stream S0; for a
+group of G steps, the 1 MiB segments run as one batched launch on stream S1
+and all second levels as one batched launch on stream S2, while S0 carries
+on with the next group.  A step's latency therefore ends when its group's
+roots are done.  Three streams need three hardware queues: HIP shares its
+default four queues among all streams of the process, so the benchmark asks
+for eight (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
+
+value = hashed bytes per second: each of the 7 primitive passes (6 direct
+hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
+METRIC = "hashing GB/s (block MD5/SHA-1, sliding-window) + % int roofline; p50/p99 latency"
+
+# int32 VALU peak of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic int32 ops of one w = 20 window up to its first digest word: 61
+# MD5 steps, 19 with a data word (5 ops) and 42 with a constant word (4 ops).
+WINDOW_OPS = 19 * 5 + 42 * 4
+
+# (digest, segment size); within a launch, jobs with the longest sequential
+# chains come first.
+BLOCK_JOBS = [(1, 64 * KiB), (0, 64 * KiB), (1, 4 * KiB), (0, 4 * KiB), (1, MiB), (0, MiB)]
+SHORT = [0, 1, 2, 3]   # indices of BLOCK_JOBS whose segments go in the per-step launch
+LONG = [4, 5]          # 1 MiB segments: batched per group
+ROOT_EARLY = [2, 3, 0, 1]  # second levels that need no 1 MiB segments, longest chain first
+ROOT_LATE = [4, 5]         # second levels of the 1 MiB jobs
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=96)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--group", type=int, default=12, help="steps per long-chain batch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--cpu-sample-mib", type=int, default=32)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run one 1 GiB device copy (counter calibration) and one window scan "
+                         "of the workload, then exit (for rocprofv3 --pmc)")
+    return ap.parse_args()
+
+
+class Pipeline:
+    """Buffers, job tables and streams of the pipelined step."""
+
+    def __init__(self, torch, hg, data, prev_digests, group):
+        self.torch, self.hg = torch, hg
+        self.data = data
+        self.prev = prev_digests
+        self.G = group
+        self.slots = 2 * group
+        self.s0 = torch.cuda.Stream()
+        self.s1 = torch.cuda.Stream()
+        self.s2 = torch.cuda.Stream()
+        self.ctx0 = hg.Context(0)
+        self.ctx1 = hg.Context(0)
+        self.ctx2 = hg.Context(0)
+        self.ctx3 = hg.Context(0)
+        dev = data.device
+        n = data.numel()
+        # Chunk outputs (capacity: every chunk but the last is >= 2 KiB).
+        self.cap = n // (2 * KiB) + 1
+        self.ends = torch.empty(self.cap, dtype=torch.int64, device=dev)
+        self.digs = torch.empty((self.cap, 20), dtype=torch.uint8, device=dev)
+        self.nchunks = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.sim = torch.zeros((self.slots, 2), dtype=torch.int64, device=dev)
+        # Ring of segment-digest buffers and root outputs, one per slot.
+        self.recs = []
+        for slot in range(self.slots):
+            specs = [(data, b, k) for k, b in BLOCK_JOBS]
+            recs, leaves, roots = self.ctx0.batch_outputs(specs)
+            self.recs.append((recs, leaves, roots))
+        Job = hg.hg_block_job
+        self.short_tables = [self.ctx0.device_job_table(self._subset(slot, SHORT))
+                             for slot in range(self.slots)]
+        self.long_tables, self.early_tables, self.late_tables = [], [], []
+
+        def table(ctx, recs):
+            return ctx.device_job_table((Job * len(recs))(*recs)), len(recs)
+        for parity in range(2):
+            slots = range(parity * group, parity * group + group)
+            self.long_tables.append(table(self.ctx1, [self.recs[s][0][j] for s in slots for j in LONG]))
+            self.early_tables.append(table(self.ctx2, [self.recs[s][0][j] for j in ROOT_EARLY for s in slots]))
+            self.late_tables.append(table(self.ctx3, [self.recs[s][0][j] for j in ROOT_LATE for s in slots]))
+        self.group_done = {}
+        self.issue_ev = {}
+
+    def _subset(self, slot, idx):
+        recs = self.recs[slot][0]
+        return (self.hg.hg_block_job * len(idx))(*[recs[i] for i in idx])
+
+    def step(self, i):
+        torch = self.torch
+        slot = i % self.slots
+        g = i // self.G
+        if i % self.G == 0 and (g - 2) in self.group_done:
+            # Slots of group g were last read by group g-2's roots.
+            self.s0.wait_event(self.group_done[g - 2])
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.s0)
+        self.issue_ev[i] = ev
+        with torch.cuda.stream(self.s0):
+            self.ctx0.run_batch(self.short_tables[slot], len(SHORT), "leaves", stream=self.s0)
+            ends, digs = self.ctx0.chunk(self.data, 20, 1, 0xFFF, 0, 2 * KiB, capacity=self.cap,
+                                         stream=self.s0, out=(self.ends, self.digs, self.nchunks))
+            self.ctx0.similarity(self.prev, digs, stream=self.s0, ends_b=ends,
+                                 out=self.sim[slot], asynchronous=True)
+        if i % self.G == self.G - 1:
+            self.close_group(g)
+
+    def close_group(self, g):
+        """Queue the long chains of group g: the 1 MiB segments on S1, then
+        (after them) their second levels; the other second levels on S2 as
+        soon as the group's short work is done."""
+        torch = self.torch
+        parity = g % 2
+        short_done = torch.cuda.Event()
+        short_done.record(self.s0)
+        self.s1.wait_event(short_done)
+        self.s2.wait_event(short_done)
+        lt, ln = self.long_tables[parity]
+        et, en = self.early_tables[parity]
+        zt, zn = self.late_tables[parity]
+        self.ctx2.run_batch(et, en, "roots", stream=self.s2)
+        self.ctx1.run_batch(lt, ln, "leaves", stream=self.s1)
+        self.ctx3.run_batch(zt, zn, "roots", stream=self.s1)
+        s1_done = torch.cuda.Event()
+        s1_done.record(self.s1)
+        self.s2.wait_event(s1_done)
+        done = torch.cuda.Event(enable_timing=True)
+        done.record(self.s2)
+        self.group_done[g] = done
+
+    def run(self, first, count):
+        for i in range(first, first + count):
+            self.step(i)
+        last = first + count - 1
+        if last % self.G != self.G - 1:
+            self.close_group(last // self.G)
+
+    def latencies_ms(self, first, count):
+        out = []
+        for i in range(first, first + count):
+            done = self.group_done[i // self.G]
+            out.append(self.issue_ev[i].elapsed_time(done))
+        return out
+
+
+def pct(xs, p):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))]
+
+
+def cpu_baseline(data_np, prev_np, mib):
+    """The oracle on the host cores, over the first `mib` MiB of the step's
+    input (the same seven passes plus the similarity lookup)."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    n = mib * MiB
+    sample, prev = data_np[:n], prev_np[:n]
+    # The previous version's block-map is an input of the step: built untimed.
+    _, _, prev_dig = oracle.chunk(oracle.MD5, oracle.SHA1, prev, 20, 1, 0xFFF, 0, 2 * KiB, threads)
+    t0 = time.perf_counter()
+    for k, b in BLOCK_JOBS:
+        lv = oracle.leaves_sharded(k, sample, b, threads)
+        oracle.root(k, lv)
+    _, ends, dig = oracle.chunk(oracle.MD5, oracle.SHA1, sample, 20, 1, 0xFFF, 0, 2 * KiB, threads)
+    import numpy as np
+    lens = np.diff(ends, prepend=np.uint64(0))
+    oracle.similarity(oracle.SHA1, prev_dig, dig, lens)
+    dt = time.perf_counter() - t0
+    return {"value": round(7 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {mib} MiB of the step input (7 passes + similarity), {dt:.2f} s wall"}
+
+
+def breakdown(torch, hg, data, host_pinned):
+    """Each primitive alone, device-resident unless noted (median of 5)."""
+    ctx = hg.Context(0)
+    s = torch.cuda.current_stream()
+    res = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            fn()
+            b.record(s)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return ts
+
+    n = data.numel()
+    for k, b in BLOCK_JOBS:
+        name = f"{'sha1' if k else 'md5'}_{b // KiB}k"
+        t_leaf = statistics.median(timed(lambda: ctx.block_hash(data, b, k, root=False)))
+        t_all = timed(lambda: ctx.block_hash(data, b, k))
+        res[name] = {"leaves_GBps": round(n / t_leaf / 1e6, 1), "leaves_ms": round(t_leaf, 3),
+                     "with_root_ms_p50": round(pct(t_all, 50), 3),
+                     "with_root_ms_p99": round(pct(t_all, 99), 3)}
+    for st in (1, 4):
+        t = statistics.median(timed(lambda: ctx.window_scan(data, 20, st, 0xFFF, 0), reps=3))
+        res[f"window_md5_w20_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1),
+                                        "Gwindows_per_s": round(((n - 20) // st + 1) / t / 1e6, 1)}
+        t = statistics.median(timed(lambda: ctx.chunk(data, 20, st, 0xFFF, 0, 2 * KiB), reps=3))
+        res[f"chunk_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1)}
+    # Host-to-device included: pinned host input streamed through the library.
+    for k in (0, 1):
+        ts = timed(lambda: ctx.block_hash(host_pinned, 64 * KiB, k, root=False), reps=5)
+        res[f"{'sha1' if k else 'md5'}_64k_with_h2d"] = {
+            "GBps": round(n / statistics.median(ts) / 1e6, 1),
+            "ms_p50": round(pct(ts, 50), 2), "ms_p99": round(pct(ts, 99), 2)}
+    ctx.close()
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    # Three concurrently busy streams: give HIP enough hardware queues before
+    # its runtime starts (it shares four among all streams by default).
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
+    import numpy as np
+    import torch
+    root = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, root)
+    from paper_1202_3669_amd import hashgpu as hg, inputs
+
+    print("[bench] generating the 1 GiB workload", file=sys.stderr, flush=True)
+    data_np = inputs.uniform_bytes(2, GiB)
+    if args.pmc_probe:
+        data = torch.from_numpy(data_np).cuda()
+        copy = torch.empty_like(data)
+        copy.copy_(data)  # plain copy: reads and writes exactly 1 GiB
+        with hg.Context(0) as c:
+            c.window_scan(data, 20, 1, 0xFFF, 0)
+        torch.cuda.synchronize()
+        print("[bench] pmc probe done", file=sys.stderr, flush=True)
+        return
+    prev_np, _ = inputs.edited_version(data_np, 3, 1024)
+    data = torch.from_numpy(data_np).cuda()
+    prev = torch.from_numpy(prev_np).cuda()
+    # Previous version's block-map (chunk digests): an input of every step.
+    with hg.Context(0) as c:
+        _, prev_dig = c.chunk(prev, 20, 1, 0xFFF, 0, 2 * KiB)
+        prev_dig = prev_dig.clone()
+    del prev
+    torch.cuda.synchronize()
+
+    pipe = Pipeline(torch, hg, data, prev_dig, args.group)
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    pipe.run(0, args.warmup)
+    torch.cuda.synchronize()
+    pipe.ctx0.timing(True)
+    pipe.ctx0.timing_reset()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = ((args.warmup + args.group - 1) // args.group) * args.group
+    pipe.run(first, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    lat = pipe.latencies_ms(first, args.steps)
+    nwt, mswt = pipe.ctx0.timing_read("window_tiles")
+    pipe.ctx0.timing(False)
+    sims = pipe.sim.cpu().tolist()
+    nchunks = int(pipe.nchunks.item())
+
+    hashed = 7 * GiB * args.steps
+    value = hashed / wall / 1e9
+    nwin = GiB - 20 + 1
+    avg_ms = mswt / max(nwt, 1)
+    achieved = nwin * WINDOW_OPS / (avg_ms / 1e3) / 1e12
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "1 GiB new file version (seed 2), resident in HBM: direct hash MD5+SHA-1 "
+                        "at 4 KiB/64 KiB/1 MiB segments with second level, content-based chunking "
+                        "(MD5 w=20 s=1 low-12-bit boundary, min 2 KiB, SHA-1 chunk digests), "
+                        "similarity vs previous version (1024 seeded 1-4 KiB edits)",
+            "input_bytes": GiB, "hashed_bytes_per_step": 7 * GiB, "group": args.group,
+            "chunks_per_step": nchunks,
+            "similarity_chunks": [int(sims[-1][0]), nchunks],
+        },
+        "input_GBps": round(GiB * args.steps / wall / 1e9, 2),
+        "latency_ms": {"step_p50": round(pct(lat, 50), 2), "step_p99": round(pct(lat, 99), 2)},
+        "roofline": {"kernel": "window hash + tile count (MD5 w=20 s=1)", "bound": "alu",
+                     "achieved": round(achieved, 2), "peak": round(INT32_PEAK_TOPS, 2),
+                     "unit": "Tops/s (int32)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
+                     "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": nwt,
+                     "ops_per_window": WINDOW_OPS},
+    }
+    if not args.no_breakdown:
+        print("[bench] per-primitive breakdown", file=sys.stderr, flush=True)
+        host_pinned = torch.from_numpy(data_np).pin_memory()
+        line["breakdown"] = breakdown(torch, hg, data, host_pinned)
+        del host_pinned
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(data_np, prev_np, args.cpu_sample_mib)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,8 +65,8 @@ enum {
     HG_EBUSY = -5    /* resource temporarily unavailable */
 };
 
-/* Flags. */
-enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u };
+/* Flags.  HG_LEN_ENDS applies to hg_similarity only. */
+enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u, HG_LEN_ENDS = 8u };
 
 /* Limits of the sliding-window primitive. */
 enum { HG_MAX_WINDOW = 4096 };
@@ -118,6 +118,44 @@ int hg_host_free(hg_ctx *ctx, void *p);
 int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, int digest,
                   void *leaf_out, void *root_out, uint32_t flags, void *stream);
 
+/* ------------------------------------------------- batched direct hash -- */
+
+/* One direct-hash job of a batch.  All pointers are device pointers. */
+typedef struct {
+    const void *in;       /* the job's bytes (may be NULL when len = 0) */
+    uint64_t len;         /* bytes */
+    uint64_t block_size;  /* segment size B >= 1 */
+    void *leaf_out;       /* ceil(len / B) * digest_size bytes, segment order */
+    void *root_out;       /* digest_size bytes, or NULL for no second level */
+    int32_t digest;       /* HG_MD5 or HG_SHA1 */
+    int32_t reserved;     /* must be 0 */
+} hg_block_job;
+
+/* Segment digests of every job of a batch in one persistent launch
+ * (batch-oriented computation, Sec. 3.1; Sec. 3.2.4).  Segments are handed
+ * to lanes in job order, so jobs with the longest sequential work should be
+ * listed first.  `jobs` (n_jobs records) is in device memory with
+ * HG_IN_DEVICE (then it is used as is and not validated: a record with
+ * block_size 0 is treated as empty) and in host memory otherwise (then every
+ * record is validated and the table copied).  Outputs always go to the
+ * device pointers inside the records; HG_OUT_DEVICE is implied.  HG_ASYNC
+ * requires HG_IN_DEVICE.  The same results as one hg_block_hash call per
+ * job. */
+int hg_leaves_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
+                    void *stream);
+
+/* Second level of every job whose root_out is not NULL: root_out receives
+ * the digest of the job's leaf_out buffer (ceil(len/B) digests), as
+ * hg_block_hash does.  Reads leaf_out, so it must be ordered after the
+ * hg_leaves_batch call that wrote it.  One lane per job.  Arguments as for
+ * hg_leaves_batch. */
+int hg_roots_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
+                   void *stream);
+
+/* hg_leaves_batch followed by hg_roots_batch on the same stream. */
+int hg_block_hash_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
+                        void *stream);
+
 /* ---------------------------------------------- content-based chunking -- */
 
 /* Sliding-window hashing (Sec. 2.1, "Content-based chunking"; Sec. 3.2.2).
@@ -165,13 +203,41 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
 
 /* Similarity of two versions' chunk digests (the block-map comparison of
  * Sec. 3.2.1): *matched = number of B's chunks, counted with multiplicity,
- * whose digest occurs among A's n_a digests; *matched_bytes = sum of len_b
- * over those chunks (0 when len_b is NULL).  dig_a, dig_b, len_b are inputs
- * (HG_IN_DEVICE); matched, matched_bytes are outputs (HG_OUT_DEVICE).
- * matched_bytes may be NULL. */
+ * whose digest occurs among A's n_a digests; *matched_bytes = sum of the
+ * lengths of those chunks (0 when len_b is NULL).  len_b holds n_b chunk
+ * lengths, or with HG_LEN_ENDS the n_b ascending chunk end offsets that
+ * hg_chunk returns (chunk j is then ends[j] - ends[j-1] long, ends[-1] = 0).
+ * dig_a, dig_b, len_b are inputs (HG_IN_DEVICE); matched, matched_bytes are
+ * outputs (HG_OUT_DEVICE).  matched_bytes may be NULL. */
 int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b,
                   const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
                   uint64_t *matched_bytes, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------ kernel timing -- */
+
+/* Kernel classes for the timing counters. */
+enum {
+    HG_K_LEAVES = 0,         /* segment digests of hg_block_hash */
+    HG_K_ROOT = 1,           /* second level of hg_block_hash */
+    HG_K_WINDOW_TILES = 2,   /* window hashing + per-tile counts (hg_window_scan, hg_chunk) */
+    HG_K_WINDOW_EMIT = 3,    /* tile prefix + ordered candidate output */
+    HG_K_CHUNK_SELECT = 4,   /* boundary decision */
+    HG_K_CHUNK_DIGESTS = 5,  /* chunk digests */
+    HG_K_SIMILARITY = 6,     /* digest set build + probe */
+    HG_K_LEAVES_BATCH = 7,   /* hg_leaves_batch */
+    HG_K_ROOTS_BATCH = 8,    /* hg_roots_batch */
+    HG_K_COUNT = 9
+};
+
+/* Measurement support.  While enabled, the context records a pair of HIP
+ * events on the call's stream around every launch of each kernel class
+ * above.  hg_timing_read waits for the recorded events and returns, for one
+ * class, the number of launches and the summed GPU duration (ms) since the
+ * last reset.  Disabled by default; recording adds two event records per
+ * launch. */
+int hg_timing_enable(hg_ctx *ctx, int enable);
+int hg_timing_read(hg_ctx *ctx, int kernel_class, uint64_t *launches, double *total_ms);
+int hg_timing_reset(hg_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -3,170 +3,409 @@
 // and Sec. 3.2.4: each detected block is then direct-hashed).
 //
 // Boundary decision: greedy over ascending candidates with a minimum chunk
-// size (the system's min/max chunk sizes are given in Sec. 4.3).  It is a
-// sequential scan; one wavefront runs it, 64 candidates at a time: a ballot
-// finds the first candidate end at or beyond last + max(min, 1), a readlane
-// moves `last` there, and the chosen lanes are compacted with a popcount.
+// size (the system's min/max chunk sizes are given in Sec. 4.3).  The rule
+// is sequential; below it is evaluated with speculative per-block chains and
+// a short fix-up walk (see cs_spec / cs_fix).
 //
-// Chunk digests: segments have uneven lengths, so a fixed lane-per-segment
-// mapping leaves most lanes idle behind the longest segment of each wave.
-// Here every lane loops over 64-byte message blocks; a lane that finishes a
-// segment stores its digest and takes the next segment index from a global
-// counter (one atomic per wave per refill), so all lanes stay busy until the
-// segment list runs out.
+// Chunk digests: one lane per chunk, chunks handed out longest-first (see
+// segment_digest_kernel).
 #include "hg_device.hpp"
 #include "hg_internal.hpp"
 
+#include <algorithm>
+
 namespace hg {
 
-__global__ __launch_bounds__(64) void chunk_select_kernel(const uint64_t *__restrict__ starts,
-                                                          const uint64_t *__restrict__ n_starts_dev,
-                                                          uint32_t w, uint64_t len, uint64_t min_chunk,
-                                                          uint64_t *__restrict__ ends, uint64_t cap,
-                                                          uint64_t *__restrict__ n_chunks_dev) {
-    const int lane = threadIdx.x;
-    const uint64_t n = *n_starts_dev;
-    const uint64_t step = min_chunk ? min_chunk : 1;
-    uint64_t last = 0, m = 0;
-    if (len == 0) {
-        if (lane == 0) *n_chunks_dev = 0;
-        return;
+// The sequential greedy rule, computed in parallel.  next(j) is the first
+// candidate whose end is >= e_j + step; the cuts are the chain first,
+// next(first), next(next(first)), ...  Chains that start at different
+// candidates merge within a few steps (each step jumps to the first end at
+// least `step` further on), which the passes below exploit twice:
+//   cs_spec   one wavefront per block of 64 candidates: every lane finds
+//             next(j) by a galloping search, and the block walks the chain
+//             that would enter it at its first candidate (a 64-bit member
+//             mask and the chain's exit);
+//   cs_super  one wavefront per superblock of 64 blocks walks the chain that
+//             would enter the superblock at its first candidate, block by
+//             block, taking each block's speculative mask as soon as it
+//             meets it; the result is a member mask per block and an exit
+//             per superblock;
+//   cs_fix    one wavefront follows the real chain superblock by superblock:
+//             from the real entry it walks until it meets the superblock's
+//             chain (usually within a block), then keeps the rest; blocks
+//             the real chain does not reach are cleared;
+//   cs_scan   block offsets (exclusive popcount scan), total, final end;
+//   cs_emit   every member writes its end at its offset.
+// Each walk falls back to next() until chains meet, so the result is exact
+// for any input.
+struct SelScratch {
+    uint32_t *next;
+    unsigned long long *spec_mask, *final_mask, *block_off;
+    uint32_t *spec_exit, *super_exit;
+};
+
+__device__ __forceinline__ uint64_t usable_count(const uint64_t *starts, uint64_t n, uint32_t w, uint64_t len) {
+    // Starts ascend and every window fits, so only the last candidate can end
+    // at len; a cut at len is not a separate chunk.
+    return (n > 0 && starts[n - 1] + w >= len) ? n - 1 : n;
+}
+
+// First index k in [lo, n) with starts[k] + w >= target, or n.
+__device__ __forceinline__ uint64_t gallop(const uint64_t *starts, uint64_t lo, uint64_t n, uint32_t w,
+                                           uint64_t target) {
+    uint64_t step = 1, hi = lo;
+    while (hi < n && starts[hi] + w < target) {
+        lo = hi + 1;
+        hi = lo + step;
+        step <<= 1;
     }
-    for (uint64_t base = 0; base < n; base += 64) {
-        const uint64_t j = base + lane;
-        const bool valid = j < n;
-        const uint64_t e = valid ? starts[j] + w : ~0ull;
-        const bool usable = valid && e < len;
-        uint64_t sel = 0;
-        while (true) {
-            const uint64_t thr = last + step < last ? ~0ull : last + step;  // saturate
-            const uint64_t elig = __ballot(usable && e >= thr);
-            if (elig == 0) break;
-            const int l = __builtin_ctzll(elig);
-            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)e, l);
-            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(e >> 32), l);
-            last = ((uint64_t)hi << 32) | lo;
-            sel |= 1ull << l;
-        }
-        if ((sel >> lane) & 1ull) {
-            const uint64_t pos = m + __builtin_popcountll(sel & ((1ull << lane) - 1ull));
-            if (pos < cap) ends[pos] = e;
-        }
-        m += __builtin_popcountll(sel);
+    if (hi > n) hi = n;
+    while (lo < hi) {  // starts[lo-1] + w < target; answer in [lo, hi]
+        const uint64_t mid = (lo + hi) >> 1;
+        if (starts[mid] + w < target) lo = mid + 1;
+        else hi = mid;
     }
-    if (lane == 0) {
-        if (m < cap) ends[m] = len;
-        *n_chunks_dev = m + 1;
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t rl32(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ unsigned long long rl64(unsigned long long v, int l) {
+    return ((unsigned long long)rl32((uint32_t)(v >> 32), l) << 32) | rl32((uint32_t)v, l);
+}
+
+// The real chain inside block b from member lane l: its member mask and the
+// first member after the block.  Uses the block's speculative chain (sm, se)
+// as soon as the walk meets it, next() before that.  Wave-uniform.
+__device__ __forceinline__ unsigned long long block_walk(const SelScratch &sc, uint64_t b, int l,
+                                                         unsigned long long sm, uint32_t se, uint64_t nu,
+                                                         uint64_t &exit) {
+    if ((sm >> l) & 1ull) {
+        exit = se;
+        return sm & (~0ull << l);
+    }
+    const uint64_t q = b * 64 + (threadIdx.x & 63);
+    const uint32_t nx_l = q < nu ? sc.next[q] : (uint32_t)nu;
+    unsigned long long m = 0;
+    while (true) {
+        m |= 1ull << l;
+        const uint32_t to = rl32(nx_l, l);
+        if (to >= b * 64 + 64 || to >= nu) {
+            exit = to;
+            return m;
+        }
+        l = (int)(to - b * 64);
+        if ((sm >> l) & 1ull) {
+            exit = se;
+            return m | (sm & (~0ull << l));
+        }
     }
 }
 
-hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint32_t w,
-                               uint64_t len, uint64_t min_chunk, uint64_t *ends, uint64_t cap,
-                               uint64_t *n_chunks_dev, hipStream_t s) {
-    chunk_select_kernel<<<1, 64, 0, s>>>(starts, n_starts_dev, w, len, min_chunk, ends, cap, n_chunks_dev);
+__global__ __launch_bounds__(256) void cs_spec(const uint64_t *__restrict__ starts, uint64_t n, uint32_t w,
+                                               uint64_t len, uint64_t step, SelScratch sc) {
+    const uint64_t nu = usable_count(starts, n, w, len);
+    const int lane = threadIdx.x & 63;
+    const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t j = b * 64 + lane;
+    const uint64_t nb = (n + 63) / 64;
+    if (b >= nb) return;  // whole wavefront
+    uint32_t nx = (uint32_t)nu;
+    if (j < nu) {
+        const uint64_t e = starts[j] + w;
+        nx = (uint32_t)gallop(starts, j + 1, nu, w, e + step);
+        sc.next[j] = nx;
+    }
+    unsigned long long mask = 0;
+    uint32_t exit = (uint32_t)nu;
+    if (b * 64 < nu) {
+        int cur = 0;
+        while (true) {
+            mask |= 1ull << cur;
+            const uint32_t to = rl32(nx, cur);
+            if (to >= b * 64 + 64 || to >= nu) {
+                exit = to;
+                break;
+            }
+            cur = (int)(to - b * 64);
+        }
+    }
+    if (lane == 0) {
+        sc.spec_mask[b] = mask;
+        sc.spec_exit[b] = exit;
+        sc.final_mask[b] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void cs_super(const uint64_t *__restrict__ starts, uint64_t n, uint32_t w,
+                                                uint64_t len, SelScratch sc) {
+    const uint64_t nu = usable_count(starts, n, w, len);
+    const int lane = threadIdx.x & 63;
+    const uint64_t S = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nb = (nu + 63) / 64;
+    const uint64_t b0 = S * 64;
+    if (b0 >= nb) return;
+    const uint64_t q = b0 + lane;
+    const unsigned long long sm_l = q < nb ? sc.spec_mask[q] : 0;
+    const uint32_t se_l = q < nb ? sc.spec_exit[q] : (uint32_t)nu;
+    uint64_t cur = b0 * 64;
+    while (cur < nu && (cur >> 6) < b0 + 64) {
+        const uint64_t b = cur >> 6;
+        const int bl = (int)(b - b0);
+        uint64_t exit;
+        const unsigned long long m = block_walk(sc, b, (int)(cur & 63), rl64(sm_l, bl), rl32(se_l, bl), nu, exit);
+        if (lane == 0) sc.final_mask[b] = m;
+        cur = exit;
+    }
+    if (lane == 0) sc.super_exit[S] = (uint32_t)cur;
+}
+
+// Clears the member masks of blocks [lo, hi) (all lanes store).
+__device__ __forceinline__ void clear_blocks(const SelScratch &sc, uint64_t lo, uint64_t hi) {
+    for (uint64_t q = lo + (threadIdx.x & 63); q < hi; q += 64) sc.final_mask[q] = 0;
+}
+
+__global__ __launch_bounds__(64) void cs_fix(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ n_dev,
+                                             uint32_t w, uint64_t len, uint64_t step, SelScratch sc) {
+    const int lane = threadIdx.x;
+    if (len == 0) return;
+    const uint64_t n = *n_dev;
+    const uint64_t nu = usable_count(starts, n, w, len);
+    const uint64_t nb = (nu + 63) / 64;
+    uint64_t cur = gallop(starts, 0, nu, w, step);  // first cut (last = 0)
+    uint64_t done_b = 0;  // blocks below this index hold their final masks
+    while (cur < nu) {
+        const uint64_t S = cur >> 12, b0 = S * 64, b_end = b0 + 64 < nb ? b0 + 64 : nb;
+        const uint64_t q = b0 + lane;
+        const unsigned long long sm_l = q < nb ? sc.spec_mask[q] : 0;
+        const uint32_t se_l = q < nb ? sc.spec_exit[q] : (uint32_t)nu;
+        const unsigned long long l1_l = q < nb ? sc.final_mask[q] : 0;
+        const uint32_t sx = sc.super_exit[S];
+        // Nothing of the real chain lies between the last finished block and
+        // the entry block.
+        clear_blocks(sc, done_b, cur >> 6);
+        while (true) {
+            const uint64_t b = cur >> 6;
+            const int bl = (int)(b - b0), l = (int)(cur & 63);
+            const unsigned long long l1 = rl64(l1_l, bl);
+            if ((l1 >> l) & 1ull) {
+                // On the superblock's chain: the rest of the superblock is right.
+                if (lane == 0) sc.final_mask[b] = l1 & (~0ull << l);
+                cur = sx;
+                done_b = b_end;
+                break;
+            }
+            uint64_t exit;
+            const unsigned long long m = block_walk(sc, b, l, rl64(sm_l, bl), rl32(se_l, bl), nu, exit);
+            if (lane == 0) sc.final_mask[b] = m;
+            if (m & l1) {  // met the superblock's chain inside block b
+                cur = sx;
+                done_b = b_end;
+                break;
+            }
+            cur = exit;
+            done_b = b + 1;
+            if (cur >= nu || (cur >> 6) >= b_end) break;  // left the superblock
+            clear_blocks(sc, done_b, cur >> 6);            // blocks the chain jumped over
+        }
+    }
+    clear_blocks(sc, done_b, nb);
+}
+
+// One workgroup: block offsets = exclusive scan of member counts; the final
+// end and the chunk count.
+__global__ __launch_bounds__(1024) void cs_scan(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ n_dev,
+                                                uint32_t w, uint64_t len, SelScratch sc, uint64_t *__restrict__ ends,
+                                                uint64_t cap, uint64_t *__restrict__ n_chunks_dev) {
+    __shared__ unsigned long long v[1024];
+    const uint32_t t = threadIdx.x;
+    if (len == 0) {
+        if (t == 0) *n_chunks_dev = 0;
+        return;
+    }
+    const uint64_t nu = usable_count(starts, *n_dev, w, len);
+    const uint64_t nb = (nu + 63) / 64;
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const unsigned long long x = c0 + t < nb ? __builtin_popcountll(sc.final_mask[c0 + t]) : 0;
+        v[t] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long y = t >= (uint32_t)off ? v[t - off] : 0;
+            __syncthreads();
+            v[t] += y;
+            __syncthreads();
+        }
+        if (c0 + t < nb) sc.block_off[c0 + t] = carry + v[t] - x;
+        carry += v[1023];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (carry < cap) ends[carry] = len;
+        *n_chunks_dev = carry + 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void cs_emit(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ n_dev,
+                                               uint32_t w, uint64_t len, SelScratch sc, uint64_t *__restrict__ ends,
+                                               uint64_t cap) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nb = (usable_count(starts, *n_dev, w, len) + 63) / 64;
+    if (b >= nb) return;
+    const unsigned long long m = sc.final_mask[b];
+    if (!((m >> lane) & 1ull)) return;
+    const uint64_t pos = sc.block_off[b] + __builtin_popcountll(m & ((1ull << lane) - 1ull));
+    if (pos < cap) ends[pos] = starts[b * 64 + lane] + w;
+}
+
+static inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t chunk_select_scratch_bytes(uint64_t n_starts) {
+    const uint64_t nb = (n_starts + 63) / 64 + 1;
+    return a256(n_starts * 4 + 4) + 3 * a256(nb * 8) + a256(nb * 4) + a256((nb / 64 + 1) * 4);
+}
+
+hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint64_t n_starts,
+                               uint32_t w, uint64_t len, uint64_t min_chunk, void *scratch, uint64_t *ends,
+                               uint64_t cap, uint64_t *n_chunks_dev, hipStream_t s) {
+    const uint64_t nb = (n_starts + 63) / 64 + 1;
+    uint8_t *q = (uint8_t *)scratch;
+    SelScratch sc;
+    sc.next = (uint32_t *)q;                 q += a256(n_starts * 4 + 4);
+    sc.spec_mask = (unsigned long long *)q;  q += a256(nb * 8);
+    sc.final_mask = (unsigned long long *)q; q += a256(nb * 8);
+    sc.block_off = (unsigned long long *)q;  q += a256(nb * 8);
+    sc.spec_exit = (uint32_t *)q;            q += a256(nb * 4);
+    sc.super_exit = (uint32_t *)q;
+    const uint64_t step = min_chunk ? min_chunk : 1;
+    hipError_t e;
+    if (n_starts) {
+        const uint64_t nbl = (n_starts + 63) / 64;
+        cs_spec<<<(unsigned)((nbl + 3) / 4), 256, 0, s>>>(starts, n_starts, w, len, step, sc);
+        const uint64_t nsb = (nbl + 63) / 64;
+        cs_super<<<(unsigned)((nsb + 3) / 4), 256, 0, s>>>(starts, n_starts, w, len, sc);
+        cs_fix<<<1, 64, 0, s>>>(starts, n_starts_dev, w, len, step, sc);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    cs_scan<<<1, 1024, 0, s>>>(starts, n_starts_dev, w, len, sc, ends, cap, n_chunks_dev);
+    if ((e = hipGetLastError()) != hipSuccess || n_starts == 0) return e;
+    const uint64_t nbl = (n_starts + 63) / 64;
+    cs_emit<<<(unsigned)((nbl + 3) / 4), 256, 0, s>>>(starts, n_starts_dev, w, len, sc, ends, cap);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------- segment digests --
-// Per-lane state of the refill loop.
-struct SegLane {
-    const uint8_t *p;   // segment start
-    uint64_t n;         // segment length
-    uint64_t done;      // bytes consumed
-    uint64_t id;        // segment index
-    int phase;          // 0: data blocks, 1: length-only block pending, 2: idle
-};
+// Chunk j is [ends[j-1], ends[j]).  Lengths are uneven (the gaps between
+// boundaries are roughly exponential), and a wavefront lasts as long as its
+// longest lane, so chunks are first ordered longest-first by a length class
+// (log2 with four sub-steps, i.e. classes 19% apart): a histogram, an
+// exclusive scan in descending class order and a scatter.  Lane t then
+// hashes chunk order[t]: each wavefront gets chunks of nearly equal length,
+// and the longest sequential chains start first.  The order inside a class
+// depends on atomics, but each digest is written at its chunk's index, so
+// the output does not.
+constexpr int SEG_CLASSES = 256;
+
+__device__ __forceinline__ uint32_t len_class(uint64_t n) {
+    if (n < 4) return (uint32_t)n;
+    const int msb = 63 - __builtin_clzll(n);
+    return (uint32_t)(msb * 4 + ((n >> (msb - 2)) & 3));
+}
+
+__device__ __forceinline__ uint64_t seg_len(const uint64_t *ends, uint64_t j) {
+    return ends[j] - (j ? ends[j - 1] : 0);
+}
+
+__global__ __launch_bounds__(256) void seg_hist(const uint64_t *__restrict__ ends, const uint64_t *__restrict__ n_dev,
+                                                uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[SEG_CLASSES];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t n = *n_dev;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[len_class(seg_len(ends, t))], 1u);
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(SEG_CLASSES) void seg_offsets(uint32_t *__restrict__ hist) {
+    // In place: hist[c] becomes the first position of class c, classes in
+    // descending order (longest first).
+    __shared__ uint32_t v[SEG_CLASSES];
+    const int t = threadIdx.x;
+    v[t] = hist[SEG_CLASSES - 1 - t];
+    __syncthreads();
+    for (int off = 1; off < SEG_CLASSES; off <<= 1) {
+        const uint32_t x = t >= off ? v[t - off] : 0;
+        __syncthreads();
+        v[t] += x;
+        __syncthreads();
+    }
+    const uint32_t incl = v[t];
+    hist[SEG_CLASSES - 1 - t] = incl - hist[SEG_CLASSES - 1 - t];
+}
+
+// Each workgroup takes a contiguous range of chunks, counts its classes in
+// LDS, reserves one range per class with a single global atomic, and then
+// places its chunks inside those ranges with LDS atomics.
+constexpr uint32_t SCATTER_PER_WG = 2048;
+
+__global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ ends, const uint64_t *__restrict__ n_dev,
+                                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ order) {
+    __shared__ uint32_t cnt[SEG_CLASSES], base[SEG_CLASSES];
+    const uint32_t t = threadIdx.x;
+    const uint64_t n = *n_dev;
+    const uint64_t lo = (uint64_t)blockIdx.x * SCATTER_PER_WG;
+    const uint64_t hi = lo + SCATTER_PER_WG < n ? lo + SCATTER_PER_WG : n;
+    cnt[t] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[len_class(seg_len(ends, i))], 1u);
+    __syncthreads();
+    base[t] = cnt[t] ? atomicAdd(&cursor[t], cnt[t]) : 0;
+    cnt[t] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + t; i < hi; i += 256) {
+        const uint32_t c = len_class(seg_len(ends, i));
+        order[base[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)i;
+    }
+}
 
 template <int KIND>
 __global__ __launch_bounds__(256) void segment_digest_kernel(const uint8_t *__restrict__ in, uint64_t len,
                                                              const uint64_t *__restrict__ ends,
                                                              const uint64_t *__restrict__ n_dev,
-                                                             uint8_t *__restrict__ out,
-                                                             uint32_t *__restrict__ counter) {
-    const uint64_t nseg = *n_dev;
-    const uint8_t *buf_end = in + len;
-    const int lane = threadIdx.x & 63;
-    SegLane L{nullptr, 0, 0, 0, 2};
-    uint32_t st[5] = {0, 0, 0, 0, 0};
-    while (true) {
-        // Refill idle lanes: one atomic per wave hands out consecutive ids.
-        const uint64_t idle = __ballot(L.phase == 2);
-        if (idle) {
-            const uint32_t want = __builtin_popcountll(idle);
-            uint32_t first = 0;
-            const int leader = __builtin_ctzll(idle);
-            if (lane == leader) first = atomicAdd(counter, want);
-            first = __builtin_amdgcn_readlane(first, leader);
-            if (L.phase == 2) {
-                const uint64_t id = first + __builtin_popcountll(idle & ((1ull << lane) - 1ull));
-                if (id < nseg) {
-                    const uint64_t s0 = id ? ends[id - 1] : 0;
-                    L.p = in + s0;
-                    L.n = ends[id] - s0;
-                    L.done = 0;
-                    L.id = id;
-                    L.phase = 0;
-                    Hash<KIND>::init(st);
-                } else {
-                    L.phase = 3;  // no work left for this lane
-                }
-            }
-        }
-        if (__ballot(L.phase < 2) == 0) break;
-        if (L.phase < 2) {
-            uint32_t X[16];
-            bool last_block = false;
-            if (L.phase == 1) {
-#pragma unroll
-                for (int j = 0; j < 16; j++) X[j] = 0;
-                Hash<KIND>::length_words(X, L.n * 8u);
-                last_block = true;
-            } else if (L.n - L.done >= 64) {
-                load_block(L.p + L.done, X);
-                L.done += 64;
-            } else {
-                const int rem = (int)(L.n - L.done);
-                load_tail(L.p + L.done, rem, buf_end, X);
-#pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    int valid = rem - 4 * j;
-                    valid = valid < 0 ? 0 : (valid > 4 ? 4 : valid);
-                    uint32_t v = X[j] & low_bytes_mask(valid);
-                    if (j == (rem >> 2)) v |= 0x80u << (8 * (rem & 3));
-                    X[j] = v;
-                }
-                if (rem < 56) {
-                    Hash<KIND>::length_words(X, L.n * 8u);
-                    last_block = true;
-                } else {
-                    L.phase = 1;
-                }
-                L.done = L.n;
-            }
-            Hash<KIND>::block(st, X);
-            if (last_block) {
-                store_digest<KIND>(out + L.id * (uint64_t)Hash<KIND>::DIGEST, st);
-                L.phase = 2;
-            }
-        }
-    }
+                                                             const uint32_t *__restrict__ order,
+                                                             uint8_t *__restrict__ out) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *n_dev) return;
+    const uint64_t j = order[t];
+    const uint64_t s0 = j ? ends[j - 1] : 0;
+    uint32_t st[5];
+    hash_range<KIND>(in + s0, ends[j] - s0, in + len, st);
+    store_digest<KIND>(out + j * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 
-__global__ void zero_u32_kernel(uint32_t *p) { *p = 0; }
+size_t segment_digest_scratch_bytes(uint64_t max_n) {
+    return SEG_CLASSES * 4 + ((max_n * 4 + 255) & ~(uint64_t)255) + 256;
+}
 
 hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
-                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
-                                  uint32_t *counter, hipStream_t s) {
+                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out, void *scratch,
+                                  hipStream_t s) {
     if (max_n == 0) return hipSuccess;
-    zero_u32_kernel<<<1, 1, 0, s>>>(counter);
-    // Enough lanes to cover the chip a few times over, never more than
-    // segments (rounded up to whole workgroups).
-    uint64_t lanes = max_n < 256ull * 1024 ? max_n : 256ull * 1024;
-    const unsigned grid = (unsigned)((lanes + 255) / 256);
+    uint32_t *hist = (uint32_t *)scratch;
+    uint32_t *order = hist + SEG_CLASSES;
+    hipError_t e = launch_fill_u32(hist, SEG_CLASSES, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned sgrid = (unsigned)std::min<uint64_t>((max_n + 255) / 256, 1024);
+    seg_hist<<<sgrid, 256, 0, s>>>(ends, n_dev, hist);
+    seg_offsets<<<1, SEG_CLASSES, 0, s>>>(hist);
+    seg_scatter<<<(unsigned)((max_n + SCATTER_PER_WG - 1) / SCATTER_PER_WG), 256, 0, s>>>(ends, n_dev, hist, order);
+    const unsigned grid = (unsigned)((max_n + 255) / 256);
     if (kind == KIND_MD5)
-        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, ends, n_dev, out, counter);
+        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, ends, n_dev, order, out);
     else
-        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, ends, n_dev, out, counter);
+        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, ends, n_dev, order, out);
     return hipGetLastError();
 }
 
@@ -210,9 +449,9 @@ __global__ __launch_bounds__(256) void set_insert(const uint8_t *__restrict__ di
 template <int D>
 __global__ __launch_bounds__(256) void set_probe(const uint8_t *__restrict__ dig_a,
                                                  const uint8_t *__restrict__ dig_b,
-                                                 const uint64_t *__restrict__ len_b, uint64_t n_b,
-                                                 const uint32_t *__restrict__ table, uint64_t slot_mask,
-                                                 unsigned long long *__restrict__ counters) {
+                                                 const uint64_t *__restrict__ len_b, int len_is_ends,
+                                                 uint64_t n_b, const uint32_t *__restrict__ table,
+                                                 uint64_t slot_mask, unsigned long long *__restrict__ counters) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool hit = false;
     uint64_t bytes = 0;
@@ -228,7 +467,7 @@ __global__ __launch_bounds__(256) void set_probe(const uint8_t *__restrict__ dig
             }
             slot = (slot + 1) & slot_mask;
         }
-        if (hit && len_b) bytes = len_b[i];
+        if (hit && len_b) bytes = len_is_ends ? len_b[i] - (i ? len_b[i - 1] : 0) : len_b[i];
     }
     // Wave reduction, then one atomic per wave.
     const unsigned long long hits = __builtin_popcountll(__ballot(hit));
@@ -256,8 +495,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 }
 
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
-                             const uint64_t *len_b, uint64_t n_b, uint32_t *table, int log2_slots,
-                             unsigned long long *counters, hipStream_t s) {
+                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
+                             int log2_slots, unsigned long long *counters, hipStream_t s) {
     const uint64_t slots = 1ull << log2_slots;
     hipError_t e = launch_fill_u32(table, slots, 0, s);
     if (e != hipSuccess) return e;
@@ -272,8 +511,10 @@ hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const
     }
     if (n_b) {
         const unsigned g = (unsigned)((n_b + 255) / 256);
-        if (kind == KIND_MD5) set_probe<16><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, n_b, table, mask, counters);
-        else set_probe<20><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, n_b, table, mask, counters);
+        if (kind == KIND_MD5)
+            set_probe<16><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, table, mask, counters);
+        else
+            set_probe<20><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, table, mask, counters);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

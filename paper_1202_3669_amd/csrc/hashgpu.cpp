@@ -17,6 +17,7 @@
 #include <cstring>
 #include <string>
 #include <unordered_set>
+#include <vector>
 
 #include "hashgpu.h"
 #include "hg_internal.hpp"
@@ -34,6 +35,10 @@ enum Slot {
     SLOT_DIG,      // chunk digests
     SLOT_TABLE,    // similarity hash set
     SLOT_OUT,      // staging of host outputs
+    SLOT_SEL,      // chunk-selection bookkeeping
+    SLOT_SEG,      // chunk-digest ordering
+    SLOT_JOBS,     // device copy of a host job table
+    SLOT_PLAN,     // batch plan
     SLOT_SMALL,    // counts and counters
     N_SLOTS
 };
@@ -43,6 +48,11 @@ constexpr size_t STAGE_PIECE = 64ull << 20;  // bytes per pinned staging buffer
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+};
+
+struct TimedLaunch {
+    int klass = -1;
+    hipEvent_t a = nullptr, b = nullptr;
 };
 
 }  // namespace
@@ -58,6 +68,12 @@ struct hg_ctx {
     hipEvent_t piece_ready = nullptr;
     hipStream_t copy_stream = nullptr;
     std::unordered_set<void *> host_allocs;
+    // Kernel timing (hg_timing_*).
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<TimedLaunch> pending;
+    uint64_t t_launches[HG_K_COUNT] = {};
+    double t_ms[HG_K_COUNT] = {};
 };
 
 namespace {
@@ -89,6 +105,57 @@ int fail(hg_ctx *ctx, int status, const char *fmt, ...) {
     } while (0)
 
 int digest_bytes(int d) { return d == HG_MD5 ? 16 : (d == HG_SHA1 ? 20 : -1); }
+
+// ------------------------------------------------------------ timing --
+int take_event(hg_ctx *ctx, hipEvent_t *e) {
+    if (!ctx->ev_pool.empty()) {
+        *e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return HG_OK;
+    }
+    HG_HIP(ctx, hipEventCreate(e));
+    return HG_OK;
+}
+
+int resolve_timing(hg_ctx *ctx) {
+    for (TimedLaunch &t : ctx->pending) {
+        HG_HIP(ctx, hipEventSynchronize(t.b));
+        float ms = 0.f;
+        HG_HIP(ctx, hipEventElapsedTime(&ms, t.a, t.b));
+        ctx->t_launches[t.klass] += 1;
+        ctx->t_ms[t.klass] += ms;
+        ctx->ev_pool.push_back(t.a);
+        ctx->ev_pool.push_back(t.b);
+    }
+    ctx->pending.clear();
+    return HG_OK;
+}
+
+int timed_begin(hg_ctx *ctx, int klass, hipStream_t st, TimedLaunch *t) {
+    if (!ctx->timing) return HG_OK;
+    if (ctx->pending.size() >= 8192) HG_TRY(resolve_timing(ctx));
+    t->klass = klass;
+    HG_TRY(take_event(ctx, &t->a));
+    HG_TRY(take_event(ctx, &t->b));
+    HG_HIP(ctx, hipEventRecord(t->a, st));
+    return HG_OK;
+}
+
+int timed_end(hg_ctx *ctx, TimedLaunch *t, hipStream_t st) {
+    if (t->klass < 0) return HG_OK;
+    HG_HIP(ctx, hipEventRecord(t->b, st));
+    ctx->pending.push_back(*t);
+    return HG_OK;
+}
+
+// Launch `expr` (a hipError_t expression) with optional event timing.
+#define HG_LAUNCH(ctx, klass, st, expr)                       \
+    do {                                                      \
+        TimedLaunch tl_;                                      \
+        HG_TRY(timed_begin((ctx), (klass), (st), &tl_));      \
+        HG_HIP((ctx), (expr));                                \
+        HG_TRY(timed_end((ctx), &tl_, (st)));                 \
+    } while (0)
 
 int ensure(hg_ctx *ctx, Slot s, size_t bytes, hipStream_t st, void **out) {
     DevBuf &b = ctx->slot[s];
@@ -124,7 +191,15 @@ bool is_pinned_host(const void *p) {
     return attr.type == hipMemoryTypeHost;
 }
 
+// The copy stream exists only in contexts that stream host input: every
+// extra stream shares the device's few hardware queues.
+int ensure_copy_stream(hg_ctx *ctx) {
+    if (!ctx->copy_stream) HG_HIP(ctx, hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+    return HG_OK;
+}
+
 int ensure_stage(hg_ctx *ctx) {
+    HG_TRY(ensure_copy_stream(ctx));
     if (ctx->stage[0]) return HG_OK;
     for (int i = 0; i < 2; i++) {
         hipError_t e = hipHostMalloc(&ctx->stage[i], STAGE_PIECE, hipHostMallocDefault);
@@ -147,6 +222,7 @@ template <class F>
 int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_t align,
               hipStream_t st, F on_piece) {
     if (n == 0) return HG_OK;
+    HG_TRY(ensure_copy_stream(ctx));
     const bool pinned = is_pinned_host(src);
     if (!pinned) HG_TRY(ensure_stage(ctx));
     uint64_t piece = STAGE_PIECE;
@@ -284,7 +360,6 @@ int hg_create(int device, hg_ctx **out) {
     hg_ctx *ctx = new hg_ctx();
     ctx->device = device;
     if (hipHostMalloc((void **)&ctx->host_small, 4096, hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->piece_ready, hipEventDisableTiming) != hipSuccess) {
         hg_destroy(ctx);
         return HG_EDEVICE;
@@ -304,6 +379,11 @@ void hg_destroy(hg_ctx *ctx) {
         if (ctx->stage_free[i]) (void)hipEventDestroy(ctx->stage_free[i]);
     }
     for (void *p : ctx->host_allocs) (void)hipHostFree(p);
+    for (TimedLaunch &t : ctx->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
     if (ctx->piece_ready) (void)hipEventDestroy(ctx->piece_ready);
     if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
@@ -361,7 +441,7 @@ int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size
     uint8_t *root = (root_out && out_dev) ? (uint8_t *)root_out : (uint8_t *)small;
 
     if (in_dev || len == 0) {
-        HG_HIP(ctx, hg::launch_leaves(digest, (const uint8_t *)in, len, block_size, n, leaves, st));
+        HG_LAUNCH(ctx, HG_K_LEAVES, st, hg::launch_leaves(digest, (const uint8_t *)in, len, block_size, n, leaves, st));
     } else {
         void *dp;
         HG_TRY(ensure(ctx, SLOT_IN, len, st, &dp));
@@ -372,16 +452,81 @@ int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size
                          [&](uint64_t off, uint64_t plen) -> int {
                              const uint64_t k0 = off / block_size;
                              const uint64_t k1 = (off + plen + block_size - 1) / block_size;
-                             HG_HIP(ctx, hg::launch_leaves(digest, din + off, plen, block_size, k1 - k0,
-                                                           leaves + k0 * (uint64_t)d, st));
+                             HG_LAUNCH(ctx, HG_K_LEAVES, st,
+                                       hg::launch_leaves(digest, din + off, plen, block_size, k1 - k0,
+                                                         leaves + k0 * (uint64_t)d, st));
                              return HG_OK;
                          }));
     }
-    if (root_out) HG_HIP(ctx, hg::launch_hash_one(digest, leaves, n * (uint64_t)d, root, st));
+    if (root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(digest, leaves, n * (uint64_t)d, root, st));
     if (leaf_out && !out_dev) HG_TRY(copy_out(ctx, leaf_out, leaves, n * (uint64_t)d, false, st));
     if (root_out && !out_dev) HG_TRY(copy_out(ctx, root_out, root, (size_t)d, false, st));
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return HG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared body of the three batch entry points.
+int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags, void *stream,
+               bool leaves, bool roots) {
+    HG_TRY(enter(ctx));
+    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC))
+        return fail(ctx, HG_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & HG_ASYNC) && !(flags & HG_IN_DEVICE))
+        return fail(ctx, HG_EINVAL, "HG_ASYNC requires a device job table (HG_IN_DEVICE)");
+    if (n_jobs == 0) return HG_OK;
+    if (!jobs) return fail(ctx, HG_EINVAL, "jobs is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const hg_block_job *djobs = jobs;
+    uint64_t total_leaves = 0;
+    const bool host_table = !(flags & HG_IN_DEVICE);
+    if (host_table) {
+        for (uint32_t i = 0; i < n_jobs; i++) {
+            const hg_block_job &j = jobs[i];
+            if (digest_bytes(j.digest) < 0) return fail(ctx, HG_EINVAL, "job %u: unknown digest", i);
+            if (j.block_size == 0) return fail(ctx, HG_EINVAL, "job %u: block_size must be >= 1", i);
+            if (j.len && (!j.in || !j.leaf_out)) return fail(ctx, HG_EINVAL, "job %u: NULL in or leaf_out", i);
+            if (j.reserved) return fail(ctx, HG_EINVAL, "job %u: reserved must be 0", i);
+            total_leaves += j.len ? (j.len + j.block_size - 1) / j.block_size : 0;
+        }
+        void *d;
+        HG_TRY(ensure(ctx, SLOT_JOBS, (size_t)n_jobs * sizeof(hg_block_job), st, &d));
+        HG_HIP(ctx, hipMemcpyAsync(d, jobs, (size_t)n_jobs * sizeof(hg_block_job), hipMemcpyHostToDevice, st));
+        djobs = (const hg_block_job *)d;
+    }
+    void *plan;
+    HG_TRY(ensure(ctx, SLOT_PLAN, hg::batch_plan_bytes(n_jobs), st, &plan));
+    HG_HIP(ctx, hg::launch_batch_plan(djobs, n_jobs, plan, st));
+    if (leaves) {
+        // A persistent grid of up to 2048 workgroups (8 per CU); fewer when
+        // the host knows there are fewer segments.
+        uint32_t grid = 2048;
+        if (host_table) grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(grid, (total_leaves + 255) / 256 + 1));
+        HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, st));
+    }
+    if (roots) HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, st));
+    if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hg_leaves_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags, void *stream) {
+    return batch_call(ctx, jobs, n_jobs, flags, stream, true, false);
+}
+
+int hg_roots_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags, void *stream) {
+    return batch_call(ctx, jobs, n_jobs, flags, stream, false, true);
+}
+
+int hg_block_hash_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
+                        void *stream) {
+    return batch_call(ctx, jobs, n_jobs, flags, stream, true, true);
 }
 
 int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, uint32_t stride,
@@ -407,10 +552,13 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
     uint64_t *small;
     HG_TRY(small_words(ctx, st, &small));
     uint64_t *total_dev = out_dev ? count : small;
-    HG_HIP(ctx, hg::launch_window_scan_count(plan, din, len, window, stride, mask, target, ws, total_dev, st));
+    HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+              hg::launch_window_scan_tiles(plan, din, len, window, stride, mask, target, ws, st));
+    HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, total_dev, st));
     if (out_dev) {
-        HG_HIP(ctx, hg::launch_window_scan_emit(plan, din, len, window, stride, mask, target, ws, starts,
-                                                capacity, st));
+        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
+                  hg::launch_window_scan_emit(plan, din, len, window, stride, mask, target, ws, starts,
+                                              capacity, st));
         if (flags & HG_ASYNC) return HG_OK;
         uint64_t total;
         HG_TRY(read_u64(ctx, total_dev, st, &total));
@@ -424,8 +572,9 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
     if (k) {
         void *o;
         HG_TRY(ensure(ctx, SLOT_OUT, k * 8, st, &o));
-        HG_HIP(ctx, hg::launch_window_scan_emit(plan, din, len, window, stride, mask, target, ws,
-                                                (uint64_t *)o, k, st));
+        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
+                  hg::launch_window_scan_emit(plan, din, len, window, stride, mask, target, ws,
+                                              (uint64_t *)o, k, st));
         HG_TRY(copy_out(ctx, starts, o, k * 8, false, st));
         HG_HIP(ctx, hipStreamSynchronize(st));
     }
@@ -457,25 +606,35 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     HG_TRY(device_input(ctx, SLOT_IN, in, len, in_dev, st, &din));
     uint64_t *small;
     HG_TRY(small_words(ctx, st, &small));
-    // small[0]: candidate total, small[1]: chunk count, small[2]: digest work counter.
+    // small[0]: candidate total, small[1]: chunk count.
     const hg::WsPlan plan = hg::plan_window_scan(din, len, pr->window, pr->stride, pr->window_digest);
     void *ws;
     HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
-    HG_HIP(ctx, hg::launch_window_scan_count(plan, din, len, pr->window, pr->stride, pr->mask, pr->target,
-                                             ws, &small[0], st));
+    HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+              hg::launch_window_scan_tiles(plan, din, len, pr->window, pr->stride, pr->mask, pr->target,
+                                           ws, st));
+    HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
     uint64_t n_cand;
     HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
     void *cand, *dends, *ddig = nullptr;
     HG_TRY(ensure(ctx, SLOT_CAND, n_cand * 8, st, &cand));
     HG_TRY(ensure(ctx, SLOT_ENDS, (n_cand + 1) * 8, st, &dends));
     if (chunk_digests) HG_TRY(ensure(ctx, SLOT_DIG, (n_cand + 1) * (uint64_t)dd, st, &ddig));
-    HG_HIP(ctx, hg::launch_window_scan_emit(plan, din, len, pr->window, pr->stride, pr->mask, pr->target, ws,
-                                            (uint64_t *)cand, n_cand, st));
-    HG_HIP(ctx, hg::launch_chunk_select((const uint64_t *)cand, &small[0], pr->window, len, pr->min_chunk,
-                                        (uint64_t *)dends, n_cand + 1, &small[1], st));
-    if (chunk_digests)
-        HG_HIP(ctx, hg::launch_segment_digests(pr->chunk_digest, din, len, (const uint64_t *)dends, &small[1],
-                                               n_cand + 1, (uint8_t *)ddig, (uint32_t *)&small[2], st));
+    HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
+              hg::launch_window_scan_emit(plan, din, len, pr->window, pr->stride, pr->mask, pr->target, ws,
+                                          (uint64_t *)cand, n_cand, st));
+    void *sel;
+    HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(n_cand), st, &sel));
+    HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+              hg::launch_chunk_select((const uint64_t *)cand, &small[0], n_cand, pr->window, len,
+                                      pr->min_chunk, sel, (uint64_t *)dends, n_cand + 1, &small[1], st));
+    if (chunk_digests) {
+        void *segs;
+        HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(n_cand + 1), st, &segs));
+        HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
+                  hg::launch_segment_digests(pr->chunk_digest, din, len, (const uint64_t *)dends, &small[1],
+                                             n_cand + 1, (uint8_t *)ddig, segs, st));
+    }
     uint64_t nc;
     HG_TRY(read_u64(ctx, &small[1], st, &nc));
     const uint64_t k = std::min(nc, capacity);
@@ -493,6 +652,8 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
                   uint64_t n_b, int digest, uint64_t *matched, uint64_t *matched_bytes, uint32_t flags,
                   void *stream) {
     HG_TRY(enter(ctx));
+    const bool len_ends = flags & HG_LEN_ENDS;
+    flags &= ~(uint32_t)HG_LEN_ENDS;
     HG_TRY(check_flags(ctx, flags, true));
     const int d = digest_bytes(digest);
     if (d < 0) return fail(ctx, HG_EINVAL, "unknown digest %d", digest);
@@ -512,11 +673,38 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
     uint64_t *small;
     HG_TRY(small_words(ctx, st, &small));
     unsigned long long *counters = (unsigned long long *)&small[4];
-    HG_HIP(ctx, hg::launch_similarity(digest, da, n_a, db, (const uint64_t *)dl, n_b, (uint32_t *)table,
-                                      log2_slots, counters, st));
+    HG_LAUNCH(ctx, HG_K_SIMILARITY, st,
+              hg::launch_similarity(digest, da, n_a, db, (const uint64_t *)dl, len_ends ? 1 : 0, n_b,
+                                    (uint32_t *)table, log2_slots, counters, st));
     HG_TRY(copy_out(ctx, matched, &counters[0], 8, out_dev, st));
     if (matched_bytes) HG_TRY(copy_out(ctx, matched_bytes, &counters[1], 8, out_dev, st));
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
+    return HG_OK;
+}
+
+int hg_timing_enable(hg_ctx *ctx, int enable) {
+    if (!ctx) return HG_EINVAL;
+    ctx->timing = enable != 0;
+    return HG_OK;
+}
+
+int hg_timing_read(hg_ctx *ctx, int kernel_class, uint64_t *launches, double *total_ms) {
+    if (!ctx) return HG_EINVAL;
+    if (kernel_class < 0 || kernel_class >= HG_K_COUNT)
+        return fail(ctx, HG_EINVAL, "unknown kernel class %d", kernel_class);
+    HG_TRY(resolve_timing(ctx));
+    if (launches) *launches = ctx->t_launches[kernel_class];
+    if (total_ms) *total_ms = ctx->t_ms[kernel_class];
+    return HG_OK;
+}
+
+int hg_timing_reset(hg_ctx *ctx) {
+    if (!ctx) return HG_EINVAL;
+    HG_TRY(resolve_timing(ctx));
+    for (int k = 0; k < HG_K_COUNT; k++) {
+        ctx->t_launches[k] = 0;
+        ctx->t_ms[k] = 0.0;
+    }
     return HG_OK;
 }
 

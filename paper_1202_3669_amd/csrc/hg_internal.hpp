@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "hashgpu.h"
+
 namespace hg {
 
 // ----------------------------------------------------------- block hash --
@@ -40,39 +42,57 @@ WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s,
 size_t window_scan_scratch_bytes(const WsPlan &p);
 
 // Pass 1: hash every window, count candidates per tile, keep up to WS_CAP
-// tile-local candidate indices per tile.  Pass 2: exclusive scan of the tile
-// counts, total, list of overflowed tiles.  Writes *total_dev.
-hipError_t launch_window_scan_count(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+// tile-local candidate indices per tile.
+hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                     uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                    uint64_t *total_dev, hipStream_t st);
+                                    hipStream_t st);
+// Pass 2: exclusive scan of the tile counts, total to *total_dev, list of
+// overflowed tiles.
+hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev,
+                                     hipStream_t st);
 
 // Pass 3: write the first `cap` candidate start offsets, ascending, to out
-// (device).  Uses the scratch filled by launch_window_scan_count.
+// (device).  Uses the scratch filled by the two passes above.
 hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
                                    uint64_t *out, uint64_t cap, hipStream_t st);
 
 // --------------------------------------------------------------- chunks --
-// Greedy selection over ascending candidate starts (count on device):
-// end e = start + w is a cut iff e >= last + max(min_chunk, 1) and e < len;
-// the final end is len.  Writes up to cap ends and *n_chunks_dev.
-hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint32_t w,
-                               uint64_t len, uint64_t min_chunk, uint64_t *ends, uint64_t cap,
-                               uint64_t *n_chunks_dev, hipStream_t s);
+// Greedy selection over ascending candidate starts: end e = start + w is a
+// cut iff e >= last + max(min_chunk, 1) and e < len; the final end is len.
+// *n_starts_dev holds the candidate count, n_starts (host) the same count
+// for sizing the grids; scratch is chunk_select_scratch_bytes(n_starts).
+// Writes up to cap ends and *n_chunks_dev.
+size_t chunk_select_scratch_bytes(uint64_t n_starts);
+hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint64_t n_starts,
+                               uint32_t w, uint64_t len, uint64_t min_chunk, void *scratch, uint64_t *ends,
+                               uint64_t cap, uint64_t *n_chunks_dev, hipStream_t s);
 
 // Digest of every segment [ends[j-1], ends[j]) (ends[-1] = 0) for
-// j < *n_dev; segments are spread over lanes with dynamic refill.
-// `counter` is a device word the launcher clears first.
+// j < *n_dev <= max_n, into out + j*digest_size.  Scratch is
+// segment_digest_scratch_bytes(max_n).
+size_t segment_digest_scratch_bytes(uint64_t max_n);
 hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
-                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
-                                  uint32_t *counter, hipStream_t s);
+                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out, void *scratch,
+                                  hipStream_t s);
+
+// ---------------------------------------------------------------- batch --
+// Jobs are hg_block_job records in device memory.  The plan (scratch of
+// batch_plan_bytes(n_jobs)) is written by launch_batch_plan and read by the
+// two launchers that follow it on the same stream.
+size_t batch_plan_bytes(uint32_t n_jobs);
+hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s);
+hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t grid,
+                               hipStream_t s);
+hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s);
 
 // ----------------------------------------------------------- similarity --
 // Open-addressing set of A's digests (table of 2^log2_slots uint32 slots),
 // then a probe of every B digest; matched count and matched byte sum land in
 // counters[0], counters[1] (cleared by the launcher).
+// len_b holds lengths, or chunk end offsets when len_is_ends is set.
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
-                             const uint64_t *len_b, uint64_t n_b, uint32_t *table,
+                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
                              int log2_slots, unsigned long long *counters, hipStream_t s);
 
 // Fill n 32-bit words with v (a kernel, so that captured graphs hold no

@@ -11,8 +11,9 @@
 //      lanes hash their windows, a wavefront scan (DPP/ds_bpermute
 //      shuffles) plus an LDS combine ranks the candidates, the tile count is
 //      stored and up to WS_CAP tile-local indices go to a per-tile bucket;
-//   2. scan: one workgroup turns tile counts into tile offsets and a total,
-//      and lists tiles whose count exceeded WS_CAP;
+//   2. scan: tile counts become tile offsets and a total (chunk sums, a
+//      scan of the chunk sums, chunk rescans), and tiles whose count
+//      exceeded WS_CAP are listed;
 //   3. emit: buckets are copied to their offsets; listed (dense) tiles are
 //      hashed again and written directly.
 // Two window-loading variants:
@@ -259,38 +260,95 @@ __global__ __launch_bounds__(WS_TPB) void ws_gen_direct(GenArgs a, const uint32_
 }
 
 // ------------------------------------------------- scan and emit passes --
+// Tile counts -> exclusive tile offsets in three passes: per-chunk sums of
+// SCAN_CHUNK tiles, one workgroup scanning the chunk sums (and writing the
+// total), per-chunk rescans writing the offsets and listing overflowed
+// tiles.
 constexpr int SCAN_TPB = 1024;
+constexpr int SCAN_PER_THREAD = 16;
+constexpr uint64_t SCAN_CHUNK = 256 * SCAN_PER_THREAD;
 
-__global__ __launch_bounds__(SCAN_TPB) void ws_scan_tiles(const uint32_t *__restrict__ tile_count,
-                                                          uint64_t n_tiles, uint64_t *__restrict__ tile_off,
+__device__ __forceinline__ unsigned long long block_exclusive64(unsigned long long v, unsigned long long &total) {
+    __shared__ unsigned long long ws[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned long long x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) ws[wid] = x;
+    __syncthreads();
+    unsigned long long base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        base += i < wid ? ws[i] : 0;
+        tot += ws[i];
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(256) void ws_chunk_sums(const uint32_t *__restrict__ tile_count, uint64_t n_tiles,
+                                                     unsigned long long *__restrict__ chunk_sum) {
+    const uint64_t lo = (uint64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER_THREAD; i++)
+        if (lo + i < n_tiles) sum += tile_count[lo + i];
+    unsigned long long total;
+    block_exclusive64(sum, total);
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_TPB) void ws_chunk_scan(unsigned long long *__restrict__ chunk_sum, uint64_t n_chunks,
                                                           uint64_t *__restrict__ total_out,
-                                                          uint32_t *__restrict__ ovf_list,
                                                           uint32_t *__restrict__ ovf_count) {
-    __shared__ uint64_t part[SCAN_TPB];
+    __shared__ unsigned long long v[SCAN_TPB];
     const uint32_t t = threadIdx.x;
     if (t == 0) *ovf_count = 0;
-    const uint64_t per = (n_tiles + SCAN_TPB - 1) / SCAN_TPB;
-    const uint64_t lo = t * per < n_tiles ? t * per : n_tiles;
-    const uint64_t hi = lo + per < n_tiles ? lo + per : n_tiles;
-    uint64_t sum = 0;
-    for (uint64_t i = lo; i < hi; i++) sum += tile_count[i];
-    part[t] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the per-thread sums.
-    for (int off = 1; off < SCAN_TPB; off <<= 1) {
-        uint64_t v = t >= (uint32_t)off ? part[t - off] : 0;
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < n_chunks; c0 += SCAN_TPB) {
+        const unsigned long long x = c0 + t < n_chunks ? chunk_sum[c0 + t] : 0;
+        v[t] = x;
         __syncthreads();
-        part[t] += v;
+        for (int off = 1; off < SCAN_TPB; off <<= 1) {
+            const unsigned long long y = t >= (uint32_t)off ? v[t - off] : 0;
+            __syncthreads();
+            v[t] += y;
+            __syncthreads();
+        }
+        if (c0 + t < n_chunks) chunk_sum[c0 + t] = carry + v[t] - x;  // exclusive
+        carry += v[SCAN_TPB - 1];
         __syncthreads();
     }
-    uint64_t base = part[t] - sum;
-    for (uint64_t i = lo; i < hi; i++) {
-        const uint32_t c = tile_count[i];
-        tile_off[i] = base;
-        base += c;
-        if (c > (uint32_t)WS_CAP) ovf_list[atomicAdd(ovf_count, 1u)] = (uint32_t)i;
+    if (t == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(256) void ws_tile_offsets(const uint32_t *__restrict__ tile_count, uint64_t n_tiles,
+                                                       const unsigned long long *__restrict__ chunk_off,
+                                                       uint64_t *__restrict__ tile_off,
+                                                       uint32_t *__restrict__ ovf_list,
+                                                       uint32_t *__restrict__ ovf_count) {
+    const uint64_t lo = (uint64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER_THREAD;
+    uint32_t c[SCAN_PER_THREAD];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER_THREAD; i++) {
+        c[i] = lo + i < n_tiles ? tile_count[lo + i] : 0;
+        sum += c[i];
     }
-    if (t == SCAN_TPB - 1) *total_out = part[t];
+    unsigned long long total;
+    unsigned long long off = chunk_off[blockIdx.x] + block_exclusive64(sum, total);
+#pragma unroll
+    for (int i = 0; i < SCAN_PER_THREAD; i++) {
+        if (lo + i < n_tiles) {
+            tile_off[lo + i] = off;
+            if (c[i] > (uint32_t)WS_CAP) ovf_list[atomicAdd(ovf_count, 1u)] = (uint32_t)(lo + i);
+        }
+        off += c[i];
+    }
 }
 
 __global__ __launch_bounds__(256) void ws_gather(const uint32_t *__restrict__ tile_count,
@@ -316,6 +374,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct WsScratch {
     uint32_t *tile_count, *bucket, *ovf_list, *ovf_count;
     uint64_t *tile_off;
+    unsigned long long *chunk_sum;
 };
 
 static WsScratch carve(const WsPlan &p, void *scratch) {
@@ -326,12 +385,14 @@ static WsScratch carve(const WsPlan &p, void *scratch) {
     s.bucket = (uint32_t *)q;    q += align256(p.n_tiles * 4 * WS_CAP);
     s.ovf_list = (uint32_t *)q;  q += align256(p.n_tiles * 4);
     s.ovf_count = (uint32_t *)q; q += 256;
+    s.chunk_sum = (unsigned long long *)q;
     return s;
 }
 
 size_t window_scan_scratch_bytes(const WsPlan &p) {
+    const uint64_t n_chunks = (p.n_tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     return align256(p.n_tiles * 8) + align256(p.n_tiles * 4) + align256(p.n_tiles * 4 * WS_CAP) +
-           align256(p.n_tiles * 4) + 256;
+           align256(p.n_tiles * 4) + 256 + align256(n_chunks * 8);
 }
 
 WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s, int kind) {
@@ -358,13 +419,10 @@ WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s,
     return p;
 }
 
-hipError_t launch_window_scan_count(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                     uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                    uint64_t *total_dev, hipStream_t st) {
-    if (p.n_tiles == 0) {
-        ws_zero_u64<<<1, 1, 0, st>>>(total_dev);
-        return hipGetLastError();
-    }
+                                    hipStream_t st) {
+    if (p.n_tiles == 0) return hipSuccess;
     WsScratch sc = carve(p, scratch);
     const dim3 grid((unsigned)p.n_tiles), blk(WS_TPB);
     if (p.variant == 1) {
@@ -378,10 +436,20 @@ hipError_t launch_window_scan_count(const WsPlan &p, const uint8_t *in, uint64_t
         else
             ws_gen_count<KIND_SHA1><<<grid, blk, p.lds_bytes, st>>>(a, sc.tile_count, sc.bucket);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    ws_scan_tiles<<<1, SCAN_TPB, 0, st>>>(sc.tile_count, p.n_tiles, sc.tile_off, total_dev, sc.ovf_list,
-                                          sc.ovf_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev, hipStream_t st) {
+    if (p.n_tiles == 0) {
+        ws_zero_u64<<<1, 1, 0, st>>>(total_dev);
+        return hipGetLastError();
+    }
+    WsScratch sc = carve(p, scratch);
+    const uint64_t n_chunks = (p.n_tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    ws_chunk_sums<<<(unsigned)n_chunks, 256, 0, st>>>(sc.tile_count, p.n_tiles, sc.chunk_sum);
+    ws_chunk_scan<<<1, SCAN_TPB, 0, st>>>(sc.chunk_sum, n_chunks, total_dev, sc.ovf_count);
+    ws_tile_offsets<<<(unsigned)n_chunks, 256, 0, st>>>(sc.tile_count, p.n_tiles, sc.chunk_sum, sc.tile_off,
+                                                        sc.ovf_list, sc.ovf_count);
     return hipGetLastError();
 }
 

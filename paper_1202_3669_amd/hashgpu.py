@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 HG_MD5, HG_SHA1 = 0, 1
 HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
-HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC = 1, 2, 4
+HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS = 1, 2, 4, 8
 HG_MAX_WINDOW = 4096
 DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
 
@@ -36,6 +36,11 @@ class hg_chunk_params(ctypes.Structure):
     _fields_ = [("window", _u32), ("stride", _u32), ("mask", _u32), ("target", _u32),
                 ("min_chunk", _u64), ("max_chunk", _u64),
                 ("window_digest", ctypes.c_int32), ("chunk_digest", ctypes.c_int32)]
+
+
+class hg_block_job(ctypes.Structure):
+    _fields_ = [("in_", _vp), ("len", _u64), ("block_size", _u64), ("leaf_out", _vp),
+                ("root_out", _vp), ("digest", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _declare(name, restype, argtypes):
@@ -59,10 +64,21 @@ hg_chunk = _declare("hg_chunk", _int,
                     [_vp, _vp, _u64, ctypes.POINTER(hg_chunk_params), _vp, _u64, _vp, _vp, _u32, _vp])
 hg_similarity = _declare("hg_similarity", _int,
                          [_vp, _vp, _u64, _vp, _vp, _u64, _int, _vp, _vp, _u32, _vp])
+hg_leaves_batch = _declare("hg_leaves_batch", _int, [_vp, _vp, _u32, _u32, _vp])
+hg_roots_batch = _declare("hg_roots_batch", _int, [_vp, _vp, _u32, _u32, _vp])
+hg_block_hash_batch = _declare("hg_block_hash_batch", _int, [_vp, _vp, _u32, _u32, _vp])
+hg_timing_enable = _declare("hg_timing_enable", _int, [_vp, _int])
+hg_timing_read = _declare("hg_timing_read", _int,
+                          [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
+hg_timing_reset = _declare("hg_timing_reset", _int, [_vp])
+
+HG_K = {"leaves": 0, "root": 1, "window_tiles": 2, "window_emit": 3, "chunk_select": 4,
+        "chunk_digests": 5, "similarity": 6, "leaves_batch": 7, "roots_batch": 8}
 
 EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_digest_size",
             "hg_host_alloc", "hg_host_free", "hg_block_hash", "hg_window_scan", "hg_chunk",
-            "hg_similarity"]
+            "hg_similarity", "hg_leaves_batch", "hg_roots_batch", "hg_block_hash_batch",
+            "hg_timing_enable", "hg_timing_read", "hg_timing_reset"]
 
 
 class HashGpuError(RuntimeError):
@@ -167,13 +183,24 @@ class Context:
 
     def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
               window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
-              capacity: int | None = None, stream=None):
-        """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks."""
+              capacity: int | None = None, stream=None, out=None):
+        """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks.
+        With out = (ends, digests, count) preallocated CUDA tensors (capacity
+        = len(ends)) the results are written there and views returned."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = data.numel()
         p = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
         d = DIGEST_SIZE[chunk_digest]
+        if out is not None:
+            ends, dig, cnt = out
+            flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+            st = hg_chunk(self.handle, data.data_ptr() if n else None, n, ctypes.byref(p),
+                          ends.data_ptr(), ends.numel(), cnt.data_ptr(),
+                          dig.data_ptr() if digests else None, flags, _stream_handle(stream))
+            self._check(st)
+            total = int(cnt.item())
+            return ends[:total], (dig[:total] if digests else None)
         if capacity is None:
             nwin = (n - window) // stride + 1 if n >= window else 0
             capacity = 1 + min(nwin, 4096 + nwin // 1024)
@@ -195,19 +222,90 @@ class Context:
             capacity = total
         raise HashGpuError(HG_ETRUNC, "chunk count changed between calls")
 
-    def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None):
-        """(matched, matched_bytes) of B's chunk digests against A's."""
+    # ------------------------------------------------------------- timing --
+    def timing(self, enable: bool = True):
+        self._check(hg_timing_enable(self.handle, 1 if enable else 0))
+
+    def timing_reset(self):
+        self._check(hg_timing_reset(self.handle))
+
+    def timing_read(self, name: str):
+        """(launches, total_ms) of a kernel class since the last reset."""
+        n = _u64(0)
+        ms = ctypes.c_double(0.0)
+        self._check(hg_timing_read(self.handle, HG_K[name], ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    # ------------------------------------------------------------ batches --
+    def batch_outputs(self, specs, roots: bool = True):
+        """Allocate outputs for [(data_tensor, block_size, digest), ...] and
+        return (records, leaf tensors, root tensors)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        recs = (hg_block_job * len(specs))()
+        leaves, rts = [], []
+        for i, (data, block, digest) in enumerate(specs):
+            d = DIGEST_SIZE[digest]
+            n = (data.numel() + block - 1) // block if data.numel() else 0
+            lv = torch.empty((n, d), dtype=torch.uint8, device=dev)
+            rt = torch.empty((d,), dtype=torch.uint8, device=dev) if roots else None
+            recs[i] = hg_block_job(data.data_ptr() if data.numel() else None, data.numel(), block,
+                                   lv.data_ptr() if n else None,
+                                   rt.data_ptr() if rt is not None else None, digest, 0)
+            leaves.append(lv)
+            rts.append(rt)
+        return recs, leaves, rts
+
+    @staticmethod
+    def device_job_table(recs):
+        """Copy hg_block_job records into a CUDA byte tensor (for
+        HG_IN_DEVICE / HG_ASYNC use)."""
+        torch = _torch()
+        raw = bytes(memoryview(recs).cast("B"))
+        return torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+
+    def block_hash_batch(self, specs, roots: bool = True, stream=None):
+        """Direct hash of many jobs: specs = [(data, block_size, digest)].
+        Returns (leaf tensors, root tensors) in spec order."""
+        recs, leaves, rts = self.batch_outputs(specs, roots)
+        fn = hg_block_hash_batch if roots else hg_leaves_batch
+        st = fn(self.handle, ctypes.addressof(recs), len(specs), HG_OUT_DEVICE,
+                _stream_handle(stream))
+        self._check(st)
+        return leaves, rts
+
+    def run_batch(self, table, n_jobs: int, which: str = "both", asynchronous: bool = True,
+                  stream=None):
+        """Run a device job table (from device_job_table): which in
+        {"leaves", "roots", "both"}."""
+        fn = {"leaves": hg_leaves_batch, "roots": hg_roots_batch,
+              "both": hg_block_hash_batch}[which]
+        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
+        self._check(fn(self.handle, table.data_ptr(), n_jobs, flags, _stream_handle(stream)))
+
+    def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None,
+                   ends_b=None, out=None, asynchronous: bool = False):
+        """(matched, matched_bytes) of B's chunk digests against A's.  Chunk
+        sizes come from len_b (lengths) or ends_b (hg_chunk end offsets).
+        With `out` (int64 CUDA tensor of 2) and asynchronous=True the counts
+        are left in `out` and nothing is returned."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         d = DIGEST_SIZE[digest]
         a = dig_a.reshape(-1, d)
         b = dig_b.reshape(-1, d)
-        res = torch.zeros(2, dtype=torch.int64, device=dev)
+        res = torch.zeros(2, dtype=torch.int64, device=dev) if out is None else out
+        lens = ends_b if ends_b is not None else len_b
+        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_LEN_ENDS if ends_b is not None else 0)
+        if asynchronous:
+            flags |= HG_ASYNC
         st = hg_similarity(self.handle, a.data_ptr() if a.numel() else None, a.shape[0],
                            b.data_ptr() if b.numel() else None,
-                           len_b.data_ptr() if len_b is not None and len_b.numel() else None,
-                           b.shape[0], digest, res.data_ptr(), res[1:].data_ptr(),
-                           HG_IN_DEVICE | HG_OUT_DEVICE, _stream_handle(stream))
+                           lens.data_ptr() if lens is not None and lens.numel() else None,
+                           b.shape[0], digest, res.data_ptr(), res[1:].data_ptr(), flags,
+                           _stream_handle(stream))
         self._check(st)
+        if asynchronous:
+            return None
         r = res.cpu()
         return int(r[0]), int(r[1])

@@ -218,7 +218,12 @@ CHUNK_CASES = [(0, 20, 1, 0xFF, 0, 2048, 0, 1), (10, 20, 1, 0xFF, 0, 2048, 0, 1)
                (5000, 20, 1, 0x3F, 0, 0, 0, 1), (5000, 20, 1, 0, 0, 0, 0, 1),
                (70_000, 20, 4, 0x3F, 1, 300, 0, 0), (70_000, 48, 3, 0x1F, 2, 500, 1, 1),
                (200_003, 20, 1, 0xFF, 0, 2048, 0, 1), (200_003, 64, 1, 0x7F, 5, 1000, 0, 1),
-               (100_000, 20, 1, 0xFF, 0, 10 ** 9, 0, 1)]
+               (100_000, 20, 1, 0xFF, 0, 10 ** 9, 0, 1),
+               # many superblocks (4096 candidates each); chains that skip
+               # whole blocks and superblocks; every window a candidate
+               (1_000_000, 20, 1, 0x3F, 0, 100_000, 0, 1), (1_000_000, 20, 1, 0xF, 0, 3000, 0, 1),
+               (1_000_000, 20, 1, 0x3, 1, 700_000, 0, 1), (2_000_003, 20, 1, 0, 0, 0, 0, 1),
+               (2_000_003, 20, 1, 0, 0, 5000, 0, 0), (2_000_003, 20, 4, 0, 0, 33, 0, 1)]
 
 
 @pytest.mark.parametrize("case", CHUNK_CASES)
@@ -292,6 +297,8 @@ def test_similarity_of_versions_small(ctx, stride):
     assert np.array_equal(host(db), xdb)
     xlb = np.diff(xb, prepend=np.uint64(0))
     assert (m, mb) == oracle.similarity(1, xda, xdb, xlb)
+    # Chunk sizes taken from the end offsets inside the kernel.
+    assert ctx.similarity(da, db, ends_b=eb) == (m, mb)
 
 
 # ------------------------------------------------------ full-size checks --
@@ -377,3 +384,43 @@ def test_invalid_arguments(ctx, hg):
     assert b"max_chunk" in buf.value
     h = ctypes.c_void_p()
     assert hg.hg_create(99, ctypes.byref(h)) == hg.HG_EDEVICE
+
+
+# ---------------------------------------------------------------- batches --
+def test_block_hash_batch_mixed_jobs(ctx, hg):
+    rng = np.random.default_rng(700)
+    specs, arrays = [], []
+    for i in range(40):
+        length = int(rng.choice([0, 1, 63, 64, 100, 5000, 70_000, 300_001, 2 * MiB + 7]))
+        block = int(rng.choice([1, 64, 100, 4096, 65536, 1 << 20]))
+        if length > 20_000 and block == 1:
+            block = 64
+        kind = int(rng.integers(0, 2))
+        data = inputs.uniform_bytes(710 + i, length)
+        arrays.append((data, block, kind))
+        specs.append((dev(data, int(rng.integers(0, 4))), block, kind))
+    note("block_hash_batch 40 mixed jobs")
+    leaves, roots = ctx.block_hash_batch(specs)
+    torch.cuda.synchronize()
+    for (data, block, kind), lv, rt in zip(arrays, leaves, roots):
+        exp = oracle.leaves(kind, data, block)
+        assert np.array_equal(host(lv), exp), (data.size, block, kind)
+        assert bytes(host(rt)) == oracle.root(kind, exp)
+
+
+def test_leaves_and_roots_batches_from_device_table(ctx, hg):
+    data = inputs.uniform_bytes(720, 8 * MiB + 3)
+    d = dev(data)
+    specs = [(d, 1 << 20, 1), (d, 1 << 20, 0), (d, 4096, 1), (d, 4096, 0), (d, 65536, 1),
+             (d, 65536, 0)]
+    recs, leaves, roots = ctx.batch_outputs(specs)
+    table = ctx.device_job_table(recs)
+    note("leaves/roots batch, device table, async")
+    s = torch.cuda.current_stream()
+    ctx.run_batch(table, len(specs), "leaves", stream=s)
+    ctx.run_batch(table, len(specs), "roots", stream=s)
+    torch.cuda.synchronize()
+    for (_, block, kind), lv, rt in zip(specs, leaves, roots):
+        exp = oracle.leaves(kind, data, block)
+        assert np.array_equal(host(lv), exp)
+        assert bytes(host(rt)) == oracle.root(kind, exp)
