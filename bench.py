@@ -151,7 +151,7 @@ class Pipeline:
         et, en = self.early_tables[parity]
         zt, zn = self.late_tables[parity]
         self.ctx2.run_batch(et, en, "roots", stream=self.s2)
-        self.ctx1.run_batch(lt, ln, "leaves", stream=self.s1)
+        self.ctx1.run_batch(lt, ln, "leaves", stream=self.s1, background=True)
         self.ctx3.run_batch(zt, zn, "roots", stream=self.s1)
         s1_done = torch.cuda.Event()
         s1_done.record(self.s1)
@@ -173,6 +173,37 @@ class Pipeline:
             done = self.group_done[i // self.G]
             out.append(self.issue_ev[i].elapsed_time(done))
         return out
+
+
+# HBM traffic of the window kernel per launch, from rocprofv3 --pmc runs
+# recorded with a hash of the kernel sources; stale figures are not used.
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "window_tiles_1GiB_pmc.md")
+KERNEL_SOURCES = ["paper_1202_3669_amd/csrc/window_scan.hip", "paper_1202_3669_amd/csrc/hg_device.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """traffic_bytes_per_launch from the profile summary, or None when the
+    summary is missing or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fields = dict(line.strip().split(": ", 1) for line in f
+                          if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+        if fields.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def pct(xs, p):
@@ -271,7 +302,8 @@ def main():
         with hg.Context(0) as c:
             c.window_scan(data, 20, 1, 0xFFF, 0)
         torch.cuda.synchronize()
-        print("[bench] pmc probe done", file=sys.stderr, flush=True)
+        print(f"[bench] pmc probe done; kernel_source_sha256: {kernel_source_hash()}",
+              file=sys.stderr, flush=True)
         return
     prev_np, _ = inputs.edited_version(data_np, 3, 1024)
     data = torch.from_numpy(data_np).cuda()
@@ -327,7 +359,7 @@ def main():
         "roofline": {"kernel": "window hash + tile count (MD5 w=20 s=1)", "bound": "alu",
                      "achieved": round(achieved, 2), "peak": round(INT32_PEAK_TOPS, 2),
                      "unit": "Tops/s (int32)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": nwt,
+                     "traffic": recorded_traffic(), "avg_launch_ms": round(avg_ms, 4), "launches": nwt,
                      "ops_per_window": WINDOW_OPS},
     }
     if not args.no_breakdown:

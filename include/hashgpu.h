@@ -65,8 +65,9 @@ enum {
     HG_EBUSY = -5    /* resource temporarily unavailable */
 };
 
-/* Flags.  HG_LEN_ENDS applies to hg_similarity only. */
-enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u, HG_LEN_ENDS = 8u };
+/* Flags.  HG_LEN_ENDS applies to hg_similarity only; HG_BACKGROUND to the
+ * batch calls only. */
+enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u, HG_LEN_ENDS = 8u, HG_BACKGROUND = 16u };
 
 /* Limits of the sliding-window primitive. */
 enum { HG_MAX_WINDOW = 4096 };
@@ -140,7 +141,10 @@ typedef struct {
  * record is validated and the table copied).  Outputs always go to the
  * device pointers inside the records; HG_OUT_DEVICE is implied.  HG_ASYNC
  * requires HG_IN_DEVICE.  The same results as one hg_block_hash call per
- * job. */
+ * job.  Wavefronts working on segments of 32 KiB or more raise their issue
+ * priority so that the launch is not stretched by its longest chains;
+ * HG_BACKGROUND keeps every wavefront at normal priority, for batches that
+ * run beside latency-critical work on another stream. */
 int hg_leaves_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
                     void *stream);
 

@@ -7,8 +7,10 @@
 //
 //   plan    one workgroup lists the jobs of each digest kind in the given
 //           order and assigns every segment a task number (prefix sums);
-//   leaves  a persistent grid; each workgroup serves one digest kind, and
-//           each lane takes the next task number from an atomic counter
+//   leaves  a persistent grid of one-wavefront workgroups (so that the
+//           first tasks, the longest chains, spread over all CUs); each
+//           workgroup serves one digest kind; a lane's first task follows
+//           from its workgroup index, later ones come from an atomic counter
 //           (one atomic per wavefront per refill), hashes that segment 64
 //           bytes per iteration, stores the digest and takes another, so
 //           uneven segments never leave a wavefront idle behind its longest
@@ -133,8 +135,13 @@ __device__ __forceinline__ uint32_t find_job(const unsigned long long *base, uin
 // Segments at least this long mark a wave as running a long chain.
 constexpr uint64_t LONG_CHAIN_BYTES = 32 * 1024;
 
+// first_task: this lane's first task (static, by workgroup index, so that
+// the first tasks -- the longest chains -- land on consecutive workgroups,
+// which the dispatcher spreads over the CUs); dyn_base: the first task
+// handed out by the refill counter.
 template <int KIND>
-__device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_jobs, Plan *plan) {
+__device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_jobs, Plan *plan,
+                              bool boost, uint64_t first_task, uint64_t dyn_base) {
     constexpr int c = KIND == KIND_SHA1 ? 1 : 0;
     constexpr int D = Hash<KIND>::DIGEST;
     const uint32_t ncls = plan->n_cls[c];
@@ -157,16 +164,20 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
     unsigned long long cb0 = 1, cb1 = 0;
     int prio = 0;
 
+    bool initial = true;
     while (true) {
         const uint64_t idle = __ballot(phase == 2);
         if (idle) {
-            const uint32_t want = __builtin_popcountll(idle);
-            const int leader = __builtin_ctzll(idle);
-            unsigned long long first = 0;
-            if (lane == leader) first = atomicAdd(&plan->next[c], (unsigned long long)want);
-            first = __shfl(first, leader, 64);
+            unsigned long long first = first_task;
+            if (!initial) {
+                const uint32_t want = __builtin_popcountll(idle);
+                const int leader = __builtin_ctzll(idle);
+                if (lane == leader) first = dyn_base + atomicAdd(&plan->next[c], (unsigned long long)want);
+                first = __shfl(first, leader, 64);
+            }
             if (phase == 2) {
-                const unsigned long long tk = first + __builtin_popcountll(idle & ((1ull << lane) - 1ull));
+                const unsigned long long tk =
+                    initial ? first : first + __builtin_popcountll(idle & ((1ull << lane) - 1ull));
                 if (tk < ntask) {
                     if (!(cb0 <= tk && tk < cb1)) {
                         ci = find_job(cbase, ncls, tk);
@@ -188,7 +199,8 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                     phase = 3;
                 }
             }
-            const int want_prio = __ballot(phase == 0 && n >= LONG_CHAIN_BYTES) ? 2 : 0;
+            initial = false;
+            const int want_prio = (boost && __ballot(phase == 0 && n >= LONG_CHAIN_BYTES)) ? 2 : 0;
             if (want_prio != prio) {
                 if (want_prio) __builtin_amdgcn_s_setprio(2);
                 else __builtin_amdgcn_s_setprio(0);
@@ -237,8 +249,8 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
     }
 }
 
-__global__ __launch_bounds__(256) void leaves_batch_kernel(const hg_block_job *__restrict__ jobs,
-                                                           uint32_t n_jobs, Plan *plan) {
+__global__ __launch_bounds__(64) void leaves_batch_kernel(const hg_block_job *__restrict__ jobs,
+                                                           uint32_t n_jobs, Plan *plan, int boost) {
     // Split the grid between the two digest kinds in proportion to their
     // VALU work (an MD5 block costs about half a SHA-1 block).
     const double w0 = (double)plan->blocks[0] * 328.0, w1 = (double)plan->blocks[1] * 618.0;
@@ -250,8 +262,13 @@ __global__ __launch_bounds__(256) void leaves_batch_kernel(const hg_block_job *_
         g0 = (uint32_t)(g * (w0 / (w0 + w1)) + 0.5);
         g0 = g0 < 1 ? 1 : (g0 > g - 1 ? g - 1 : g0);
     }
-    if (blockIdx.x < g0) leaves_worker<KIND_MD5>(jobs, n_jobs, plan);
-    else leaves_worker<KIND_SHA1>(jobs, n_jobs, plan);
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x < g0)
+        leaves_worker<KIND_MD5>(jobs, n_jobs, plan, boost != 0, (uint64_t)blockIdx.x * 64 + lane,
+                                (uint64_t)g0 * 64);
+    else
+        leaves_worker<KIND_SHA1>(jobs, n_jobs, plan, boost != 0, (uint64_t)(blockIdx.x - g0) * 64 + lane,
+                                 (uint64_t)(g - g0) * 64);
 }
 
 template <int KIND>
@@ -264,8 +281,8 @@ __device__ void root_lane(const hg_block_job &j) {
 
 // Workgroups [0, g0) take MD5 jobs, the rest SHA-1 jobs, 64 per workgroup.
 __global__ __launch_bounds__(64) void roots_batch_kernel(const hg_block_job *__restrict__ jobs,
-                                                         uint32_t n_jobs, const Plan *__restrict__ plan) {
-    __builtin_amdgcn_s_setprio(3);
+                                                         uint32_t n_jobs, const Plan *__restrict__ plan, int boost) {
+    if (boost) __builtin_amdgcn_s_setprio(3);
     const uint32_t g0 = (plan->n_cls[0] + 63) / 64;
     const int c = blockIdx.x < g0 ? 0 : 1;
     const uint32_t i = (c == 0 ? blockIdx.x : blockIdx.x - g0) * 64 + threadIdx.x;
@@ -282,15 +299,15 @@ hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *pl
 }
 
 hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t grid,
-                               hipStream_t s) {
-    leaves_batch_kernel<<<grid, 256, 0, s>>>(jobs, n_jobs, (Plan *)plan);
+                               bool boost, hipStream_t s) {
+    leaves_batch_kernel<<<grid, 64, 0, s>>>(jobs, n_jobs, (Plan *)plan, boost ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s) {
+hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, bool boost, hipStream_t s) {
     // Enough workgroups for every job of either kind; surplus ones return.
     const uint32_t grid = 2 * ((n_jobs + 63) / 64);
-    roots_batch_kernel<<<grid, 64, 0, s>>>(jobs, n_jobs, (const Plan *)plan);
+    roots_batch_kernel<<<grid, 64, 0, s>>>(jobs, n_jobs, (const Plan *)plan, boost ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -473,8 +473,9 @@ namespace {
 int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags, void *stream,
                bool leaves, bool roots) {
     HG_TRY(enter(ctx));
-    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC))
+    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC | HG_BACKGROUND))
         return fail(ctx, HG_EINVAL, "unknown flag bits 0x%x", flags);
+    const bool boost = !(flags & HG_BACKGROUND);
     if ((flags & HG_ASYNC) && !(flags & HG_IN_DEVICE))
         return fail(ctx, HG_EINVAL, "HG_ASYNC requires a device job table (HG_IN_DEVICE)");
     if (n_jobs == 0) return HG_OK;
@@ -501,13 +502,13 @@ int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t 
     HG_TRY(ensure(ctx, SLOT_PLAN, hg::batch_plan_bytes(n_jobs), st, &plan));
     HG_HIP(ctx, hg::launch_batch_plan(djobs, n_jobs, plan, st));
     if (leaves) {
-        // A persistent grid of up to 2048 workgroups (8 per CU); fewer when
-        // the host knows there are fewer segments.
-        uint32_t grid = 2048;
-        if (host_table) grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(grid, (total_leaves + 255) / 256 + 1));
-        HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, st));
+        // A persistent grid of up to 8192 one-wavefront workgroups (8 waves
+        // per CU); fewer when the host knows there are fewer segments.
+        uint32_t grid = 8192;
+        if (host_table) grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(grid, (total_leaves + 63) / 64 + 1));
+        HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, boost, st));
     }
-    if (roots) HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, st));
+    if (roots) HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, boost, st));
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return HG_OK;
 }

@@ -82,9 +82,10 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
 // two launchers that follow it on the same stream.
 size_t batch_plan_bytes(uint32_t n_jobs);
 hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s);
+// boost: waves on long chains raise their issue priority.
 hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t grid,
-                               hipStream_t s);
-hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s);
+                               bool boost, hipStream_t s);
+hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, bool boost, hipStream_t s);
 
 // ----------------------------------------------------------- similarity --
 // Open-addressing set of A's digests (table of 2^log2_slots uint32 slots),

@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 HG_MD5, HG_SHA1 = 0, 1
 HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
-HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS = 1, 2, 4, 8
+HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS, HG_BACKGROUND = 1, 2, 4, 8, 16
 HG_MAX_WINDOW = 4096
 DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
 
@@ -275,12 +275,14 @@ class Context:
         return leaves, rts
 
     def run_batch(self, table, n_jobs: int, which: str = "both", asynchronous: bool = True,
-                  stream=None):
+                  stream=None, background: bool = False):
         """Run a device job table (from device_job_table): which in
         {"leaves", "roots", "both"}."""
         fn = {"leaves": hg_leaves_batch, "roots": hg_roots_batch,
               "both": hg_block_hash_batch}[which]
         flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
+        if background:
+            flags |= HG_BACKGROUND
         self._check(fn(self.handle, table.data_ptr(), n_jobs, flags, _stream_handle(stream)))
 
     def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None,
