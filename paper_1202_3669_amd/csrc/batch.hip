@@ -208,6 +208,33 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
             }
         }
         if (__ballot(phase < 2) == 0) break;
+        // Fast path: every active lane has at least m full blocks left (its
+        // next one already in Y), so m iterations need no tail handling.
+        // Lanes without work do not limit m; a lane in its tail makes m 0.
+        {
+            const uint64_t fb = phase == 0 ? (n - done) >> 6 : (phase == 1 ? 0 : ~0ull);
+            uint64_t m = fb;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t o = __shfl_xor(m, off, 64);
+                m = o < m ? o : m;
+            }
+            if (m != ~0ull && m > 0) {
+                for (uint64_t k = 0; k < m; k++) {
+                    uint32_t X[16];
+#pragma unroll
+                    for (int i = 0; i < 16; i++) X[i] = Y[i];
+                    if (phase == 0) {
+                        // Prefetch the following block, or reload the
+                        // current one when there is none (harmless).
+                        const uint64_t nb = k + 1 < fb ? done + 64 * (k + 1) : done + 64 * k;
+                        load_block(p + nb, Y);
+                    }
+                    Hash<KIND>::block(st, X);
+                }
+                if (phase == 0) done += 64 * m;
+            }
+        }
         if (phase < 2) {
             uint32_t X[16];
             bool last = false;
