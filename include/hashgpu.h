@@ -217,6 +217,65 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
                   const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
                   uint64_t *matched_bytes, uint32_t flags, void *stream);
 
+/* -------------------------------------------------------- file batches -- */
+
+/* A planned batch of many files held in one device arena: every file gets
+ * the direct hash (segments + optional second level) and content-based
+ * chunking with chunk digests, exactly as one hg_block_hash and one hg_chunk
+ * call per file would give (batch-oriented computation, Sec. 3.1; the
+ * buffered, batched chunking of Sec. 3.2.4).  The plan uploads the file
+ * layout once and owns all scratch, so runs allocate nothing and a run can
+ * be captured into a HIP graph and replayed. */
+typedef struct hg_batch hg_batch;
+
+typedef struct {
+    uint64_t block_size;      /* direct-hash segment size; 0 = no direct hash */
+    int32_t block_digest;     /* HG_MD5 or HG_SHA1 */
+    int32_t roots;            /* nonzero: also the second level of every file */
+    hg_chunk_params chunk;    /* chunk.window == 0: no chunking */
+    uint64_t max_candidates;  /* boundary-candidate capacity over all files; 0 = twice the
+                                 expectation for random data (mask bits) plus slack */
+} hg_batch_params;
+
+/* Outputs of a run, all device pointers (sizes from hg_batch_layout). */
+typedef struct {
+    void *leaf_digests;     /* n_leaves_total * d: file f's segments start at leaf_first[f] */
+    void *roots;            /* n_files * d, file order (or NULL) */
+    uint64_t *chunk_ends;   /* max_chunks: ends relative to the file start, files in order */
+    void *chunk_digests;    /* max_chunks * d_chunk, same order (or NULL) */
+    uint64_t *chunk_off;    /* n_files + 1: chunks of file f are [chunk_off[f], chunk_off[f+1]) */
+    uint64_t *status;       /* 4 words: candidates, chunks, overflow (nonzero: the candidate
+                               capacity was too small and the chunk outputs are incomplete;
+                               re-plan with a larger max_candidates), 0 */
+} hg_batch_out;
+
+/* file_off, file_len: host arrays of n_files byte offsets/lengths inside the
+ * arena that runs will pass.  Files may overlap and need no alignment. */
+int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_len, uint32_t n_files,
+                    const hg_batch_params *params, hg_batch **out);
+void hg_batch_destroy(hg_batch *b);
+
+/* Sizes of the outputs; leaf_first (host, n_files + 1 entries) may be NULL. */
+int hg_batch_layout(const hg_batch *b, uint64_t *leaf_first, uint64_t *n_leaves_total, uint64_t *max_chunks);
+
+/* Enqueues the whole batch on `stream` (asynchronous: results are valid when
+ * the stream has completed; no host synchronization inside).  The direct
+ * hash and the chunking run as two concurrent branches. */
+int hg_batch_run(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream);
+
+/* Captures one hg_batch_run with these arguments into a HIP graph owned by
+ * the batch; hg_batch_replay launches it (one launch per batch). */
+int hg_batch_capture(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream);
+int hg_batch_replay(hg_batch *b, void *stream);
+
+/* Schedule autotuner: times the direct-hash part of the batch under each
+ * candidate segment-to-lane schedule (file order: longest first or as
+ * given; persistent grid: 1024-8192 one-wavefront workgroups) with HIP
+ * events, keeps the fastest for later runs (and captures), and writes a
+ * one-line report of what it measured.  Synchronous. */
+int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream, char *report,
+                  size_t report_len);
+
 /* ------------------------------------------------------ kernel timing -- */
 
 /* Kernel classes for the timing counters. */

@@ -333,6 +333,7 @@ hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *
 
 hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, bool boost, hipStream_t s) {
     // Enough workgroups for every job of either kind; surplus ones return.
+    if (n_jobs == 0) return hipSuccess;
     const uint32_t grid = 2 * ((n_jobs + 63) / 64);
     roots_batch_kernel<<<grid, 64, 0, s>>>(jobs, n_jobs, (const Plan *)plan, boost ? 1 : 0);
     return hipGetLastError();

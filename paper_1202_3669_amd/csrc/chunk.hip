@@ -312,18 +312,22 @@ __device__ __forceinline__ uint32_t len_class(uint64_t n) {
     return (uint32_t)(msb * 4 + ((n >> (msb - 2)) & 3));
 }
 
-__device__ __forceinline__ uint64_t seg_len(const uint64_t *ends, uint64_t j) {
-    return ends[j] - (j ? ends[j - 1] : 0);
+// Segment j is [starts[j], ends[j]), or [ends[j-1], ends[j]) without starts.
+__device__ __forceinline__ uint64_t seg_start(const uint64_t *starts, const uint64_t *ends, uint64_t j) {
+    return starts ? starts[j] : (j ? ends[j - 1] : 0);
+}
+__device__ __forceinline__ uint64_t seg_len(const uint64_t *starts, const uint64_t *ends, uint64_t j) {
+    return ends[j] - seg_start(starts, ends, j);
 }
 
-__global__ __launch_bounds__(256) void seg_hist(const uint64_t *__restrict__ ends, const uint64_t *__restrict__ n_dev,
-                                                uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(256) void seg_hist(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ ends,
+                                                const uint64_t *__restrict__ n_dev, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[SEG_CLASSES];
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t n = *n_dev;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[len_class(seg_len(ends, t))], 1u);
+        atomicAdd(&h[len_class(seg_len(starts, ends, t))], 1u);
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
@@ -350,8 +354,9 @@ __global__ __launch_bounds__(SEG_CLASSES) void seg_offsets(uint32_t *__restrict_
 // places its chunks inside those ranges with LDS atomics.
 constexpr uint32_t SCATTER_PER_WG = 2048;
 
-__global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ ends, const uint64_t *__restrict__ n_dev,
-                                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ order) {
+__global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ ends,
+                                                   const uint64_t *__restrict__ n_dev, uint32_t *__restrict__ cursor,
+                                                   uint32_t *__restrict__ order) {
     __shared__ uint32_t cnt[SEG_CLASSES], base[SEG_CLASSES];
     const uint32_t t = threadIdx.x;
     const uint64_t n = *n_dev;
@@ -359,19 +364,20 @@ __global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ 
     const uint64_t hi = lo + SCATTER_PER_WG < n ? lo + SCATTER_PER_WG : n;
     cnt[t] = 0;
     __syncthreads();
-    for (uint64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[len_class(seg_len(ends, i))], 1u);
+    for (uint64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[len_class(seg_len(starts, ends, i))], 1u);
     __syncthreads();
     base[t] = cnt[t] ? atomicAdd(&cursor[t], cnt[t]) : 0;
     cnt[t] = 0;
     __syncthreads();
     for (uint64_t i = lo + t; i < hi; i += 256) {
-        const uint32_t c = len_class(seg_len(ends, i));
+        const uint32_t c = len_class(seg_len(starts, ends, i));
         order[base[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)i;
     }
 }
 
 template <int KIND>
 __global__ __launch_bounds__(256) void segment_digest_kernel(const uint8_t *__restrict__ in, uint64_t len,
+                                                             const uint64_t *__restrict__ starts,
                                                              const uint64_t *__restrict__ ends,
                                                              const uint64_t *__restrict__ n_dev,
                                                              const uint32_t *__restrict__ order,
@@ -379,7 +385,7 @@ __global__ __launch_bounds__(256) void segment_digest_kernel(const uint8_t *__re
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *n_dev) return;
     const uint64_t j = order[t];
-    const uint64_t s0 = j ? ends[j - 1] : 0;
+    const uint64_t s0 = seg_start(starts, ends, j);
     uint32_t st[5];
     hash_range<KIND>(in + s0, ends[j] - s0, in + len, st);
     store_digest<KIND>(out + j * (uint64_t)Hash<KIND>::DIGEST, st);
@@ -389,23 +395,24 @@ size_t segment_digest_scratch_bytes(uint64_t max_n) {
     return SEG_CLASSES * 4 + ((max_n * 4 + 255) & ~(uint64_t)255) + 256;
 }
 
-hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
-                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out, void *scratch,
-                                  hipStream_t s) {
+hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *starts,
+                                  const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
+                                  void *scratch, hipStream_t s) {
     if (max_n == 0) return hipSuccess;
     uint32_t *hist = (uint32_t *)scratch;
     uint32_t *order = hist + SEG_CLASSES;
     hipError_t e = launch_fill_u32(hist, SEG_CLASSES, 0, s);
     if (e != hipSuccess) return e;
     const unsigned sgrid = (unsigned)std::min<uint64_t>((max_n + 255) / 256, 1024);
-    seg_hist<<<sgrid, 256, 0, s>>>(ends, n_dev, hist);
+    seg_hist<<<sgrid, 256, 0, s>>>(starts, ends, n_dev, hist);
     seg_offsets<<<1, SEG_CLASSES, 0, s>>>(hist);
-    seg_scatter<<<(unsigned)((max_n + SCATTER_PER_WG - 1) / SCATTER_PER_WG), 256, 0, s>>>(ends, n_dev, hist, order);
+    seg_scatter<<<(unsigned)((max_n + SCATTER_PER_WG - 1) / SCATTER_PER_WG), 256, 0, s>>>(starts, ends, n_dev, hist,
+                                                                                           order);
     const unsigned grid = (unsigned)((max_n + 255) / 256);
     if (kind == KIND_MD5)
-        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, ends, n_dev, order, out);
+        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, order, out);
     else
-        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, ends, n_dev, order, out);
+        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, order, out);
     return hipGetLastError();
 }
 

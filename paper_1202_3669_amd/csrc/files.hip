@@ -1,0 +1,165 @@
+// files.hip -- content-based chunking and direct hashing of many files at
+// once (batch-oriented computation, paper Sec. 3.1 and Sec. 3.2.4).
+//
+// The files sit in one arena; every file is chunked on its own (windows,
+// boundaries and chunks never cross a file edge).  The window scan runs over
+// all files through a tile map and leaves the candidates of all files in one
+// ascending array, file after file.  Then:
+//   files_select   one wavefront per file applies the greedy boundary rule
+//                  to that file's candidates (ballot: the first candidate end
+//                  at or beyond last + max(min, 1); readlane moves `last`);
+//                  a file has at most (its candidates + 1) chunks, so its
+//                  ends go to slots starting at (first candidate + file);
+//   files_scan     chunk counts become per-file chunk offsets and a total;
+//   files_compact  one wavefront per file copies its ends to their final
+//                  place and writes each chunk's absolute arena range for
+//                  the digest pass.
+// Direct hashing of every file reuses the batch kernels; files_jobs writes
+// their job records on the device so that a captured graph can be replayed.
+#include "hg_device.hpp"
+#include "hg_internal.hpp"
+
+namespace hg {
+
+__device__ __forceinline__ void file_cand_range(const FilesChunk &fc, uint64_t total, uint32_t f, uint64_t &c0,
+                                                uint64_t &c1) {
+    const uint64_t t0 = fc.first_tile[f], t1 = fc.first_tile[f + 1];
+    c0 = t0 < fc.n_tiles ? fc.tile_off[t0] : total;
+    c1 = t1 < fc.n_tiles ? fc.tile_off[t1] : total;
+}
+
+__global__ __launch_bounds__(64) void files_select(FilesChunk fc, uint32_t w, uint64_t step,
+                                                  uint64_t *__restrict__ status) {
+    const uint32_t f = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t total = status[0];
+    uint64_t c0, c1;
+    file_cand_range(fc, total, f, c0, c1);
+    if (c1 > fc.cap_cand) {
+        // Candidates past the capacity were not stored: the result of this
+        // run is incomplete, and says so.
+        if (lane == 0) atomicOr((unsigned long long *)&status[2], 1ull);
+        c1 = fc.cap_cand;
+        if (c0 > c1) c0 = c1;
+    }
+    const uint64_t L = fc.len[f];
+    uint64_t *out = fc.slots + c0 + f;
+    uint64_t last = 0, m = 0;
+    for (uint64_t base = c0; base < c1; base += 64) {
+        const uint64_t j = base + lane;
+        const bool valid = j < c1;
+        const uint64_t e = valid ? fc.cand[j] + w : ~0ull;
+        const bool usable = valid && e < L;
+        uint64_t sel = 0;
+        while (true) {
+            const uint64_t thr = last + step < last ? ~0ull : last + step;
+            const uint64_t elig = __ballot(usable && e >= thr);
+            if (elig == 0) break;
+            const int l = __builtin_ctzll(elig);
+            last = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(e >> 32), l) << 32) |
+                   __builtin_amdgcn_readlane((uint32_t)e, l);
+            sel |= 1ull << l;
+        }
+        if ((sel >> lane) & 1ull) out[m + __builtin_popcountll(sel & ((1ull << lane) - 1ull))] = e;
+        m += __builtin_popcountll(sel);
+    }
+    if (lane == 0) {
+        if (L > 0) out[m++] = L;
+        fc.cnt[f] = (uint32_t)m;
+    }
+}
+
+// One workgroup: chunk offsets per file and the total.
+__global__ __launch_bounds__(1024) void files_scan(const uint32_t *__restrict__ cnt, uint32_t n,
+                                                   uint64_t *__restrict__ chunk_off, uint64_t *__restrict__ status) {
+    __shared__ unsigned long long v[1024];
+    const uint32_t t = threadIdx.x;
+    unsigned long long carry = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += 1024) {
+        const unsigned long long x = c0 + t < n ? cnt[c0 + t] : 0;
+        v[t] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long y = t >= (uint32_t)off ? v[t - off] : 0;
+            __syncthreads();
+            v[t] += y;
+            __syncthreads();
+        }
+        if (c0 + t < n) chunk_off[c0 + t] = carry + v[t] - x;
+        carry += v[1023];
+        __syncthreads();
+    }
+    if (t == 0) {
+        chunk_off[n] = carry;
+        status[1] = carry;
+    }
+}
+
+__global__ __launch_bounds__(64) void files_compact(FilesChunk fc, const uint64_t *__restrict__ chunk_off,
+                                                   uint64_t *__restrict__ chunk_ends, uint64_t max_chunks,
+                                                   const uint64_t *__restrict__ status) {
+    const uint32_t f = blockIdx.x;
+    const uint64_t total = status[0];
+    uint64_t c0, c1;
+    file_cand_range(fc, total, f, c0, c1);
+    if (c0 > fc.cap_cand) c0 = fc.cap_cand;
+    const uint64_t *src = fc.slots + c0 + f;
+    const uint64_t o = chunk_off[f], n = fc.cnt[f], base = fc.off[f];
+    for (uint64_t j = threadIdx.x; j < n; j += 64) {
+        const uint64_t e = src[j], b = j ? src[j - 1] : 0;
+        if (o + j < max_chunks) {
+            chunk_ends[o + j] = e;
+            fc.seg_start[o + j] = base + b;
+            fc.seg_end[o + j] = base + e;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void files_jobs(const uint8_t *arena, const uint64_t *__restrict__ off,
+                                                  const uint64_t *__restrict__ len,
+                                                  const uint64_t *__restrict__ leaf_first,
+                                                  const uint32_t *__restrict__ order, uint32_t n, uint64_t block,
+                                                  int digest, uint8_t *leaf_out, uint8_t *roots,
+                                                  hg_block_job *__restrict__ jobs) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t f = order[i];
+    const int d = digest == HG_SHA1 ? 20 : 16;
+    hg_block_job j;
+    j.in = arena + off[f];
+    j.len = len[f];
+    j.block_size = block;
+    j.leaf_out = leaf_out + leaf_first[f] * d;
+    j.root_out = roots ? roots + (uint64_t)f * d : nullptr;
+    j.digest = digest;
+    j.reserved = 0;
+    jobs[i] = j;
+}
+
+hipError_t launch_files_select(const FilesChunk &fc, uint32_t w, uint64_t min_chunk, uint64_t *status,
+                               hipStream_t s) {
+    if (fc.n_files == 0) return hipSuccess;
+    files_select<<<fc.n_files, 64, 0, s>>>(fc, w, min_chunk ? min_chunk : 1, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_files_compact(const FilesChunk &fc, uint64_t *chunk_off, uint64_t *chunk_ends,
+                                uint64_t max_chunks, uint64_t *status, hipStream_t s) {
+    files_scan<<<1, 1024, 0, s>>>(fc.cnt, fc.n_files, chunk_off, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || fc.n_files == 0) return e;
+    files_compact<<<fc.n_files, 64, 0, s>>>(fc, chunk_off, chunk_ends, max_chunks, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_files_jobs(const uint8_t *arena, const uint64_t *off, const uint64_t *len,
+                             const uint64_t *leaf_first, const uint32_t *order, uint32_t n_files,
+                             uint64_t block, int digest, uint8_t *leaf_out, uint8_t *roots, hg_block_job *jobs,
+                             hipStream_t s) {
+    if (n_files == 0) return hipSuccess;
+    files_jobs<<<(n_files + 255) / 256, 256, 0, s>>>(arena, off, len, leaf_first, order, n_files, block, digest,
+                                                     leaf_out, roots, jobs);
+    return hipGetLastError();
+}
+
+}  // namespace hg

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -633,8 +634,8 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
         void *segs;
         HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(n_cand + 1), st, &segs));
         HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
-                  hg::launch_segment_digests(pr->chunk_digest, din, len, (const uint64_t *)dends, &small[1],
-                                             n_cand + 1, (uint8_t *)ddig, segs, st));
+                  hg::launch_segment_digests(pr->chunk_digest, din, len, nullptr, (const uint64_t *)dends,
+                                             &small[1], n_cand + 1, (uint8_t *)ddig, segs, st));
     }
     uint64_t nc;
     HG_TRY(read_u64(ctx, &small[1], st, &nc));
@@ -705,6 +706,359 @@ int hg_timing_reset(hg_ctx *ctx) {
     for (int k = 0; k < HG_K_COUNT; k++) {
         ctx->t_launches[k] = 0;
         ctx->t_ms[k] = 0.0;
+    }
+    return HG_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ file batches
+
+struct hg_batch {
+    hg_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    hg_batch_params p{};
+    int d_block = 0, d_chunk = 0;
+    bool do_hash = false, do_chunk = false;
+    std::vector<uint64_t> off, len, leaf_first;
+    std::vector<uint32_t> order_desc, order_given;
+    uint64_t n_leaves = 0, total_windows = 0, n_tiles = 0, cap_cand = 0, max_chunks = 0;
+    hg::WsPlan wsp{};
+    std::vector<void *> allocs;
+    // device tables
+    uint64_t *d_off = nullptr, *d_len = nullptr, *d_leaf_first = nullptr, *d_first_tile = nullptr;
+    hg::FileTile *d_tiles = nullptr;
+    uint32_t *d_order = nullptr;
+    hg_block_job *d_jobs = nullptr;
+    void *d_plan = nullptr, *d_ws = nullptr, *d_seg = nullptr;
+    uint64_t *d_cand = nullptr, *d_slots = nullptr, *d_seg_start = nullptr, *d_seg_end = nullptr;
+    uint32_t *d_cnt = nullptr;
+    // schedule (set by hg_batch_tune)
+    uint32_t grid = 8192;
+    bool longest_first = true;
+    // concurrency and graph
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int batch_alloc(hg_batch *b, size_t bytes, void **out) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(b->ctx, HG_ENOMEM, "batch allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    b->allocs.push_back(p);
+    *out = p;
+    return HG_OK;
+}
+
+template <class T>
+int batch_upload(hg_batch *b, const std::vector<T> &v, T **out) {
+    void *p;
+    HG_TRY(batch_alloc(b, v.size() * sizeof(T), &p));
+    if (!v.empty()) HG_HIP(b->ctx, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = (T *)p;
+    return HG_OK;
+}
+
+void batch_free(hg_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (void *p : b->allocs) (void)hipFree(p);
+    b->allocs.clear();
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+}
+
+// The direct hash of every file: job records, plan, segments, roots.
+int batch_hash(hg_batch *b, const uint8_t *arena, const hg_batch_out *out, hipStream_t st) {
+    HG_HIP(b->ctx, hg::launch_files_jobs(arena, b->d_off, b->d_len, b->d_leaf_first, b->d_order, b->n,
+                                         b->p.block_size, b->p.block_digest, (uint8_t *)out->leaf_digests,
+                                         b->p.roots ? (uint8_t *)out->roots : nullptr, b->d_jobs, st));
+    HG_HIP(b->ctx, hg::launch_batch_plan(b->d_jobs, b->n, b->d_plan, st));
+    HG_HIP(b->ctx, hg::launch_leaves_batch(b->d_jobs, b->n, b->d_plan, b->grid, true, st));
+    if (b->p.roots) HG_HIP(b->ctx, hg::launch_roots_batch(b->d_jobs, b->n, b->d_plan, true, st));
+    return HG_OK;
+}
+
+int batch_chunk(hg_batch *b, const uint8_t *arena, const hg_batch_out *out, hipStream_t st) {
+    const hg_chunk_params &c = b->p.chunk;
+    hg::WsFiles files{arena, b->d_off, b->d_len, b->d_tiles};
+    HG_HIP(b->ctx, hg::launch_window_scan_tiles(b->wsp, nullptr, 0, c.window, c.stride, c.mask, c.target, b->d_ws,
+                                                st, &files));
+    HG_HIP(b->ctx, hg::launch_window_scan_prefix(b->wsp, b->d_ws, &out->status[0], st));
+    HG_HIP(b->ctx, hg::launch_window_scan_emit(b->wsp, nullptr, 0, c.window, c.stride, c.mask, c.target, b->d_ws,
+                                               b->d_cand, b->cap_cand, st, &files));
+    hg::FilesChunk fc{b->d_off, b->d_len, b->d_first_tile,
+                      hg::window_scan_tile_offsets(b->wsp, b->d_ws),
+                      b->wsp.n_tiles, b->d_cand, b->cap_cand, b->d_slots, b->d_cnt, b->d_seg_start,
+                      b->d_seg_end, b->n};
+    HG_HIP(b->ctx, hg::launch_files_select(fc, c.window, c.min_chunk, out->status, st));
+    HG_HIP(b->ctx, hg::launch_files_compact(fc, out->chunk_off, out->chunk_ends, b->max_chunks, out->status, st));
+    if (out->chunk_digests)
+        HG_HIP(b->ctx, hg::launch_segment_digests(c.chunk_digest, arena, 0, b->d_seg_start, b->d_seg_end,
+                                                  &out->status[1], b->max_chunks, (uint8_t *)out->chunk_digests,
+                                                  b->d_seg, st));
+    return HG_OK;
+}
+
+int batch_enqueue(hg_batch *b, const void *arena, const hg_batch_out *out, hipStream_t st) {
+    HG_HIP(b->ctx, hg::launch_fill_u32((uint32_t *)out->status, 8, 0, st));
+    if (b->do_hash && b->do_chunk) {
+        // Two branches: the direct hash on the helper stream, chunking here.
+        HG_HIP(b->ctx, hipEventRecord(b->fork, st));
+        HG_HIP(b->ctx, hipStreamWaitEvent(b->aux, b->fork, 0));
+        HG_TRY(batch_hash(b, (const uint8_t *)arena, out, b->aux));
+        HG_TRY(batch_chunk(b, (const uint8_t *)arena, out, st));
+        HG_HIP(b->ctx, hipEventRecord(b->join, b->aux));
+        HG_HIP(b->ctx, hipStreamWaitEvent(st, b->join, 0));
+    } else if (b->do_hash) {
+        HG_TRY(batch_hash(b, (const uint8_t *)arena, out, st));
+    } else if (b->do_chunk) {
+        HG_TRY(batch_chunk(b, (const uint8_t *)arena, out, st));
+    }
+    return HG_OK;
+}
+
+int check_batch_out(hg_batch *b, const void *arena, const hg_batch_out *out) {
+    if (!out || !out->status) return fail(b->ctx, HG_EINVAL, "out or out->status is NULL");
+    if (!arena && b->n) return fail(b->ctx, HG_EINVAL, "arena is NULL");
+    if (b->do_hash && b->n_leaves && !out->leaf_digests) return fail(b->ctx, HG_EINVAL, "leaf_digests is NULL");
+    if (b->do_hash && b->p.roots && !out->roots) return fail(b->ctx, HG_EINVAL, "roots is NULL");
+    if (b->do_chunk && (!out->chunk_ends || !out->chunk_off))
+        return fail(b->ctx, HG_EINVAL, "chunk_ends or chunk_off is NULL");
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_len, uint32_t n_files,
+                    const hg_batch_params *params, hg_batch **out) {
+    HG_TRY(enter(ctx));
+    if (!out || !params) return fail(ctx, HG_EINVAL, "out or params is NULL");
+    *out = nullptr;
+    if (n_files && (!file_off || !file_len)) return fail(ctx, HG_EINVAL, "file_off or file_len is NULL");
+    const hg_batch_params &p = *params;
+    const bool do_hash = p.block_size != 0, do_chunk = p.chunk.window != 0;
+    if (do_hash && digest_bytes(p.block_digest) < 0) return fail(ctx, HG_EINVAL, "unknown block digest");
+    if (do_chunk) {
+        if (digest_bytes(p.chunk.window_digest) < 0 || digest_bytes(p.chunk.chunk_digest) < 0)
+            return fail(ctx, HG_EINVAL, "unknown chunk digest");
+        if (p.chunk.window > HG_MAX_WINDOW) return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
+        if (p.chunk.stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
+        if (p.chunk.max_chunk != 0) return fail(ctx, HG_EINVAL, "max_chunk must be 0");
+    }
+    hg_batch *b = new hg_batch();
+    b->ctx = ctx;
+    b->n = n_files;
+    b->p = p;
+    b->do_hash = do_hash;
+    b->do_chunk = do_chunk;
+    b->d_block = do_hash ? digest_bytes(p.block_digest) : 0;
+    b->d_chunk = do_chunk ? digest_bytes(p.chunk.chunk_digest) : 0;
+    b->off.assign(file_off, file_off + n_files);
+    b->len.assign(file_len, file_len + n_files);
+    int st = HG_OK;
+    do {
+        // Direct-hash layout and the longest-first file order.
+        b->leaf_first.assign(n_files + 1, 0);
+        for (uint32_t f = 0; f < n_files; f++)
+            b->leaf_first[f + 1] = b->leaf_first[f] + (do_hash && b->len[f] ? (b->len[f] + p.block_size - 1) / p.block_size : 0);
+        b->n_leaves = b->leaf_first[n_files];
+        b->order_given.resize(n_files);
+        std::iota(b->order_given.begin(), b->order_given.end(), 0u);
+        b->order_desc = b->order_given;
+        std::stable_sort(b->order_desc.begin(), b->order_desc.end(),
+                         [&](uint32_t x, uint32_t y) { return b->len[x] > b->len[y]; });
+        if ((st = batch_upload(b, b->off, &b->d_off)) != HG_OK) break;
+        if ((st = batch_upload(b, b->len, &b->d_len)) != HG_OK) break;
+        if ((st = batch_upload(b, b->leaf_first, &b->d_leaf_first)) != HG_OK) break;
+        if ((st = batch_upload(b, b->order_desc, &b->d_order)) != HG_OK) break;
+        void *q;
+        if ((st = batch_alloc(b, (size_t)std::max<uint32_t>(n_files, 1) * sizeof(hg_block_job), &q)) != HG_OK) break;
+        b->d_jobs = (hg_block_job *)q;
+        if ((st = batch_alloc(b, hg::batch_plan_bytes(std::max<uint32_t>(n_files, 1)), &b->d_plan)) != HG_OK) break;
+        // Chunking layout: tiles that never span a file.
+        std::vector<uint64_t> first_tile(n_files + 1, 0);
+        std::vector<hg::FileTile> tiles;
+        if (do_chunk) {
+            const uint32_t w = p.chunk.window, s = p.chunk.stride;
+            const uint64_t tw = hg::window_scan_tile_windows(w, s, p.chunk.window_digest);
+            for (uint32_t f = 0; f < n_files; f++) {
+                first_tile[f] = tiles.size();
+                const uint64_t nw = b->len[f] >= w ? (b->len[f] - w) / s + 1 : 0;
+                b->total_windows += nw;
+                for (uint64_t k0 = 0; k0 < nw; k0 += tw) tiles.push_back(hg::FileTile{f, 0, k0});
+            }
+            first_tile[n_files] = tiles.size();
+            b->n_tiles = tiles.size();
+            b->wsp = hg::plan_window_scan_files(b->n_tiles, b->total_windows, w, s, p.chunk.window_digest);
+            // Candidate capacity: twice the expectation for random data
+            // (each window matches with probability 2^-popcount(mask)) plus
+            // slack per file, unless given.
+            const double prob = std::ldexp(1.0, -__builtin_popcount(p.chunk.mask));
+            b->cap_cand = p.max_candidates ? p.max_candidates
+                                           : (uint64_t)(2.0 * prob * (double)b->total_windows) + 64ull * n_files + 4096;
+            b->cap_cand = std::min<uint64_t>(b->cap_cand, b->total_windows);
+            b->max_chunks = b->cap_cand + n_files;
+            if ((st = batch_upload(b, first_tile, &b->d_first_tile)) != HG_OK) break;
+            if ((st = batch_upload(b, tiles, &b->d_tiles)) != HG_OK) break;
+            if ((st = batch_alloc(b, hg::window_scan_scratch_bytes(b->wsp), &b->d_ws)) != HG_OK) break;
+            if ((st = batch_alloc(b, b->cap_cand * 8, &q)) != HG_OK) break;
+            b->d_cand = (uint64_t *)q;
+            if ((st = batch_alloc(b, b->max_chunks * 8, &q)) != HG_OK) break;
+            b->d_slots = (uint64_t *)q;
+            if ((st = batch_alloc(b, b->max_chunks * 8, &q)) != HG_OK) break;
+            b->d_seg_start = (uint64_t *)q;
+            if ((st = batch_alloc(b, b->max_chunks * 8, &q)) != HG_OK) break;
+            b->d_seg_end = (uint64_t *)q;
+            if ((st = batch_alloc(b, (size_t)std::max<uint32_t>(n_files, 1) * 4, &q)) != HG_OK) break;
+            b->d_cnt = (uint32_t *)q;
+            if ((st = batch_alloc(b, hg::segment_digest_scratch_bytes(b->max_chunks), &b->d_seg)) != HG_OK) break;
+        }
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming)) != hipSuccess) {
+            st = fail(ctx, HG_EDEVICE, "batch stream/event creation failed: %s", hipGetErrorString(e));
+            break;
+        }
+    } while (0);
+    if (st != HG_OK) {
+        batch_free(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return HG_OK;
+}
+
+void hg_batch_destroy(hg_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+    delete b;
+}
+
+int hg_batch_layout(const hg_batch *b, uint64_t *leaf_first, uint64_t *n_leaves_total, uint64_t *max_chunks) {
+    if (!b) return HG_EINVAL;
+    if (leaf_first) memcpy(leaf_first, b->leaf_first.data(), (b->n + 1) * sizeof(uint64_t));
+    if (n_leaves_total) *n_leaves_total = b->n_leaves;
+    if (max_chunks) *max_chunks = b->max_chunks;
+    return HG_OK;
+}
+
+int hg_batch_run(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream) {
+    if (!b) return HG_EINVAL;
+    HG_TRY(enter(b->ctx));
+    HG_TRY(check_batch_out(b, arena, out));
+    return batch_enqueue(b, arena, out, (hipStream_t)stream);
+}
+
+int hg_batch_capture(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream) {
+    if (!b) return HG_EINVAL;
+    HG_TRY(enter(b->ctx));
+    HG_TRY(check_batch_out(b, arena, out));
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return fail(b->ctx, HG_EINVAL, "capture needs a non-default stream");
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    HG_HIP(b->ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int r = batch_enqueue(b, arena, out, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (r != HG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(b->ctx, HG_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    b->graph = g;
+    HG_HIP(b->ctx, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return HG_OK;
+}
+
+int hg_batch_replay(hg_batch *b, void *stream) {
+    if (!b) return HG_EINVAL;
+    HG_TRY(enter(b->ctx));
+    if (!b->exec) return fail(b->ctx, HG_EINVAL, "no captured graph");
+    HG_HIP(b->ctx, hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return HG_OK;
+}
+
+int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream, char *report,
+                  size_t report_len) {
+    if (!b) return HG_EINVAL;
+    HG_TRY(enter(b->ctx));
+    HG_TRY(check_batch_out(b, arena, out));
+    hipStream_t st = (hipStream_t)stream;
+    std::string rep;
+    if (!b->do_hash || b->n == 0) {
+        rep = "nothing to tune";
+    } else {
+        hipEvent_t e0, e1;
+        HG_HIP(b->ctx, hipEventCreate(&e0));
+        HG_HIP(b->ctx, hipEventCreate(&e1));
+        float best = 1e30f;
+        uint32_t best_grid = b->grid;
+        bool best_order = b->longest_first;
+        const uint32_t grids[] = {1024, 2048, 4096, 8192};
+        for (int lf = 1; lf >= 0; lf--) {
+            const std::vector<uint32_t> &ord = lf ? b->order_desc : b->order_given;
+            HG_HIP(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
+            for (uint32_t g : grids) {
+                b->grid = g;
+                float t = 1e30f;
+                for (int rep_i = 0; rep_i < 3; rep_i++) {
+                    HG_HIP(b->ctx, hipEventRecord(e0, st));
+                    HG_TRY(batch_hash(b, (const uint8_t *)arena, out, st));
+                    HG_HIP(b->ctx, hipEventRecord(e1, st));
+                    HG_HIP(b->ctx, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HG_HIP(b->ctx, hipEventElapsedTime(&ms, e0, e1));
+                    if (rep_i > 0) t = std::min(t, ms);  // first run warms up
+                }
+                char buf[96];
+                snprintf(buf, sizeof buf, "%s/%u:%.3fms ", lf ? "longest" : "given", g, t);
+                rep += buf;
+                if (t < best) {
+                    best = t;
+                    best_grid = g;
+                    best_order = lf;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->grid = best_grid;
+        b->longest_first = best_order;
+        const std::vector<uint32_t> &ord = best_order ? b->order_desc : b->order_given;
+        HG_HIP(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
+        char buf[128];
+        snprintf(buf, sizeof buf, "-> %s order, %u workgroups", best_order ? "longest-first" : "given", best_grid);
+        rep += buf;
+        // A graph captured before holds the old schedule.
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
+    if (report && report_len) {
+        size_t k = std::min(report_len - 1, rep.size());
+        memcpy(report, rep.data(), k);
+        report[k] = 0;
     }
     return HG_OK;
 }

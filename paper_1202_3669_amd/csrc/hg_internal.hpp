@@ -36,26 +36,48 @@ struct WsPlan {
     uint32_t lds_bytes;   // dynamic LDS per workgroup (generic path)
 };
 
+// Many files in one arena: tile t covers windows [tiles[t].k0, +tile_windows)
+// of file tiles[t].file; a tile never spans two files.
+struct FileTile {
+    uint32_t file;
+    uint32_t pad;
+    uint64_t k0;
+};
+struct WsFiles {
+    const uint8_t *arena;
+    const uint64_t *off, *len;
+    const FileTile *tiles;
+};
+
 WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s, int kind);
+WsPlan plan_window_scan_files(uint64_t n_tiles, uint64_t total_windows, uint32_t w, uint32_t s, int kind);
+// Windows per tile for these parameters (the tile map of files uses it).
+uint64_t window_scan_tile_windows(uint32_t w, uint32_t s, int kind);
 
 // Scratch needed by a window scan plan, in bytes (256-byte aligned pieces).
 size_t window_scan_scratch_bytes(const WsPlan &p);
+// The per-tile first-candidate offsets inside that scratch (valid after
+// the prefix pass).
+const uint64_t *window_scan_tile_offsets(const WsPlan &p, const void *scratch);
 
 // Pass 1: hash every window, count candidates per tile, keep up to WS_CAP
-// tile-local candidate indices per tile.
+// tile-local candidate indices per tile.  With `files`, in/len are unused
+// and the windows come from the files' tile map.
 hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                     uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                    hipStream_t st);
+                                    hipStream_t st, const WsFiles *files = nullptr);
 // Pass 2: exclusive scan of the tile counts, total to *total_dev, list of
 // overflowed tiles.
 hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev,
                                      hipStream_t st);
 
-// Pass 3: write the first `cap` candidate start offsets, ascending, to out
-// (device).  Uses the scratch filled by the two passes above.
+// Pass 3: write the first `cap` candidate start offsets, ascending (per
+// file and file-relative with `files`), to out (device).  Uses the scratch
+// filled by the two passes above.
 hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                   uint64_t *out, uint64_t cap, hipStream_t st);
+                                   uint64_t *out, uint64_t cap, hipStream_t st,
+                                   const WsFiles *files = nullptr);
 
 // --------------------------------------------------------------- chunks --
 // Greedy selection over ascending candidate starts: end e = start + w is a
@@ -68,13 +90,42 @@ hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_
                                uint32_t w, uint64_t len, uint64_t min_chunk, void *scratch, uint64_t *ends,
                                uint64_t cap, uint64_t *n_chunks_dev, hipStream_t s);
 
-// Digest of every segment [ends[j-1], ends[j]) (ends[-1] = 0) for
-// j < *n_dev <= max_n, into out + j*digest_size.  Scratch is
-// segment_digest_scratch_bytes(max_n).
+// Digest of every segment j < *n_dev <= max_n, into out + j*digest_size.
+// Segment j is [starts[j], ends[j]) when starts is given, else
+// [ends[j-1], ends[j]) with ends[-1] = 0 (offsets relative to in).  Scratch
+// is segment_digest_scratch_bytes(max_n).
 size_t segment_digest_scratch_bytes(uint64_t max_n);
-hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
-                                  const uint64_t *n_dev, uint64_t max_n, uint8_t *out, void *scratch,
-                                  hipStream_t s);
+hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *starts,
+                                  const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
+                                  void *scratch, hipStream_t s);
+
+// ---------------------------------------------------------------- files --
+// Content-based chunking of many files (see files.hip).  cand: candidate
+// starts (file-relative, files in order) with capacity cap_cand; the tile
+// offsets and the total come from the window scan's prefix pass.
+struct FilesChunk {
+    const uint64_t *off, *len;        // per file
+    const uint64_t *first_tile;       // n_files + 1
+    const uint64_t *tile_off;         // per tile: first candidate
+    uint64_t n_tiles;
+    const uint64_t *cand;             // candidate starts
+    uint64_t cap_cand;
+    uint64_t *slots;                  // cap_cand + n_files chunk ends
+    uint32_t *cnt;                    // chunks per file
+    uint64_t *seg_start, *seg_end;    // absolute arena offsets, cap_cand + n_files
+    uint32_t n_files;
+};
+// status[0] = candidates (written by the prefix pass), status[1] = chunks,
+// status[2] = nonzero when the candidate capacity was exceeded.
+hipError_t launch_files_select(const FilesChunk &fc, uint32_t w, uint64_t min_chunk, uint64_t *status,
+                               hipStream_t s);
+hipError_t launch_files_compact(const FilesChunk &fc, uint64_t *chunk_off, uint64_t *chunk_ends,
+                                uint64_t max_chunks, uint64_t *status, hipStream_t s);
+// Job records of the direct hash of every file (order[i] = file of record i).
+hipError_t launch_files_jobs(const uint8_t *arena, const uint64_t *off, const uint64_t *len,
+                             const uint64_t *leaf_first, const uint32_t *order, uint32_t n_files,
+                             uint64_t block, int digest, uint8_t *leaf_out, uint8_t *roots, hg_block_job *jobs,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- batch --
 // Jobs are hg_block_job records in device memory.  The plan (scratch of

@@ -77,28 +77,64 @@ __device__ __forceinline__ uint32_t win_word(const uint32_t (&dw)[ND], const int
     return 0u;
 }
 
-// Candidate bits of the lane's WS_G windows (bit g = window k0 + g).
+// Where a tile's windows come from: one buffer cut into tiles of
+// consecutive windows, or files of an arena through a tile map (a tile never
+// spans two files, so window indices and offsets stay file-relative).
+struct TileView {
+    const uint8_t *in;  // the buffer (file) the windows lie in
+    uint64_t len;       // its length
+    uint64_t nwin;      // its number of windows
+    uint64_t k0;        // first window of the tile
+};
+
+struct SingleSrc {
+    const uint8_t *in;
+    uint64_t len, nwin, tile_windows;
+    __device__ TileView view(uint64_t t) const { return {in, len, nwin, t * tile_windows}; }
+};
+
+struct FileSrc {
+    const uint8_t *arena;
+    const uint64_t *off, *flen;
+    const FileTile *tiles;
+    uint32_t w, s;
+    __device__ TileView view(uint64_t t) const {
+        const FileTile ft = tiles[t];
+        const uint64_t L = flen[ft.file];
+        return {arena + off[ft.file], L, L >= w ? (L - w) / s + 1 : 0, ft.k0};
+    }
+};
+
+// Candidate bits of the lane's WS_G windows (bit g = window k0 + g) of a
+// tile view.
 template <int W, int S>
-__device__ __forceinline__ uint32_t ws_reg_bits(const uint8_t *__restrict__ in, uint64_t len,
-                                                uint64_t nwin, uint32_t mask, uint32_t target,
-                                                uint64_t tile) {
+__device__ __forceinline__ uint32_t ws_reg_bits(const TileView v, uint32_t mask, uint32_t target) {
     constexpr int SPAN = (WS_G - 1) * S + W;
     constexpr int ND = (SPAN + 3) / 4;
-    const uint64_t k0 = tile * (uint64_t)(WS_TPB * WS_G) + (uint64_t)threadIdx.x * WS_G;
-    if (k0 >= nwin) return 0;
-    const uint64_t b0 = k0 * S;  // multiple of 16 * S: 16-byte aligned
+    const uint64_t k0 = v.k0 + (uint64_t)threadIdx.x * WS_G;
+    if (k0 >= v.nwin) return 0;
+    const uint64_t b0 = k0 * S;
+    const uint8_t *in = v.in;
+    const uint64_t len = v.len;
     uint32_t dw[ND];
     if (b0 + 4 * ND <= len) {
         __builtin_memcpy(dw, in + b0, 4 * ND);
     } else {
-        // Last lanes of the buffer: dword-wise, and only dwords that start
-        // before len (each such aligned dword holds at least one byte of
-        // the buffer).  Bytes past len only feed windows k >= nwin.
+        // Last lanes of a buffer: whole dwords while they fit, then single
+        // bytes, so nothing at or past len is read.  Bytes past len only
+        // feed windows k >= nwin.
 #pragma unroll
         for (int j = 0; j < ND; j++) {
-            uint32_t v = 0;
-            if (b0 + 4 * j < len) __builtin_memcpy(&v, in + b0 + 4 * j, 4);
-            dw[j] = v;
+            uint32_t x = 0;
+            const uint64_t o = b0 + 4 * j;
+            if (o + 4 <= len) {
+                __builtin_memcpy(&x, in + o, 4);
+            } else {
+#pragma unroll
+                for (int b = 0; b < 3; b++)
+                    if (o + b < len) x |= (uint32_t)in[o + b] << (8 * b);
+            }
+            dw[j] = x;
         }
     }
     const uint32_t st[4] = {MD5_IV0, MD5_IV1, MD5_IV2, MD5_IV3};
@@ -109,19 +145,18 @@ __device__ __forceinline__ uint32_t ws_reg_bits(const uint8_t *__restrict__ in, 
 #pragma unroll
         for (int j = 0; j < 16; j++) X[j] = win_word<W, ND>(dw, g * S, j);
         uint32_t a0 = md5_compress_word0(st, X);
-        bool hit = ((a0 & mask) == target) && (k0 + g < nwin);
+        bool hit = ((a0 & mask) == target) && (k0 + g < v.nwin);
         bits |= (uint32_t)hit << g;
     }
     return bits;
 }
 
-template <int W, int S>
-__global__ __launch_bounds__(WS_TPB) void ws_reg_count(const uint8_t *__restrict__ in, uint64_t len,
-                                                       uint64_t nwin, uint32_t mask, uint32_t target,
+template <int W, int S, class Src>
+__global__ __launch_bounds__(WS_TPB) void ws_reg_count(Src src, uint32_t mask, uint32_t target,
                                                        uint32_t *__restrict__ tile_count,
                                                        uint32_t *__restrict__ bucket) {
     const uint64_t tile = blockIdx.x;
-    uint32_t bits = ws_reg_bits<W, S>(in, len, nwin, mask, target, tile);
+    uint32_t bits = ws_reg_bits<W, S>(src.view(tile), mask, target);
     uint32_t total;
     uint32_t pre = block_exclusive(__popc(bits), total);
     if (threadIdx.x == 0) tile_count[tile] = total;
@@ -135,9 +170,8 @@ __global__ __launch_bounds__(WS_TPB) void ws_reg_count(const uint8_t *__restrict
     }
 }
 
-template <int W, int S>
-__global__ __launch_bounds__(WS_TPB) void ws_reg_direct(const uint8_t *__restrict__ in, uint64_t len,
-                                                        uint64_t nwin, uint32_t mask, uint32_t target,
+template <int W, int S, class Src>
+__global__ __launch_bounds__(WS_TPB) void ws_reg_direct(Src src, uint32_t mask, uint32_t target,
                                                         const uint32_t *__restrict__ ovf_list,
                                                         const uint32_t *__restrict__ ovf_count,
                                                         const uint64_t *__restrict__ tile_off,
@@ -145,11 +179,12 @@ __global__ __launch_bounds__(WS_TPB) void ws_reg_direct(const uint8_t *__restric
     const uint32_t n_ovf = *ovf_count;
     for (uint32_t i = blockIdx.x; i < n_ovf; i += gridDim.x) {
         const uint64_t tile = ovf_list[i];
-        uint32_t bits = ws_reg_bits<W, S>(in, len, nwin, mask, target, tile);
+        const TileView v = src.view(tile);
+        uint32_t bits = ws_reg_bits<W, S>(v, mask, target);
         uint32_t total;
         uint32_t pre = block_exclusive(__popc(bits), total);
         uint64_t pos = tile_off[tile] + pre;
-        const uint64_t k0 = tile * (uint64_t)(WS_TPB * WS_G) + (uint64_t)threadIdx.x * WS_G;
+        const uint64_t k0 = v.k0 + (uint64_t)threadIdx.x * WS_G;
         while (bits) {
             int g = __ffs(bits) - 1;
             bits &= bits - 1;
@@ -187,33 +222,36 @@ __device__ __forceinline__ uint32_t lds_hash_word0(const uint32_t *lds, uint32_t
     return Hash<KIND>::word0(st);
 }
 
-struct GenArgs {
-    const uint8_t *in;
-    uint64_t len, nwin, tile_windows;
-    uint32_t w, s, mask, target;
-};
-
 // One tile: stage its bytes in LDS, hash its windows in rounds of WS_TPB
 // consecutive windows (lane i takes window round*WS_TPB + i), rank
 // candidates in window order.  EMIT = false: count + bucket; EMIT = true:
 // write offsets at tile_off[tile] onward.
 template <int KIND, bool EMIT>
-__device__ __forceinline__ void ws_gen_tile(const GenArgs &a, uint64_t tile, uint32_t *lds,
+__device__ __forceinline__ void ws_gen_tile(const TileView v, uint64_t tile_windows, uint32_t w, uint32_t s,
+                                            uint32_t mask, uint32_t target, uint64_t tile, uint32_t *lds,
                                             uint32_t *tile_count, uint32_t *bucket,
                                             const uint64_t *tile_off, uint64_t *out, uint64_t cap) {
-    const uint64_t kf = tile * a.tile_windows;
-    const uint64_t ke = kf + a.tile_windows < a.nwin ? kf + a.tile_windows : a.nwin;
-    const uint8_t *src = a.in + kf * a.s;
+    const uint64_t kf = v.k0;
+    const uint64_t ke = kf + tile_windows < v.nwin ? kf + tile_windows : v.nwin;
+    const uint8_t *src = v.in + kf * s;
     const uintptr_t base = (uintptr_t)src & ~(uintptr_t)3;
     const uint32_t delta = (uint32_t)((uintptr_t)src - base);
-    const uint64_t nbytes = (ke - 1) * a.s + a.w - kf * a.s + delta;
+    const uint64_t nbytes = ke > kf ? (ke - 1) * s + w - kf * s + delta : 0;
     const uint32_t ndw = (uint32_t)((nbytes + 3) >> 2);
-    const uintptr_t end = (uintptr_t)(a.in + a.len);
+    const uintptr_t first = (uintptr_t)v.in, end = (uintptr_t)(v.in + v.len);
     for (uint32_t i = threadIdx.x; i <= ndw; i += WS_TPB) {
         const uintptr_t addr = base + 4ull * i;
-        // An aligned dword that starts before the buffer end holds at least
-        // one byte of the buffer; the pad dword at index ndw is zero.
-        lds[i] = (i < ndw && addr < end) ? *(const uint32_t *)addr : 0u;
+        uint32_t x = 0;
+        if (i < ndw) {
+            if (addr >= first && addr + 4 <= end) {
+                x = *(const uint32_t *)addr;
+            } else {
+                // Edge dwords: only the bytes inside the buffer.
+                for (int b = 0; b < 4; b++)
+                    if (addr + b >= first && addr + b < end) x |= (uint32_t)(*(const uint8_t *)(addr + b)) << (8 * b);
+            }
+        }
+        lds[i] = x;  // the pad dword at index ndw is zero
     }
     __syncthreads();
     uint32_t done = 0;
@@ -222,15 +260,15 @@ __device__ __forceinline__ void ws_gen_tile(const GenArgs &a, uint64_t tile, uin
         const uint64_t k = kf + r0 + threadIdx.x;
         bool hit = false;
         if (k < ke) {
-            const uint32_t o = delta + (uint32_t)((r0 + threadIdx.x) * a.s);
-            hit = (lds_hash_word0<KIND>(lds, o, a.w) & a.mask) == a.target;
+            const uint32_t o = delta + (uint32_t)((r0 + threadIdx.x) * s);
+            hit = (lds_hash_word0<KIND>(lds, o, w) & mask) == target;
         }
         uint32_t total;
         const uint32_t pre = block_exclusive(hit ? 1u : 0u, total);
         if (hit) {
             const uint32_t rank = done + pre;
             if (EMIT) {
-                if (pos0 + rank < cap) out[pos0 + rank] = k * a.s;
+                if (pos0 + rank < cap) out[pos0 + rank] = k * s;
             } else if (rank < (uint32_t)WS_CAP) {
                 bucket[tile * WS_CAP + rank] = (uint32_t)(r0 + threadIdx.x);
             }
@@ -241,22 +279,30 @@ __device__ __forceinline__ void ws_gen_tile(const GenArgs &a, uint64_t tile, uin
     __syncthreads();  // the LDS tile may be restaged by the next tile
 }
 
-template <int KIND>
-__global__ __launch_bounds__(WS_TPB) void ws_gen_count(GenArgs a, uint32_t *__restrict__ tile_count,
+template <int KIND, class Src>
+__global__ __launch_bounds__(WS_TPB) void ws_gen_count(Src src, uint64_t tile_windows, uint32_t w, uint32_t s,
+                                                       uint32_t mask, uint32_t target,
+                                                       uint32_t *__restrict__ tile_count,
                                                        uint32_t *__restrict__ bucket) {
     extern __shared__ uint32_t lds[];
-    ws_gen_tile<KIND, false>(a, blockIdx.x, lds, tile_count, bucket, nullptr, nullptr, 0);
+    ws_gen_tile<KIND, false>(src.view(blockIdx.x), tile_windows, w, s, mask, target, blockIdx.x, lds,
+                             tile_count, bucket, nullptr, nullptr, 0);
 }
 
-template <int KIND>
-__global__ __launch_bounds__(WS_TPB) void ws_gen_direct(GenArgs a, const uint32_t *__restrict__ ovf_list,
+template <int KIND, class Src>
+__global__ __launch_bounds__(WS_TPB) void ws_gen_direct(Src src, uint64_t tile_windows, uint32_t w, uint32_t s,
+                                                        uint32_t mask, uint32_t target,
+                                                        const uint32_t *__restrict__ ovf_list,
                                                         const uint32_t *__restrict__ ovf_count,
                                                         const uint64_t *__restrict__ tile_off,
                                                         uint64_t *__restrict__ out, uint64_t cap) {
     extern __shared__ uint32_t lds[];
     const uint32_t n_ovf = *ovf_count;
-    for (uint32_t i = blockIdx.x; i < n_ovf; i += gridDim.x)
-        ws_gen_tile<KIND, true>(a, ovf_list[i], lds, nullptr, nullptr, tile_off, out, cap);
+    for (uint32_t i = blockIdx.x; i < n_ovf; i += gridDim.x) {
+        const uint64_t tile = ovf_list[i];
+        ws_gen_tile<KIND, true>(src.view(tile), tile_windows, w, s, mask, target, tile, lds, nullptr, nullptr,
+                                tile_off, out, cap);
+    }
 }
 
 // ------------------------------------------------- scan and emit passes --
@@ -351,18 +397,19 @@ __global__ __launch_bounds__(256) void ws_tile_offsets(const uint32_t *__restric
     }
 }
 
-__global__ __launch_bounds__(256) void ws_gather(const uint32_t *__restrict__ tile_count,
+template <class Src>
+__global__ __launch_bounds__(256) void ws_gather(Src src, const uint32_t *__restrict__ tile_count,
                                                  const uint32_t *__restrict__ bucket,
                                                  const uint64_t *__restrict__ tile_off, uint64_t n_tiles,
-                                                 uint64_t tile_windows, uint32_t s,
-                                                 uint64_t *__restrict__ out, uint64_t cap) {
+                                                 uint32_t s, uint64_t *__restrict__ out, uint64_t cap) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const uint32_t c = tile_count[t];
     if (c == 0 || c > (uint32_t)WS_CAP) return;
     const uint64_t off = tile_off[t];
+    const uint64_t k0 = src.view(t).k0;
     for (uint32_t i = 0; i < c; i++) {
-        if (off + i < cap) out[off + i] = (t * tile_windows + bucket[t * WS_CAP + i]) * s;
+        if (off + i < cap) out[off + i] = (k0 + bucket[t * WS_CAP + i]) * s;
     }
 }
 
@@ -389,54 +436,82 @@ static WsScratch carve(const WsPlan &p, void *scratch) {
     return s;
 }
 
+const uint64_t *window_scan_tile_offsets(const WsPlan &p, const void *scratch) {
+    return carve(p, (void *)scratch).tile_off;
+}
+
 size_t window_scan_scratch_bytes(const WsPlan &p) {
     const uint64_t n_chunks = (p.n_tiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
     return align256(p.n_tiles * 8) + align256(p.n_tiles * 4) + align256(p.n_tiles * 4 * WS_CAP) +
            align256(p.n_tiles * 4) + 256 + align256(n_chunks * 8);
 }
 
-WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s, int kind) {
+uint64_t window_scan_tile_windows(uint32_t w, uint32_t s, int kind) {
+    if (kind == KIND_MD5 && w == 20 && (s == 1 || s == 4)) return (uint64_t)WS_TPB * WS_G;
+    // Largest tile whose bytes fit the LDS budget, capped at 2048 windows and
+    // rounded to whole rounds of WS_TPB windows when possible.
+    uint64_t t = ((uint64_t)WS_LDS_MAX - w - 8) / s + 1;
+    if (t > 2048) t = 2048;
+    if (t >= WS_TPB) t -= t % WS_TPB;
+    if (t == 0) t = 1;
+    return t;
+}
+
+static WsPlan plan_common(uint32_t w, uint32_t s, int kind) {
     WsPlan p{};
     p.kind = kind;
-    p.nwin = (w == 0 || s == 0 || len < w) ? 0 : (len - w) / s + 1;
-    const bool aligned16 = ((uintptr_t)in & 15) == 0;
-    if (kind == KIND_MD5 && w == 20 && (s == 1 || s == 4) && aligned16) {
+    p.tile_windows = window_scan_tile_windows(w, s, kind);
+    if (kind == KIND_MD5 && w == 20 && (s == 1 || s == 4)) {
         p.variant = s == 1 ? 1 : 2;
-        p.tile_windows = (uint64_t)WS_TPB * WS_G;
         p.lds_bytes = 0;
     } else {
         p.variant = 0;
-        // Largest tile whose bytes fit the LDS budget, capped at 2048 windows
-        // and rounded to whole rounds of WS_TPB windows when possible.
-        uint64_t t = ((uint64_t)WS_LDS_MAX - w - 8) / s + 1;
-        if (t > 2048) t = 2048;
-        if (t >= WS_TPB) t -= t % WS_TPB;
-        if (t == 0) t = 1;
-        p.tile_windows = t;
-        p.lds_bytes = (uint32_t)((((t - 1) * s + w + 3 + 3) / 4 + 1) * 4);
+        p.lds_bytes = (uint32_t)((((p.tile_windows - 1) * s + w + 3 + 3) / 4 + 1) * 4);
     }
+    return p;
+}
+
+WsPlan plan_window_scan(const uint8_t *in, uint64_t len, uint32_t w, uint32_t s, int kind) {
+    (void)in;
+    WsPlan p = plan_common(w, s, kind);
+    p.nwin = (w == 0 || s == 0 || len < w) ? 0 : (len - w) / s + 1;
     p.n_tiles = p.nwin ? (p.nwin + p.tile_windows - 1) / p.tile_windows : 0;
     return p;
 }
 
-hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
-                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                    hipStream_t st) {
-    if (p.n_tiles == 0) return hipSuccess;
-    WsScratch sc = carve(p, scratch);
+WsPlan plan_window_scan_files(uint64_t n_tiles, uint64_t total_windows, uint32_t w, uint32_t s, int kind) {
+    WsPlan p = plan_common(w, s, kind);
+    p.nwin = total_windows;
+    p.n_tiles = n_tiles;
+    return p;
+}
+
+template <class Src>
+static hipError_t launch_tiles(const WsPlan &p, Src src, uint32_t w, uint32_t s, uint32_t mask, uint32_t target,
+                               const WsScratch &sc, hipStream_t st) {
     const dim3 grid((unsigned)p.n_tiles), blk(WS_TPB);
     if (p.variant == 1) {
-        ws_reg_count<20, 1><<<grid, blk, 0, st>>>(in, len, p.nwin, mask, target, sc.tile_count, sc.bucket);
+        ws_reg_count<20, 1, Src><<<grid, blk, 0, st>>>(src, mask, target, sc.tile_count, sc.bucket);
     } else if (p.variant == 2) {
-        ws_reg_count<20, 4><<<grid, blk, 0, st>>>(in, len, p.nwin, mask, target, sc.tile_count, sc.bucket);
+        ws_reg_count<20, 4, Src><<<grid, blk, 0, st>>>(src, mask, target, sc.tile_count, sc.bucket);
+    } else if (p.kind == KIND_MD5) {
+        ws_gen_count<KIND_MD5, Src><<<grid, blk, p.lds_bytes, st>>>(src, p.tile_windows, w, s, mask, target,
+                                                                   sc.tile_count, sc.bucket);
     } else {
-        GenArgs a{in, len, p.nwin, p.tile_windows, w, s, mask, target};
-        if (p.kind == KIND_MD5)
-            ws_gen_count<KIND_MD5><<<grid, blk, p.lds_bytes, st>>>(a, sc.tile_count, sc.bucket);
-        else
-            ws_gen_count<KIND_SHA1><<<grid, blk, p.lds_bytes, st>>>(a, sc.tile_count, sc.bucket);
+        ws_gen_count<KIND_SHA1, Src><<<grid, blk, p.lds_bytes, st>>>(src, p.tile_windows, w, s, mask, target,
+                                                                    sc.tile_count, sc.bucket);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
+                                    hipStream_t st, const WsFiles *files) {
+    if (p.n_tiles == 0) return hipSuccess;
+    WsScratch sc = carve(p, scratch);
+    if (files) return launch_tiles(p, FileSrc{files->arena, files->off, files->len, files->tiles, w, s}, w, s,
+                                   mask, target, sc, st);
+    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows}, w, s, mask, target, sc, st);
 }
 
 hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev, hipStream_t st) {
@@ -453,32 +528,38 @@ hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *t
     return hipGetLastError();
 }
 
-hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
-                                   uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                   uint64_t *out, uint64_t cap, hipStream_t st) {
-    if (p.n_tiles == 0 || cap == 0 || out == nullptr) return hipSuccess;
-    WsScratch sc = carve(p, scratch);
-    ws_gather<<<dim3((unsigned)((p.n_tiles + 255) / 256)), dim3(256), 0, st>>>(
-        sc.tile_count, sc.bucket, sc.tile_off, p.n_tiles, p.tile_windows, s, out, cap);
+template <class Src>
+static hipError_t launch_emit(const WsPlan &p, Src src, uint32_t w, uint32_t s, uint32_t mask, uint32_t target,
+                              const WsScratch &sc, uint64_t *out, uint64_t cap, hipStream_t st) {
+    ws_gather<Src><<<dim3((unsigned)((p.n_tiles + 255) / 256)), dim3(256), 0, st>>>(
+        src, sc.tile_count, sc.bucket, sc.tile_off, p.n_tiles, s, out, cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned dgrid = (unsigned)(p.n_tiles < 1024 ? p.n_tiles : 1024);
     if (p.variant == 1) {
-        ws_reg_direct<20, 1><<<dgrid, WS_TPB, 0, st>>>(in, len, p.nwin, mask, target, sc.ovf_list,
-                                                      sc.ovf_count, sc.tile_off, out, cap);
+        ws_reg_direct<20, 1, Src><<<dgrid, WS_TPB, 0, st>>>(src, mask, target, sc.ovf_list, sc.ovf_count,
+                                                           sc.tile_off, out, cap);
     } else if (p.variant == 2) {
-        ws_reg_direct<20, 4><<<dgrid, WS_TPB, 0, st>>>(in, len, p.nwin, mask, target, sc.ovf_list,
-                                                      sc.ovf_count, sc.tile_off, out, cap);
+        ws_reg_direct<20, 4, Src><<<dgrid, WS_TPB, 0, st>>>(src, mask, target, sc.ovf_list, sc.ovf_count,
+                                                           sc.tile_off, out, cap);
+    } else if (p.kind == KIND_MD5) {
+        ws_gen_direct<KIND_MD5, Src><<<dgrid, WS_TPB, p.lds_bytes, st>>>(
+            src, p.tile_windows, w, s, mask, target, sc.ovf_list, sc.ovf_count, sc.tile_off, out, cap);
     } else {
-        GenArgs a{in, len, p.nwin, p.tile_windows, w, s, mask, target};
-        if (p.kind == KIND_MD5)
-            ws_gen_direct<KIND_MD5><<<dgrid, WS_TPB, p.lds_bytes, st>>>(a, sc.ovf_list, sc.ovf_count,
-                                                                       sc.tile_off, out, cap);
-        else
-            ws_gen_direct<KIND_SHA1><<<dgrid, WS_TPB, p.lds_bytes, st>>>(a, sc.ovf_list, sc.ovf_count,
-                                                                        sc.tile_off, out, cap);
+        ws_gen_direct<KIND_SHA1, Src><<<dgrid, WS_TPB, p.lds_bytes, st>>>(
+            src, p.tile_windows, w, s, mask, target, sc.ovf_list, sc.ovf_count, sc.tile_off, out, cap);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+                                   uint32_t s, uint32_t mask, uint32_t target, void *scratch,
+                                   uint64_t *out, uint64_t cap, hipStream_t st, const WsFiles *files) {
+    if (p.n_tiles == 0 || cap == 0 || out == nullptr) return hipSuccess;
+    WsScratch sc = carve(p, scratch);
+    if (files) return launch_emit(p, FileSrc{files->arena, files->off, files->len, files->tiles, w, s}, w, s,
+                                  mask, target, sc, out, cap, st);
+    return launch_emit(p, SingleSrc{in, len, p.nwin, p.tile_windows}, w, s, mask, target, sc, out, cap, st);
 }
 
 }  // namespace hg

@@ -43,6 +43,16 @@ class hg_block_job(ctypes.Structure):
                 ("root_out", _vp), ("digest", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class hg_batch_params(ctypes.Structure):
+    _fields_ = [("block_size", _u64), ("block_digest", ctypes.c_int32), ("roots", ctypes.c_int32),
+                ("chunk", hg_chunk_params), ("max_candidates", _u64)]
+
+
+class hg_batch_out(ctypes.Structure):
+    _fields_ = [("leaf_digests", _vp), ("roots", _vp), ("chunk_ends", _vp), ("chunk_digests", _vp),
+                ("chunk_off", _vp), ("status", _vp)]
+
+
 def _declare(name, restype, argtypes):
     fn = getattr(_lib, name)
     fn.restype = restype
@@ -67,6 +77,15 @@ hg_similarity = _declare("hg_similarity", _int,
 hg_leaves_batch = _declare("hg_leaves_batch", _int, [_vp, _vp, _u32, _u32, _vp])
 hg_roots_batch = _declare("hg_roots_batch", _int, [_vp, _vp, _u32, _u32, _vp])
 hg_block_hash_batch = _declare("hg_block_hash_batch", _int, [_vp, _vp, _u32, _u32, _vp])
+hg_batch_create = _declare("hg_batch_create", _int,
+                           [_vp, _vp, _vp, _u32, ctypes.POINTER(hg_batch_params), ctypes.POINTER(_vp)])
+hg_batch_destroy = _declare("hg_batch_destroy", None, [_vp])
+hg_batch_layout = _declare("hg_batch_layout", _int, [_vp, _vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)])
+hg_batch_run = _declare("hg_batch_run", _int, [_vp, _vp, ctypes.POINTER(hg_batch_out), _vp])
+hg_batch_capture = _declare("hg_batch_capture", _int, [_vp, _vp, ctypes.POINTER(hg_batch_out), _vp])
+hg_batch_replay = _declare("hg_batch_replay", _int, [_vp, _vp])
+hg_batch_tune = _declare("hg_batch_tune", _int,
+                         [_vp, _vp, ctypes.POINTER(hg_batch_out), _vp, ctypes.c_char_p, ctypes.c_size_t])
 hg_timing_enable = _declare("hg_timing_enable", _int, [_vp, _int])
 hg_timing_read = _declare("hg_timing_read", _int,
                           [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
@@ -78,7 +97,9 @@ HG_K = {"leaves": 0, "root": 1, "window_tiles": 2, "window_emit": 3, "chunk_sele
 EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_digest_size",
             "hg_host_alloc", "hg_host_free", "hg_block_hash", "hg_window_scan", "hg_chunk",
             "hg_similarity", "hg_leaves_batch", "hg_roots_batch", "hg_block_hash_batch",
-            "hg_timing_enable", "hg_timing_read", "hg_timing_reset"]
+            "hg_timing_enable", "hg_timing_read", "hg_timing_reset", "hg_batch_create",
+            "hg_batch_destroy", "hg_batch_layout", "hg_batch_run", "hg_batch_capture",
+            "hg_batch_replay", "hg_batch_tune"]
 
 
 class HashGpuError(RuntimeError):
@@ -311,3 +332,77 @@ class Context:
             return None
         r = res.cpu()
         return int(r[0]), int(r[1])
+
+
+class Batch:
+    """A planned hg_batch over files of one arena, with its output tensors.
+
+    offsets/lengths: host integer sequences (bytes within the arena).  The
+    outputs live in CUDA tensors: ``leaves`` (n_leaves, d), ``roots`` (n, d),
+    ``chunk_ends`` (max_chunks,) int64, ``chunk_digests`` (max_chunks, d2),
+    ``chunk_off`` (n + 1,) int64, ``status`` (4,) int64.
+    """
+
+    def __init__(self, ctx: Context, offsets, lengths, block_size: int = 64 * 1024,
+                 block_digest: int = HG_SHA1, roots: bool = True, window: int = 20, stride: int = 1,
+                 mask: int = 0xFFF, target: int = 0, min_chunk: int = 2048,
+                 window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
+                 max_candidates: int = 0):
+        torch = _torch()
+        import numpy as np
+        self.ctx = ctx
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        ln = np.ascontiguousarray(lengths, dtype=np.uint64)
+        self.n = int(off.size)
+        p = hg_batch_params(block_size, block_digest, 1 if roots else 0,
+                            hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest,
+                                            chunk_digest), max_candidates)
+        h = _vp()
+        ctx._check(hg_batch_create(ctx.handle, off.ctypes.data if self.n else None,
+                                   ln.ctypes.data if self.n else None, self.n, ctypes.byref(p),
+                                   ctypes.byref(h)))
+        self.handle = h
+        lf = np.zeros(self.n + 1, dtype=np.uint64)
+        nl, mc = _u64(0), _u64(0)
+        hg_batch_layout(h, lf.ctypes.data, ctypes.byref(nl), ctypes.byref(mc))
+        self.leaf_first = lf
+        self.n_leaves, self.max_chunks = int(nl.value), int(mc.value)
+        dev = torch.device("cuda", ctx.device)
+        d1, d2 = DIGEST_SIZE[block_digest], DIGEST_SIZE[chunk_digest]
+        self.leaves = torch.zeros((max(self.n_leaves, 1), d1), dtype=torch.uint8, device=dev)
+        self.roots = torch.zeros((max(self.n, 1), d1), dtype=torch.uint8, device=dev)
+        self.chunk_ends = torch.zeros(max(self.max_chunks, 1), dtype=torch.int64, device=dev)
+        self.chunk_digests = torch.zeros((max(self.max_chunks, 1), d2), dtype=torch.uint8, device=dev)
+        self.chunk_off = torch.zeros(self.n + 1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(4, dtype=torch.int64, device=dev)
+        self._out = hg_batch_out(self.leaves.data_ptr(), self.roots.data_ptr() if roots else None,
+                                 self.chunk_ends.data_ptr(), self.chunk_digests.data_ptr(),
+                                 self.chunk_off.data_ptr(), self.status.data_ptr())
+
+    def close(self):
+        if self.handle:
+            hg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, arena, stream=None):
+        self.ctx._check(hg_batch_run(self.handle, arena.data_ptr(), ctypes.byref(self._out),
+                                     _stream_handle(stream)))
+
+    def capture(self, arena, stream):
+        self.ctx._check(hg_batch_capture(self.handle, arena.data_ptr(), ctypes.byref(self._out),
+                                         _stream_handle(stream)))
+
+    def replay(self, stream=None):
+        self.ctx._check(hg_batch_replay(self.handle, _stream_handle(stream)))
+
+    def tune(self, arena, stream=None) -> str:
+        buf = ctypes.create_string_buffer(2048)
+        self.ctx._check(hg_batch_tune(self.handle, arena.data_ptr(), ctypes.byref(self._out),
+                                      _stream_handle(stream), buf, 2048))
+        return buf.value.decode()
