@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=32)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-file batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run one 1 GiB device copy (counter calibration) and one window scan "
                          "of the workload, then exit (for rocprofv3 --pmc)")
@@ -277,6 +280,151 @@ def breakdown(torch, hg, data, host_pinned):
     return res
 
 
+def timed_ms(torch, fn, reps=5, stream=None):
+    """Median GPU time (ms) of fn() on `stream` (torch's current by default)."""
+    s = stream or torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def batched(torch, hg, inputs, data):
+    """4096 files of log-normal sizes (median 256 KiB, sigma 1.5, cap
+    64 MiB, seed 5) in one arena: 64 KiB-segment SHA-1 direct hash and
+    content-based chunking of every file, as one captured graph, schedule
+    from the autotuner.  Reference: the same two passes over the 1 GiB
+    buffer as single calls (direct hash, then chunking)."""
+    arena_np, off, ln = inputs.file_batch(5, 4096)
+    arena = torch.from_numpy(arena_np).cuda()
+    total = int(arena_np.size)
+    del arena_np
+    ctx = hg.Context(0)
+    b = hg.Batch(ctx, off, ln)
+    s = torch.cuda.Stream()
+    report = b.tune(arena, s)
+    b.capture(arena, s)
+    ms = timed_ms(torch, lambda: [b.replay(s) for _ in range(5)], reps=3, stream=s) / 5
+    st = b.status.cpu().tolist()
+    t_hash = timed_ms(torch, lambda: ctx.block_hash(data, 64 * KiB, hg.HG_SHA1))
+    t_chunk = timed_ms(torch, lambda: ctx.chunk(data, 20, 1, 0xFFF, 0, 2 * KiB), reps=3)
+    single = data.numel() / (t_hash + t_chunk) / 1e6
+    rate = total / ms / 1e6
+    b.close()
+    ctx.close()
+    del arena
+    return {"files": 4096, "bytes": total, "ms_per_batch": round(ms, 3), "GBps": round(rate, 1),
+            "single_buffer_GBps": round(single, 1), "ratio_vs_single": round(rate / single, 3),
+            "chunks": int(st[1]), "candidates": int(st[0]), "tuner": report}
+
+
+def serving(torch, hg, inputs, data, host_pinned, n_req):
+    """The serving loop under the request stream (seed 6): log-normal sizes
+    4 KiB-256 MiB (median 1 MiB, sigma 1.85), mix 50% block SHA-1 / 30% block
+    MD5 (64 KiB segments + second level) / 20% chunking (w = 20, stride 1,
+    low 12 bits, min 2 KiB, SHA-1 chunk digests); payloads are slices of
+    the 1 GiB input at seeded offsets.  Peak = all requests at once;
+    load points at 10-90% of that peak with Poisson arrivals; latency =
+    completion minus arrival.  Co-runner: an fp32 4096x4096 GEMM loop on
+    its own stream."""
+    import threading
+    import numpy as np
+    arr1, sizes, kinds = inputs.request_stream(6, n_req, 1.0)
+    rng = np.random.default_rng(6 + 1000)
+    offs = np.array([int(rng.integers(0, data.numel() - int(z) + 1)) for z in sizes])
+    specs = list(zip(kinds.tolist(), offs.tolist(), sizes.tolist()))
+    total = float(sizes.sum())
+    mean = total / n_req
+    rs = hg.RequestSet(data.data_ptr(), True, specs)
+    srv = hg.Server(0, slots=3, max_requests=1024, device_budget=4 * GiB, max_group_bytes=1 * GiB)
+    zeros = np.zeros(n_req)
+    srv.play(rs, zeros)  # warm-up: every group's buffers touched once
+
+    def burst(reqs):
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        _, sts = srv.play(reqs, zeros)
+        wall = time.perf_counter() - t0
+        assert (sts == 0).all(), "serving errors"
+        return total / wall / 1e9, srv.stats()
+
+    peak, st = burst(rs)
+    res = {"requests": n_req, "bytes": int(total), "mean_request_bytes": int(mean),
+           "peak_GBps": round(peak, 1), "peak_groups": int(st["groups"]), "loads": []}
+
+    def at_load(load, reqs=rs):
+        rate = load * peak * 1e9 / mean
+        arr = arr1 / rate
+        srv.reset_stats()
+        t0 = time.perf_counter()
+        lat, sts = srv.play(reqs, arr)
+        wall = time.perf_counter() - t0
+        assert (sts == 0).all(), "serving errors"
+        g = srv.stats()["groups"]
+        return {"load": load, "offered_GBps": round(load * peak, 1), "served_GBps": round(total / wall / 1e9, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "groups": int(g)}
+
+    for load in (0.1, 0.3, 0.5, 0.7, 0.9):
+        res["loads"].append(at_load(load))
+    # Single-buffer reference for the same byte mix: each primitive alone
+    # over the whole 1 GiB input.
+    ctx = hg.Context(0)
+    t = {0: timed_ms(torch, lambda: ctx.block_hash(data, 64 * KiB, hg.HG_SHA1)),
+         1: timed_ms(torch, lambda: ctx.block_hash(data, 64 * KiB, hg.HG_MD5)),
+         2: timed_ms(torch, lambda: ctx.chunk(data, 20, 1, 0xFFF, 0, 2 * KiB), reps=3)}
+    ctx.close()
+    by_kind = {k: float(sizes[kinds == k].sum()) for k in (0, 1, 2)}
+    single_s = sum(by_kind[k] / data.numel() * t[k] / 1e3 for k in (0, 1, 2))
+    single = total / single_s / 1e9
+    res["single_buffer_GBps"] = round(single, 1)
+    res["peak_ratio_vs_single"] = round(peak / single, 3)
+    # Host payloads (pinned): staging copy included.
+    rs_h = hg.RequestSet(host_pinned.data_ptr(), False, specs)
+    peak_h, _ = burst(rs_h)
+    res["with_h2d"] = {"peak_GBps": round(peak_h, 1), "load_0.5": at_load(0.5, rs_h)}
+    # GEMM co-runner: fp32 4096^2 matmuls on their own stream, alone and
+    # while the server runs the 50% load point.
+    gs = torch.cuda.Stream()
+    a = torch.randn(4096, 4096, device="cuda")
+    bm = torch.randn(4096, 4096, device="cuda")
+    c = torch.empty(4096, 4096, device="cuda")
+
+    def gemms(k):
+        with torch.cuda.stream(gs):
+            for _ in range(k):
+                torch.matmul(a, bm, out=c)
+
+    t_alone = timed_ms(torch, lambda: gemms(20), reps=3, stream=gs) / 20
+    out = {}
+    th = threading.Thread(target=lambda: out.update(r=at_load(0.5)))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(gs)
+    th.start()
+    k = 0
+    while th.is_alive() or k == 0:
+        gemms(4)
+        k += 4
+        gs.synchronize()
+    e1.record(gs)
+    th.join()
+    torch.cuda.synchronize()
+    t_with = e0.elapsed_time(e1) / k
+    res["corunner"] = {"gemm": "fp32 4096x4096x4096 (torch.matmul), own stream",
+                       "gemm_ms_alone": round(t_alone, 3), "gemm_ms_with_serving": round(t_with, 3),
+                       "gemm_slowdown": round(t_with / t_alone - 1.0, 3), "gemms": k,
+                       "serving_at_0.5_with_gemm": out.get("r")}
+    srv.close()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -362,11 +510,19 @@ def main():
                      "traffic": recorded_traffic(), "avg_launch_ms": round(avg_ms, 4), "launches": nwt,
                      "ops_per_window": WINDOW_OPS},
     }
+    host_pinned = None
+    if not args.no_breakdown or not args.no_serving:
+        host_pinned = torch.from_numpy(data_np).pin_memory()
     if not args.no_breakdown:
         print("[bench] per-primitive breakdown", file=sys.stderr, flush=True)
-        host_pinned = torch.from_numpy(data_np).pin_memory()
         line["breakdown"] = breakdown(torch, hg, data, host_pinned)
-        del host_pinned
+    if not args.no_batched:
+        print("[bench] batched files (4096, one captured graph)", file=sys.stderr, flush=True)
+        line["batched"] = batched(torch, hg, inputs, data)
+    if not args.no_serving:
+        print(f"[bench] serving loop ({args.serve_requests} requests per point)", file=sys.stderr, flush=True)
+        line["serving"] = serving(torch, hg, inputs, data, host_pinned, args.serve_requests)
+    del host_pinned
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(data_np, prev_np, args.cpu_sample_mib)

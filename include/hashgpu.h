@@ -276,6 +276,115 @@ int hg_batch_replay(hg_batch *b, void *stream);
 int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream, char *report,
                   size_t report_len);
 
+/* ------------------------------------------------------------- serving -- */
+
+/* A serving loop for hash requests (the job lifecycle of the paper's
+ * CrystalGPU layer, Sec. 3.2.3: jobs are handed to an outstanding queue, run
+ * on the GPU with buffers allocated once and reused, and reported by
+ * callback; Sec. 3.1: batching and overlap of transfers with work).
+ *
+ * Continuous batching: `slots` workers each own a stream pair and a
+ * pre-allocated group (job table, segment and chunk scratch, pinned output
+ * buffer).  A worker that becomes idle takes the waiting requests from the
+ * head of the queue, in arrival order, while they fit its group and the
+ * device staging budget, and runs them as one group: one persistent launch
+ * for the segment digests of all its block requests, the second levels in
+ * one launch, and the sliding-window chunking of all its chunk requests
+ * through one tile map.  Groups of different workers overlap on the device;
+ * a request that arrives while groups run joins the next group that frees
+ * up, without waiting for the others to drain.
+ *
+ * Admission by device memory: a payload in host memory is admitted only
+ * when its bytes fit the staging region (device_budget bytes, allocated once
+ * at start and carved first-fit); it is copied there on the worker's stream
+ * and its bytes return to the region when the request completes.  A payload
+ * in device memory (HG_IN_DEVICE) takes no staging bytes.
+ *
+ * Each request's results are those of the single call of its primitive
+ * (hg_block_hash with its block size and digest, or hg_chunk with its
+ * parameters), bit for bit.  Outputs are host memory. */
+typedef struct hg_server hg_server;
+
+enum { HG_REQ_BLOCK = 0, HG_REQ_CHUNK = 1 };
+
+/* Request flag for tests of failure handling: the worker fails the request
+ * with HG_EDEVICE at its staging step, before any of its work is enqueued;
+ * the other requests of its group are served normally. */
+enum { HG_REQ_FAIL_INJECT = 1u << 8 };
+
+typedef struct {
+    int32_t kind;           /* HG_REQ_BLOCK or HG_REQ_CHUNK */
+    uint32_t flags;         /* HG_IN_DEVICE (payload in device memory), HG_REQ_FAIL_INJECT */
+    const void *payload;    /* len bytes (may be NULL when len is 0) */
+    uint64_t len;
+    /* HG_REQ_BLOCK: the direct hash (hg_block_hash) */
+    uint64_t block_size;    /* segment size B >= 1 */
+    int32_t digest;         /* HG_MD5 or HG_SHA1 */
+    int32_t reserved;
+    void *leaf_out;         /* ceil(len / B) digests, or NULL */
+    void *root_out;         /* one digest, or NULL (not both NULL) */
+    /* HG_REQ_CHUNK: content-based chunking (hg_chunk) */
+    hg_chunk_params chunk;
+    uint64_t *chunk_ends;   /* capacity entries (may be NULL when capacity is 0) */
+    uint64_t capacity;
+    uint64_t *n_chunks;     /* one word: the full number of chunks */
+    void *chunk_digests;    /* capacity digests, or NULL */
+} hg_request;
+
+typedef struct {
+    uint32_t slots;           /* workers (groups in flight), 1..64 */
+    uint32_t max_requests;    /* requests per group, >= 1 */
+    uint64_t device_budget;   /* staging bytes for host payloads, >= 1 */
+    uint64_t max_group_bytes; /* payload bytes per group, >= 1 MiB; a larger request runs alone */
+    uint32_t flags;           /* HG_BACKGROUND: no raised issue priority for long segments */
+    uint32_t reserved;
+} hg_server_cfg;
+
+typedef struct {
+    uint64_t submitted, completed, failed; /* failed: status other than HG_OK and HG_ETRUNC */
+    uint64_t bytes;                        /* payload bytes of completed requests */
+    uint64_t groups;                       /* groups run */
+    uint64_t queued;                       /* waiting now */
+    uint32_t in_flight, max_in_flight;     /* requests admitted and not completed */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency submit -> completion, completed requests */
+} hg_server_stats;
+
+/* Starts the workers on `device`; allocates every group and the staging
+ * region now (HG_ENOMEM if that fails).  Streams are created with default
+ * priority. */
+int hg_server_start(int device, const hg_server_cfg *cfg, hg_server **out);
+
+/* Queues a copy of *req (the payload and output buffers are not copied: the
+ * caller keeps them alive until completion).  Thread-safe.  *id receives the
+ * request id.  With a callback, cb(id, status, user) runs on a worker thread
+ * after the outputs are written, and the request is released after it; the
+ * caller must not hg_wait on it.  Without a callback the caller must
+ * hg_wait on the id.  HG_EINVAL for a malformed request, HG_EBUSY when the
+ * server is stopping or a host payload exceeds device_budget (it could never
+ * be admitted). */
+int hg_submit(hg_server *s, const hg_request *req, void (*cb)(uint64_t id, int status, void *user), void *user,
+              uint64_t *id);
+
+/* Waits for request `id` (timeout_ms < 0: no limit) and releases it;
+ * *status receives its status (HG_OK, HG_ETRUNC when the chunk capacity was
+ * too small, or the failure).  Returns HG_EBUSY on timeout (the request
+ * stays), HG_EINVAL for an unknown id. */
+int hg_wait(hg_server *s, uint64_t id, int timeout_ms, int *status);
+
+/* Load replay: submits req[i] at start + arrival_s[i] (arrival_s ascending,
+ * seconds) from a native submitter thread, waits for all, and writes each
+ * request's latency (completion minus its scheduled arrival, ms) and status.
+ * The arrival schedule is kept even when the server falls behind. */
+int hg_server_play(hg_server *s, const hg_request *req, const double *arrival_s, uint64_t n, double *latency_ms,
+                   int32_t *status);
+
+int hg_server_stats_read(hg_server *s, hg_server_stats *out);
+int hg_server_stats_reset(hg_server *s);
+
+/* Stops admitting, serves every queued request, joins the workers and frees
+ * everything.  Requests not yet waited for are released. */
+int hg_server_stop(hg_server *s);
+
 /* ------------------------------------------------------ kernel timing -- */
 
 /* Kernel classes for the timing counters. */

@@ -386,8 +386,12 @@ __global__ __launch_bounds__(256) void segment_digest_kernel(const uint8_t *__re
     if (t >= *n_dev) return;
     const uint64_t j = order[t];
     const uint64_t s0 = seg_start(starts, ends, j);
+    // Without explicit starts the segments tile [0, len) of one buffer and a
+    // tail may be loaded as a whole block below in + len; with explicit
+    // starts (files of an arena) only the segment's own bytes are read.
+    const uint8_t *buf_end = starts ? in + ends[j] : in + len;
     uint32_t st[5];
-    hash_range<KIND>(in + s0, ends[j] - s0, in + len, st);
+    hash_range<KIND>(in + s0, ends[j] - s0, buf_end, st);
     store_digest<KIND>(out + j * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 

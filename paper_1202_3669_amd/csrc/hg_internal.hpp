@@ -92,8 +92,10 @@ hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_
 
 // Digest of every segment j < *n_dev <= max_n, into out + j*digest_size.
 // Segment j is [starts[j], ends[j]) when starts is given, else
-// [ends[j-1], ends[j]) with ends[-1] = 0 (offsets relative to in).  Scratch
-// is segment_digest_scratch_bytes(max_n).
+// [ends[j-1], ends[j]) with ends[-1] = 0 (offsets relative to in, taken
+// modulo 2^64).  Without starts, reads stay below in + len; with starts,
+// each segment reads only its own bytes (len is then unused).  Scratch is
+// segment_digest_scratch_bytes(max_n).
 size_t segment_digest_scratch_bytes(uint64_t max_n);
 hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *starts,
                                   const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,

@@ -53,6 +53,32 @@ class hg_batch_out(ctypes.Structure):
                 ("chunk_off", _vp), ("status", _vp)]
 
 
+HG_REQ_BLOCK, HG_REQ_CHUNK = 0, 1
+HG_REQ_FAIL_INJECT = 1 << 8
+
+
+class hg_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("flags", _u32), ("payload", _vp), ("len", _u64),
+                ("block_size", _u64), ("digest", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("leaf_out", _vp), ("root_out", _vp), ("chunk", hg_chunk_params),
+                ("chunk_ends", _vp), ("capacity", _u64), ("n_chunks", _vp), ("chunk_digests", _vp)]
+
+
+class hg_server_cfg(ctypes.Structure):
+    _fields_ = [("slots", _u32), ("max_requests", _u32), ("device_budget", _u64),
+                ("max_group_bytes", _u64), ("flags", _u32), ("reserved", _u32)]
+
+
+class hg_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("failed", _u64), ("bytes", _u64),
+                ("groups", _u64), ("queued", _u64), ("in_flight", _u32), ("max_in_flight", _u32),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
+HG_SERVER_CB = ctypes.CFUNCTYPE(None, _u64, ctypes.c_int, _vp)
+
+
 def _declare(name, restype, argtypes):
     fn = getattr(_lib, name)
     fn.restype = restype
@@ -90,6 +116,14 @@ hg_timing_enable = _declare("hg_timing_enable", _int, [_vp, _int])
 hg_timing_read = _declare("hg_timing_read", _int,
                           [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
 hg_timing_reset = _declare("hg_timing_reset", _int, [_vp])
+hg_server_start = _declare("hg_server_start", _int, [_int, ctypes.POINTER(hg_server_cfg), ctypes.POINTER(_vp)])
+hg_submit = _declare("hg_submit", _int,
+                     [_vp, ctypes.POINTER(hg_request), HG_SERVER_CB, _vp, ctypes.POINTER(_u64)])
+hg_wait = _declare("hg_wait", _int, [_vp, _u64, _int, ctypes.POINTER(_int)])
+hg_server_play = _declare("hg_server_play", _int, [_vp, _vp, _vp, _u64, _vp, _vp])
+hg_server_stats_read = _declare("hg_server_stats_read", _int, [_vp, ctypes.POINTER(hg_server_stats)])
+hg_server_stats_reset = _declare("hg_server_stats_reset", _int, [_vp])
+hg_server_stop = _declare("hg_server_stop", _int, [_vp])
 
 HG_K = {"leaves": 0, "root": 1, "window_tiles": 2, "window_emit": 3, "chunk_select": 4,
         "chunk_digests": 5, "similarity": 6, "leaves_batch": 7, "roots_batch": 8}
@@ -99,7 +133,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_similarity", "hg_leaves_batch", "hg_roots_batch", "hg_block_hash_batch",
             "hg_timing_enable", "hg_timing_read", "hg_timing_reset", "hg_batch_create",
             "hg_batch_destroy", "hg_batch_layout", "hg_batch_run", "hg_batch_capture",
-            "hg_batch_replay", "hg_batch_tune"]
+            "hg_batch_replay", "hg_batch_tune", "hg_server_start", "hg_submit", "hg_wait",
+            "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop"]
 
 
 class HashGpuError(RuntimeError):
@@ -406,3 +441,155 @@ class Batch:
         self.ctx._check(hg_batch_tune(self.handle, arena.data_ptr(), ctypes.byref(self._out),
                                       _stream_handle(stream), buf, 2048))
         return buf.value.decode()
+
+
+class Server:
+    """An hg_server (continuous-batching serving loop) on one device."""
+
+    def __init__(self, device: int = 0, slots: int = 3, max_requests: int = 1024,
+                 device_budget: int = 1 << 30, max_group_bytes: int = 512 << 20,
+                 background: bool = False):
+        cfg = hg_server_cfg(slots, max_requests, device_budget, max_group_bytes,
+                            HG_BACKGROUND if background else 0, 0)
+        h = _vp()
+        st = hg_server_start(device, ctypes.byref(cfg), ctypes.byref(h))
+        if st != HG_OK:
+            raise HashGpuError(st, "hg_server_start failed")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            hg_server_stop(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, req: "hg_request") -> int:
+        rid = _u64(0)
+        st = hg_submit(self.handle, ctypes.byref(req), HG_SERVER_CB(), None, ctypes.byref(rid))
+        if st != HG_OK:
+            raise HashGpuError(st, "hg_submit failed")
+        return int(rid.value)
+
+    def wait(self, rid: int, timeout_ms: int = -1) -> int:
+        out = _int(0)
+        st = hg_wait(self.handle, rid, timeout_ms, ctypes.byref(out))
+        if st != HG_OK:
+            raise HashGpuError(st, "hg_wait failed")
+        return int(out.value)
+
+    def play(self, requests: "RequestSet", arrival_s):
+        """Replays requests.reqs at the given arrival times; returns
+        (latency_ms, status) arrays."""
+        import numpy as np
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        n = len(requests)
+        assert arr.size == n
+        lat = np.zeros(n, dtype=np.float64)
+        sts = np.zeros(n, dtype=np.int32)
+        st = hg_server_play(self.handle, ctypes.addressof(requests.reqs) if n else None,
+                            arr.ctypes.data if n else None, n, lat.ctypes.data if n else None,
+                            sts.ctypes.data if n else None)
+        if st != HG_OK:
+            raise HashGpuError(st, "hg_server_play failed")
+        return lat, sts
+
+    def stats(self) -> dict:
+        s = hg_server_stats()
+        hg_server_stats_read(self.handle, ctypes.byref(s))
+        return {k: getattr(s, k) for k, _ in hg_server_stats._fields_}
+
+    def reset_stats(self):
+        hg_server_stats_reset(self.handle)
+
+
+class RequestSet:
+    """Serving requests over slices of one payload pool, with host outputs.
+
+    pool_ptr: address of the pool (device memory when in_device, else host
+    memory, preferably pinned).  specs: sequence of (kind, offset, length),
+    kind 0 = block SHA-1, 1 = block MD5, 2 = chunking (the mix labels of the
+    serving workload).  Block requests use `block_size` and ask for segment
+    digests and the second level; chunk requests use the chunk parameters
+    and a capacity of len // max(min_chunk, 1) + 1 chunks (an upper bound).
+    Outputs: ``leaves[i]``, ``root[i]``, ``ends[i]``/``digests[i]`` (first
+    ``n_chunks[i]`` entries) as numpy views.
+    """
+
+    def __init__(self, pool_ptr: int, in_device: bool, specs, block_size: int = 64 * 1024,
+                 window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
+                 min_chunk: int = 2048, window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
+                 fail=()):
+        import numpy as np
+        specs = [(int(k), int(o), int(n)) for k, o, n in specs]
+        self.specs = specs
+        n = len(specs)
+        self.reqs = (hg_request * max(n, 1))()
+        cp = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
+        self.chunk_params = cp
+        dc = DIGEST_SIZE[chunk_digest]
+        leaf_n, cap = [], []
+        for k, o, ln in specs:
+            leaf_n.append((ln + block_size - 1) // block_size if k != 2 else 0)
+            cap.append(ln // max(min_chunk, 1) + 1 if k == 2 else 0)
+        self._leaf_buf = np.zeros(max(sum(leaf_n) * 20, 1), dtype=np.uint8)
+        self._root_buf = np.zeros((max(n, 1), 20), dtype=np.uint8)
+        self._end_buf = np.zeros(max(sum(cap), 1), dtype=np.uint64)
+        self._dig_buf = np.zeros((max(sum(cap), 1), dc), dtype=np.uint8)
+        self.n_chunks = np.zeros(max(n, 1), dtype=np.uint64)
+        self.leaves, self.root, self.ends, self.digests = [], [], [], []
+        lo = eo = 0
+        fail = set(fail)
+        for i, (k, o, ln) in enumerate(specs):
+            r = self.reqs[i]
+            r.flags = (HG_IN_DEVICE if in_device else 0) | (HG_REQ_FAIL_INJECT if i in fail else 0)
+            r.payload = pool_ptr + o
+            r.len = ln
+            if k in (0, 1):
+                d = 20 if k == 0 else 16
+                r.kind = HG_REQ_BLOCK
+                r.block_size = block_size
+                r.digest = HG_SHA1 if k == 0 else HG_MD5
+                lv = self._leaf_buf[lo:lo + leaf_n[i] * d].reshape(leaf_n[i], d)
+                lo += leaf_n[i] * 20
+                r.leaf_out = lv.ctypes.data if leaf_n[i] else self._leaf_buf.ctypes.data
+                r.root_out = self._root_buf[i].ctypes.data
+                self.leaves.append(lv)
+                self.root.append(self._root_buf[i, :d])
+                self.ends.append(None)
+                self.digests.append(None)
+            else:
+                r.kind = HG_REQ_CHUNK
+                r.chunk = cp
+                c = cap[i]
+                r.chunk_ends = self._end_buf[eo:eo + c].ctypes.data
+                r.capacity = c
+                r.n_chunks = self.n_chunks[i:i + 1].ctypes.data
+                r.chunk_digests = self._dig_buf[eo:eo + c].ctypes.data
+                self.ends.append(self._end_buf[eo:eo + c])
+                self.digests.append(self._dig_buf[eo:eo + c])
+                eo += c
+                self.leaves.append(None)
+                self.root.append(None)
+
+    def __len__(self):
+        return len(self.specs)
+
+    def result(self, i: int):
+        """('block', leaves, root) or ('chunk', ends, digests), copies."""
+        k = self.specs[i][0]
+        if k in (0, 1):
+            return ("block", self.leaves[i].copy(), bytes(self.root[i]))
+        m = int(self.n_chunks[i])
+        return ("chunk", self.ends[i][:m].copy(), self.digests[i][:m].copy())

@@ -68,3 +68,39 @@ def test_create_without_gpu_reports_edevice():
     if r.returncode == 3:
         pytest.skip("a GPU is present")
     assert r.returncode == 0, r.stderr
+
+
+def test_server_argument_checks():
+    from paper_1202_3669_amd import hashgpu as hg
+    h = ctypes.c_void_p()
+    assert hg.hg_server_start(0, None, ctypes.byref(h)) == hg.HG_EINVAL
+    for bad in (hg.hg_server_cfg(0, 16, 1 << 20, 1 << 20, 0, 0),        # no workers
+                hg.hg_server_cfg(2, 0, 1 << 20, 1 << 20, 0, 0),        # no requests per group
+                hg.hg_server_cfg(2, 16, 0, 1 << 20, 0, 0),             # no staging budget
+                hg.hg_server_cfg(2, 16, 1 << 20, 1 << 19, 0, 0),       # group under 1 MiB
+                hg.hg_server_cfg(2, 16, 1 << 20, 1 << 20, 1, 0)):      # unknown flag
+        assert hg.hg_server_start(0, ctypes.byref(bad), ctypes.byref(h)) == hg.HG_EINVAL
+    rid = ctypes.c_uint64(0)
+    req = hg.hg_request()
+    assert hg.hg_submit(None, ctypes.byref(req), hg.HG_SERVER_CB(), None, ctypes.byref(rid)) == hg.HG_EINVAL
+    assert hg.hg_wait(None, 1, 0, None) == hg.HG_EINVAL
+    assert hg.hg_server_play(None, None, None, 0, None, None) == hg.HG_EINVAL
+    assert hg.hg_server_stats_read(None, None) == hg.HG_EINVAL
+    assert hg.hg_server_stats_reset(None) == hg.HG_EINVAL
+    assert hg.hg_server_stop(None) == hg.HG_EINVAL
+
+
+def test_server_start_without_gpu_reports_edevice():
+    code = (
+        "import ctypes, sys\n"
+        "from paper_1202_3669_amd import hashgpu as hg\n"
+        "import torch\n"
+        "if torch.cuda.device_count() > 0: sys.exit(3)\n"
+        "h = ctypes.c_void_p()\n"
+        "cfg = hg.hg_server_cfg(2, 16, 1 << 20, 1 << 20, 0, 0)\n"
+        "sys.exit(0 if hg.hg_server_start(0, ctypes.byref(cfg), ctypes.byref(h)) == hg.HG_EDEVICE else 1)\n"
+    )
+    r = subprocess.run(["python", "-c", code], cwd=ROOT, capture_output=True, text=True)
+    if r.returncode == 3:
+        pytest.skip("a GPU is present")
+    assert r.returncode == 0, r.stderr
