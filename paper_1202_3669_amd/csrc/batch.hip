@@ -156,9 +156,12 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
     uint8_t *out = nullptr;
     int phase = 2;  // 0 data, 1 length block pending, 2 idle, 3 finished
     uint32_t st[5] = {0, 0, 0, 0, 0};
-    // Next full block of the lane's segment, loaded one iteration ahead so
-    // that its latency hides behind the current compression.
-    uint32_t Y[16];
+    // The lane's next full blocks -- two (one 128-byte line when aligned) or
+    // the last one -- loaded an iteration ahead so that their latency hides
+    // behind the current compression.  Lanes read whole lines at once: a
+    // line read in two halves at different times is easily evicted from L2
+    // in between and fetched twice.
+    uint32_t Y[32];
     // Cached job range of the last task for the fast lookup path.
     uint32_t ci = 0;
     unsigned long long cb0 = 1, cb1 = 0;
@@ -194,7 +197,8 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                     done = 0;
                     phase = 0;
                     Hash<KIND>::init(st);
-                    if (n >= 64) load_block(p, Y);
+                    if (n >= 128) load_pair(p, Y);
+                    else if (n >= 64) load_block(p, Y);
                 } else {
                     phase = 3;
                 }
@@ -208,9 +212,10 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
             }
         }
         if (__ballot(phase < 2) == 0) break;
-        // Fast path: every active lane has at least m full blocks left (its
-        // next one already in Y), so m iterations need no tail handling.
-        // Lanes without work do not limit m; a lane in its tail makes m 0.
+        // Fast path: every active lane has at least m full blocks left (the
+        // next two already in Y), so m / 2 pair iterations need no tail
+        // handling.  Lanes without work do not limit m; a lane in its tail
+        // makes m 0.
         {
             const uint64_t fb = phase == 0 ? (n - done) >> 6 : (phase == 1 ? 0 : ~0ull);
             uint64_t m = fb;
@@ -219,21 +224,24 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                 const uint64_t o = __shfl_xor(m, off, 64);
                 m = o < m ? o : m;
             }
-            if (m != ~0ull && m > 0) {
-                for (uint64_t k = 0; k < m; k++) {
-                    uint32_t X[16];
+            const uint64_t m2 = m == ~0ull ? 0 : m >> 1;
+            for (uint64_t k = 0; k < m2; k++) {
+                uint32_t X[32];
 #pragma unroll
-                    for (int i = 0; i < 16; i++) X[i] = Y[i];
-                    if (phase == 0) {
-                        // Prefetch the following block, or reload the
-                        // current one when there is none (harmless).
-                        const uint64_t nb = k + 1 < fb ? done + 64 * (k + 1) : done + 64 * k;
-                        load_block(p + nb, Y);
-                    }
-                    Hash<KIND>::block(st, X);
+                for (int i = 0; i < 32; i++) X[i] = Y[i];
+                if (phase == 0) {
+                    const uint64_t left = fb - 2 * (k + 1);  // full blocks after this pair
+                    const uint8_t *q = p + done + 128 * (k + 1);
+                    if (left >= 2) load_pair(q, Y);
+                    else if (left == 1) load_block(q, Y);
                 }
-                if (phase == 0) done += 64 * m;
+                // Keep the loads ahead of the rounds (the scheduler would
+                // otherwise sink them next to their use).
+                __builtin_amdgcn_sched_barrier(0);
+                Hash<KIND>::block(st, X);
+                Hash<KIND>::block(st, X + 16);
             }
+            if (phase == 0) done += 128 * m2;
         }
         if (phase < 2) {
             uint32_t X[16];
@@ -244,10 +252,16 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                 Hash<KIND>::length_words(X, n * 8u);
                 last = true;
             } else if (n - done >= 64) {
+                // One block from Y; its second block moves down, and the
+                // block after it is loaded behind it.
+                const uint64_t avail = (n - done) >> 6;
 #pragma unroll
-                for (int i = 0; i < 16; i++) X[i] = Y[i];
+                for (int i = 0; i < 16; i++) {
+                    X[i] = Y[i];
+                    Y[i] = Y[i + 16];
+                }
                 done += 64;
-                if (n - done >= 64) load_block(p + done, Y);
+                if (avail >= 3) load_block(p + done + 64, Y + 16);
             } else {
                 const int rem = (int)(n - done);
                 load_tail(p + done, rem, end, X);

@@ -5,16 +5,18 @@
 // buffer is hashed again for the final value.
 //
 // Mapping on gfx950: one lane per segment, 256 lanes per workgroup.  A lane
-// walks its segment 64 bytes at a time with 16-byte vector loads (double
-// buffered) and keeps the chaining state in VGPRs.  The second level is one
-// lane over the digest buffer.
+// walks its segment 128 bytes (one line, two blocks) at a time with 16-byte
+// vector loads, double buffered, and keeps the chaining state in VGPRs; the
+// register budget is held to four waves per SIMD, enough to fill the chip
+// with one lane per 4 KiB segment of 1 GiB.  The second level is one lane
+// over the digest buffer.
 #include "hg_device.hpp"
 #include "hg_internal.hpp"
 
 namespace hg {
 
 template <int KIND>
-__global__ __launch_bounds__(256) void leaf_kernel(const uint8_t *__restrict__ in, uint64_t len,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void leaf_kernel(const uint8_t *__restrict__ in, uint64_t len,
                                                    uint64_t block, uint64_t n_leaves,
                                                    uint8_t *__restrict__ out) {
     uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ 
 }
 
 template <int KIND>
-__global__ __launch_bounds__(256) void segment_digest_kernel(const uint8_t *__restrict__ in, uint64_t len,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void segment_digest_kernel(const uint8_t *__restrict__ in, uint64_t len,
                                                              const uint64_t *__restrict__ starts,
                                                              const uint64_t *__restrict__ ends,
                                                              const uint64_t *__restrict__ n_dev,

@@ -276,38 +276,67 @@ __device__ __forceinline__ void load_block(const uint8_t *p, uint32_t X[16]) {
 }
 
 // Tail of a message: the last n (< 64) bytes at p.  When a whole 64-byte
-// block starting at p lies before buf_end it is loaded and masked (one
-// vector load); otherwise the bytes are read one at a time so that nothing
-// at or past buf_end is touched.
+// block starting at p lies before buf_end it is loaded (one vector load; the
+// caller masks what lies beyond n); otherwise the bytes are read one at a
+// time so that nothing at or past buf_end is touched.
 __device__ __forceinline__ void load_tail(const uint8_t *p, int n, const uint8_t *buf_end,
                                           uint32_t X[16]) {
-    if (p + 64 <= buf_end) load_block(p, X);
-    else load_partial(p, n, X);
+    if (n == 0) {
+        // Nothing to read (a message that ends on a block boundary).
+#pragma unroll
+        for (int j = 0; j < 16; j++) X[j] = 0;
+    } else if (p + 64 <= buf_end) {
+        load_block(p, X);
+    } else {
+        load_partial(p, n, X);
+    }
+}
+
+// 128 bytes (two blocks) from p into X; p may have any alignment.
+__device__ __forceinline__ void load_pair(const uint8_t *p, uint32_t X[32]) {
+    __builtin_memcpy(X, p, 128);
 }
 
 // Hash the n bytes at p with one lane (p: any alignment; buf_end bounds the
-// readable buffer).  The loop double-buffers: block b+1 is in flight while
-// block b is compressed.
+// readable buffer).  Bytes are read in pairs of blocks, i.e. whole 128-byte
+// lines for aligned input: with one lane per segment, the lanes of a wave
+// read 64 different lines at a time, and a line read in two halves at
+// different times is easily evicted from L2 in between and fetched twice.
+// The loop double-buffers: pair q+1 is in flight while pair q is compressed.
 template <int KIND>
 __device__ __forceinline__ void hash_range(const uint8_t *p, uint64_t n, const uint8_t *buf_end,
                                            uint32_t st[5]) {
     Hash<KIND>::init(st);
-    uint64_t full = n >> 6;
-    uint32_t X[16], Y[16];
-    uint64_t b = 0;
-    if (full > 0) load_block(p, X);
-    while (b + 1 < full) {
-        load_block(p + ((b + 1) << 6), Y);
+    const uint64_t full = n >> 6, pairs = full >> 1;
+    uint32_t X[32], Y[32];
+    uint64_t q = 0;
+    if (pairs > 0) load_pair(p, X);
+    while (q + 1 < pairs) {
+        load_pair(p + ((q + 1) << 7), Y);
+        // Keep the loads ahead of the rounds: left alone, the scheduler sinks
+        // them next to their first use to save registers, and their latency
+        // is then exposed.
+        __builtin_amdgcn_sched_barrier(0);
         Hash<KIND>::block(st, X);
-        // Unconditional prefetch (clamped to the last full block) keeps the
-        // loop free of branches and register copies.
-        uint64_t nb = b + 2 < full ? b + 2 : full - 1;
-        load_block(p + (nb << 6), X);
+        Hash<KIND>::block(st, X + 16);
+        // Unconditional prefetch (clamped to the last pair) keeps the loop
+        // free of branches and register copies.
+        const uint64_t nq = q + 2 < pairs ? q + 2 : pairs - 1;
+        load_pair(p + (nq << 7), X);
+        __builtin_amdgcn_sched_barrier(0);
         Hash<KIND>::block(st, Y);
-        b += 2;
+        Hash<KIND>::block(st, Y + 16);
+        q += 2;
     }
-    if (b < full) Hash<KIND>::block(st, X);
-    int rem = (int)(n & 63);
+    if (q < pairs) {
+        Hash<KIND>::block(st, X);
+        Hash<KIND>::block(st, X + 16);
+    }
+    if (full & 1) {
+        load_block(p + ((full - 1) << 6), X);
+        Hash<KIND>::block(st, X);
+    }
+    const int rem = (int)(n & 63);
     load_tail(p + (full << 6), rem, buf_end, X);
     finish_tail<KIND>(st, X, rem, n);
 }
