@@ -18,13 +18,16 @@ Workload (one step = one pass of the whole path over one input):
 Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1): the
 second-level hash of a job is one sequential chain (for 4 KiB SHA-1 segments
 of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
-sequential chains per job.  Short work of each step runs on stream S0; for a
-group of G steps, the 1 MiB segments run as one batched launch on stream S1
-and all second levels as one batched launch on stream S2, while S0 carries
-on with the next group.  A step's latency therefore ends when its group's
-roots are done.  Three streams need three hardware queues: HIP shares its
-default four queues among all streams of the process, so the benchmark asks
-for eight (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
+sequential chains per job.  Per step, chunking runs on stream SA[step % 3]
+(the window scan is the throughput engine; while one stream waits for its
+counts or runs its chunk digests, the others' window scans run) and the 4 KiB / 64 KiB segments on
+stream SB; for a group of G steps, the 1 MiB segments run as one batched
+launch on stream S1 and all second levels as one batched launch on stream
+S2, while the other streams carry on with the next group.  A step's latency
+therefore ends when its group's roots are done.  Five busy streams need as
+many hardware queues: HIP shares its default four queues among all streams
+of the process, so the benchmark asks for eight (GPU_MAX_HW_QUEUES, read
+when the HIP runtime starts).
 
 value = hashed bytes per second: each of the 7 primitive passes (6 direct
 hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
@@ -45,6 +48,19 @@ INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # MD5 steps, 19 with a data word (5 ops) and 42 with a constant word (4 ops).
 WINDOW_OPS = 19 * 5 + 42 * 4
 
+# Algorithmic int32 ops of one 64-byte compression: MD5 64 steps x 5 + 4
+# final additions; SHA-1 80 rounds x 5 + 64 schedule words x 3 + 16 byte
+# swaps + 5 final additions.
+BLOCK_OPS = {0: 324, 1: 613}
+# Chunking streams (steps round-robin), each driven by its own host thread.
+CHUNK_STREAMS = 3
+
+
+def padded_blocks(n):
+    """Compressions of a standard MD5/SHA-1 hash of n bytes (with padding)."""
+    return (n + 8) // 64 + 1
+
+
 # (digest, segment size); within a launch, jobs with the longest sequential
 # chains come first.
 BLOCK_JOBS = [(1, 64 * KiB), (0, 64 * KiB), (1, 4 * KiB), (0, 4 * KiB), (1, MiB), (0, MiB)]
@@ -62,10 +78,13 @@ def parse():
     ap.add_argument("--group", type=int, default=12, help="steps per long-chain batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
-    ap.add_argument("--cpu-sample-mib", type=int, default=32)
+    ap.add_argument("--cpu-sample-mib", type=int, default=128)
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-file batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--leaf-probe", action="store_true",
+                    help="only hash the 1 GiB input with one lane per segment (MD5/SHA-1, 4 KiB and "
+                         "64 KiB segments, 3 launches each, no second level), for counter runs")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run one 1 GiB device copy (counter calibration) and one window scan "
                          "of the workload, then exit (for rocprofv3 --pmc)")
@@ -81,20 +100,28 @@ class Pipeline:
         self.prev = prev_digests
         self.G = group
         self.slots = 2 * group
-        self.s0 = torch.cuda.Stream()
+        # Chunking goes round-robin over CHUNK_STREAMS streams so that one
+        # step's counts, boundary decision and chunk digests overlap other
+        # steps' window scans; the short segment batch has a stream of its
+        # own so that it overlaps the window scans as well.
+        self.NA = CHUNK_STREAMS
+        self.sa = [torch.cuda.Stream() for _ in range(self.NA)]
+        self.sb = torch.cuda.Stream()
         self.s1 = torch.cuda.Stream()
         self.s2 = torch.cuda.Stream()
+        self.ctxa = [hg.Context(0) for _ in range(self.NA)]
         self.ctx0 = hg.Context(0)
         self.ctx1 = hg.Context(0)
         self.ctx2 = hg.Context(0)
         self.ctx3 = hg.Context(0)
         dev = data.device
         n = data.numel()
-        # Chunk outputs (capacity: every chunk but the last is >= 2 KiB).
+        # Chunk outputs per chunking stream (capacity: every chunk but the last is
+        # >= 2 KiB).
         self.cap = n // (2 * KiB) + 1
-        self.ends = torch.empty(self.cap, dtype=torch.int64, device=dev)
-        self.digs = torch.empty((self.cap, 20), dtype=torch.uint8, device=dev)
-        self.nchunks = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ends = [torch.empty(self.cap, dtype=torch.int64, device=dev) for _ in range(self.NA)]
+        self.digs = [torch.empty((self.cap, 20), dtype=torch.uint8, device=dev) for _ in range(self.NA)]
+        self.nchunks = 0
         self.sim = torch.zeros((self.slots, 2), dtype=torch.int64, device=dev)
         # Ring of segment-digest buffers and root outputs, one per slot.
         self.recs = []
@@ -116,6 +143,13 @@ class Pipeline:
             self.late_tables.append(table(self.ctx3, [self.recs[s][0][j] for j in ROOT_LATE for s in slots]))
         self.group_done = {}
         self.issue_ev = {}
+        self.issue_ev_a = {}
+        # One host thread per chunking stream: hg_chunk waits on the host for
+        # its candidate and chunk counts, and those waits must not hold up
+        # the other stream or the rest of the step.
+        from concurrent.futures import ThreadPoolExecutor
+        self.pool = [ThreadPoolExecutor(1) for _ in range(self.NA)]
+        self.futures = []
 
     def _subset(self, slot, idx):
         recs = self.recs[slot][0]
@@ -127,18 +161,26 @@ class Pipeline:
         g = i // self.G
         if i % self.G == 0 and (g - 2) in self.group_done:
             # Slots of group g were last read by group g-2's roots.
-            self.s0.wait_event(self.group_done[g - 2])
+            self.sb.wait_event(self.group_done[g - 2])
         ev = torch.cuda.Event(enable_timing=True)
-        ev.record(self.s0)
+        ev.record(self.sb)
         self.issue_ev[i] = ev
-        with torch.cuda.stream(self.s0):
-            self.ctx0.run_batch(self.short_tables[slot], len(SHORT), "leaves", stream=self.s0)
-            ends, digs = self.ctx0.chunk(self.data, 20, 1, 0xFFF, 0, 2 * KiB, capacity=self.cap,
-                                         stream=self.s0, out=(self.ends, self.digs, self.nchunks))
-            self.ctx0.similarity(self.prev, digs, stream=self.s0, ends_b=ends,
-                                 out=self.sim[slot], asynchronous=True)
+        self.ctx0.run_batch(self.short_tables[slot], len(SHORT), "leaves", stream=self.sb)
+        self.futures.append(self.pool[i % self.NA].submit(self._chunk, i, slot))
         if i % self.G == self.G - 1:
             self.close_group(g)
+
+    def _chunk(self, i, slot):
+        """Chunking and similarity of step i (on its stream's thread)."""
+        p = i % self.NA
+        sa, ca = self.sa[p], self.ctxa[p]
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record(sa)
+        self.issue_ev_a[i] = ev
+        ends, digs = ca.chunk(self.data, 20, 1, 0xFFF, 0, 2 * KiB, stream=sa,
+                              out=(self.ends[p], self.digs[p]), asynchronous=True)
+        ca.similarity(self.prev, digs, stream=sa, ends_b=ends, out=self.sim[slot], asynchronous=True)
+        return ends.numel()
 
     def close_group(self, g):
         """Queue the long chains of group g: the 1 MiB segments on S1, then
@@ -147,7 +189,7 @@ class Pipeline:
         torch = self.torch
         parity = g % 2
         short_done = torch.cuda.Event()
-        short_done.record(self.s0)
+        short_done.record(self.sb)
         self.s1.wait_event(short_done)
         self.s2.wait_event(short_done)
         lt, ln = self.long_tables[parity]
@@ -169,12 +211,16 @@ class Pipeline:
         last = first + count - 1
         if last % self.G != self.G - 1:
             self.close_group(last // self.G)
+        for f in self.futures:
+            self.nchunks = f.result()
+        self.futures.clear()
 
     def latencies_ms(self, first, count):
         out = []
         for i in range(first, first + count):
             done = self.group_done[i // self.G]
-            out.append(self.issue_ev[i].elapsed_time(done))
+            # From the first of the step's launches to its group's last root.
+            out.append(max(self.issue_ev[i].elapsed_time(done), self.issue_ev_a[i].elapsed_time(done)))
         return out
 
 
@@ -455,6 +501,15 @@ def main():
         print(f"[bench] pmc probe done; kernel_source_sha256: {kernel_source_hash()}",
               file=sys.stderr, flush=True)
         return
+    if args.leaf_probe:
+        data = torch.from_numpy(data_np).cuda()
+        with hg.Context(0) as c:
+            for k, _, b in [(0, 0, 4 * KiB), (0, 0, 64 * KiB), (1, 0, 4 * KiB), (1, 0, 64 * KiB)]:
+                for _ in range(3):
+                    c.block_hash(data, b, k, root=False)
+        torch.cuda.synchronize()
+        print("[bench] leaf probe done", file=sys.stderr, flush=True)
+        return
     prev_np, _ = inputs.edited_version(data_np, 3, 1024)
     data = torch.from_numpy(data_np).cuda()
     prev = torch.from_numpy(prev_np).cuda()
@@ -469,8 +524,13 @@ def main():
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     pipe.run(0, args.warmup)
     torch.cuda.synchronize()
-    pipe.ctx0.timing(True)
-    pipe.ctx0.timing_reset()
+    origin = torch.cuda.Event(enable_timing=True)
+    origin.record()
+    torch.cuda.synchronize()
+    for c in pipe.ctxa:
+        c.timing(True)
+        c.timing_reset()
+        c.timing_origin(origin)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -480,16 +540,46 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     lat = pipe.latencies_ms(first, args.steps)
-    nwt, mswt = pipe.ctx0.timing_read("window_tiles")
-    pipe.ctx0.timing(False)
+    nwt, mswt = 0, 0.0
+    starts, finishes = [], []
+    for c in pipe.ctxa:
+        a, b = c.timing_read("window_tiles")
+        nwt, mswt = nwt + a, mswt + b
+        st_, en_ = c.timing_intervals("window_tiles")
+        starts += st_.tolist()
+        finishes += en_.tolist()
+        c.timing(False)
+        c.timing_origin(None)
+    # Launches of the window kernel overlap (one per chunking stream): its
+    # rate is taken over the time at least one launch was running.
+    busy_ms, cur_s, cur_e = 0.0, None, None
+    for a, b in sorted(zip(starts, finishes)):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                busy_ms += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        busy_ms += cur_e - cur_s
     sims = pipe.sim.cpu().tolist()
-    nchunks = int(pipe.nchunks.item())
+    nchunks = pipe.nchunks
+
+    # Whole-step algorithmic int32 work, for the step's ALU roofline.
+    ends_np = pipe.ends[0][:nchunks].cpu().numpy()
+    chunk_lens = np.diff(ends_np, prepend=0)
+    step_ops = (GiB - 20 + 1) * WINDOW_OPS
+    for k, b in BLOCK_JOBS:
+        n_leaves = GiB // b
+        d = 20 if k else 16
+        step_ops += (n_leaves * padded_blocks(b) + padded_blocks(n_leaves * d)) * BLOCK_OPS[k]
+    step_ops += int(((chunk_lens + 8) // 64 + 1).sum()) * BLOCK_OPS[1]
 
     hashed = 7 * GiB * args.steps
     value = hashed / wall / 1e9
     nwin = GiB - 20 + 1
     avg_ms = mswt / max(nwt, 1)
-    achieved = nwin * WINDOW_OPS / (avg_ms / 1e3) / 1e12
+    achieved = nwin * WINDOW_OPS * nwt / (busy_ms / 1e3) / 1e12 if busy_ms > 0 else 0.0
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3),
@@ -506,10 +596,14 @@ def main():
         },
         "input_GBps": round(GiB * args.steps / wall / 1e9, 2),
         "latency_ms": {"step_p50": round(pct(lat, 50), 2), "step_p99": round(pct(lat, 99), 2)},
+        "step_alu": {"ops_per_step": int(step_ops),
+                     "achieved_Tops": round(step_ops / (wall / args.steps) / 1e12, 2),
+                     "frac": round(step_ops / (wall / args.steps) / 1e12 / INT32_PEAK_TOPS, 4)},
         "roofline": {"kernel": "window hash + tile count (MD5 w=20 s=1)", "bound": "alu",
                      "achieved": round(achieved, 2), "peak": round(INT32_PEAK_TOPS, 2),
                      "unit": "Tops/s (int32)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
                      "traffic": recorded_traffic(), "avg_launch_ms": round(avg_ms, 4), "launches": nwt,
+                     "busy_ms": round(busy_ms, 2), "overlap": round(mswt / busy_ms, 2) if busy_ms else None,
                      "ops_per_window": WINDOW_OPS},
     }
     host_pinned = None

@@ -23,10 +23,11 @@
  *     GPU work of the call is ordered on it.
  *   - Synchrony: without HG_ASYNC the call returns when its results are in
  *     the caller's memory.  HG_ASYNC (valid only with HG_IN_DEVICE and
- *     HG_OUT_DEVICE, and only for hg_block_hash, hg_window_scan and
- *     hg_similarity) returns after enqueueing; results are valid once the
- *     stream has completed, and truncation can then only be seen by comparing
- *     the written count with the capacity.
+ *     HG_OUT_DEVICE, and only for hg_block_hash, hg_window_scan,
+ *     hg_similarity and hg_chunk) returns after enqueueing; results are valid
+ *     once the stream has completed, and truncation can then only be seen by
+ *     comparing the written count with the capacity (hg_chunk still waits
+ *     for its counts, see there).
  *   - Ownership: the caller owns every buffer it passes and keeps it alive
  *     until the results are valid; the library retains no caller pointer
  *     after that.  A context owns its device scratch, pinned staging memory
@@ -66,8 +67,15 @@ enum {
 };
 
 /* Flags.  HG_LEN_ENDS applies to hg_similarity only; HG_BACKGROUND to the
- * batch calls only. */
-enum { HG_IN_DEVICE = 1u, HG_OUT_DEVICE = 2u, HG_ASYNC = 4u, HG_LEN_ENDS = 8u, HG_BACKGROUND = 16u };
+ * batch calls only; HG_COUNT_HOST to hg_chunk only. */
+enum {
+    HG_IN_DEVICE = 1u,
+    HG_OUT_DEVICE = 2u,
+    HG_ASYNC = 4u,
+    HG_LEN_ENDS = 8u,
+    HG_BACKGROUND = 16u,
+    HG_COUNT_HOST = 32u
+};
 
 /* Limits of the sliding-window primitive. */
 enum { HG_MAX_WINDOW = 4096 };
@@ -200,7 +208,15 @@ typedef struct {
  *   n_chunks       one uint64: the number of chunks (always the full number).
  *   chunk_digests  capacity * digest_size(chunk_digest) bytes, or NULL.
  * Returns HG_ETRUNC when n_chunks > capacity (outputs hold the first
- * `capacity` chunks).  HG_ASYNC is not accepted. */
+ * `capacity` chunks).
+ * The call waits on the host for two counts it needs to size its launches:
+ * the candidates after the window scan and the chunks after the boundary
+ * decision.  With HG_ASYNC (and HG_IN_DEVICE, HG_OUT_DEVICE) it returns
+ * right after enqueueing the chunk digests and the output copies, so that
+ * the digests can overlap the caller's next work on another stream; the
+ * outputs are valid once the stream has completed.  With HG_COUNT_HOST,
+ * n_chunks is a host pointer (written before the call returns) even when
+ * the other outputs are device pointers. */
 int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *params,
              uint64_t *ends, uint64_t capacity, uint64_t *n_chunks, void *chunk_digests,
              uint32_t flags, void *stream);
@@ -410,6 +426,19 @@ enum {
 int hg_timing_enable(hg_ctx *ctx, int enable);
 int hg_timing_read(hg_ctx *ctx, int kernel_class, uint64_t *launches, double *total_ms);
 int hg_timing_reset(hg_ctx *ctx);
+
+/* Per-launch intervals, for launches that overlap (several streams): after
+ * hg_timing_origin(ctx, event) -- `event` is a hipEvent_t with timing,
+ * already recorded before the launches to be measured and kept alive by the
+ * caller until the reads are done (NULL turns this off) -- every timed
+ * launch also records its start and end in ms after that event.
+ * hg_timing_intervals copies up to `capacity` of them for one kernel class
+ * (launch order) and sets *count to the number recorded since the last
+ * reset (HG_ETRUNC when that exceeds capacity).  Contexts given the same
+ * origin share one time axis, so their intervals can be merged. */
+int hg_timing_origin(hg_ctx *ctx, void *event);
+int hg_timing_intervals(hg_ctx *ctx, int kernel_class, double *start_ms, double *end_ms, uint64_t capacity,
+                        uint64_t *count);
 
 #ifdef __cplusplus
 }

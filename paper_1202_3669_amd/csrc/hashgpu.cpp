@@ -75,6 +75,9 @@ struct hg_ctx {
     std::vector<TimedLaunch> pending;
     uint64_t t_launches[HG_K_COUNT] = {};
     double t_ms[HG_K_COUNT] = {};
+    // With an origin event: every launch's [start, end) in ms after it.
+    hipEvent_t t_origin = nullptr;
+    std::vector<double> t_start[HG_K_COUNT], t_end[HG_K_COUNT];
 };
 
 namespace {
@@ -125,6 +128,13 @@ int resolve_timing(hg_ctx *ctx) {
         HG_HIP(ctx, hipEventElapsedTime(&ms, t.a, t.b));
         ctx->t_launches[t.klass] += 1;
         ctx->t_ms[t.klass] += ms;
+        if (ctx->t_origin) {
+            float a = 0.f, b = 0.f;
+            HG_HIP(ctx, hipEventElapsedTime(&a, ctx->t_origin, t.a));
+            HG_HIP(ctx, hipEventElapsedTime(&b, ctx->t_origin, t.b));
+            ctx->t_start[t.klass].push_back(a);
+            ctx->t_end[t.klass].push_back(b);
+        }
         ctx->ev_pool.push_back(t.a);
         ctx->ev_pool.push_back(t.b);
     }
@@ -589,7 +599,9 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
 int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *pr, uint64_t *ends,
              uint64_t capacity, uint64_t *n_chunks, void *chunk_digests, uint32_t flags, void *stream) {
     HG_TRY(enter(ctx));
-    HG_TRY(check_flags(ctx, flags, false));
+    const bool count_host = flags & HG_COUNT_HOST;
+    flags &= ~(uint32_t)HG_COUNT_HOST;
+    HG_TRY(check_flags(ctx, flags, true));
     if (!pr) return fail(ctx, HG_EINVAL, "params is NULL");
     if (digest_bytes(pr->window_digest) < 0 || digest_bytes(pr->chunk_digest) < 0)
         return fail(ctx, HG_EINVAL, "unknown digest");
@@ -618,10 +630,12 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
     uint64_t n_cand;
     HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
-    void *cand, *dends, *ddig = nullptr;
+    // Chunks <= candidates + 1: the boundary decision writes straight into
+    // the caller's device buffer when it is that large.
+    const bool ends_direct = out_dev && capacity >= n_cand + 1;
+    void *cand, *dends = ends;
     HG_TRY(ensure(ctx, SLOT_CAND, n_cand * 8, st, &cand));
-    HG_TRY(ensure(ctx, SLOT_ENDS, (n_cand + 1) * 8, st, &dends));
-    if (chunk_digests) HG_TRY(ensure(ctx, SLOT_DIG, (n_cand + 1) * (uint64_t)dd, st, &ddig));
+    if (!ends_direct) HG_TRY(ensure(ctx, SLOT_ENDS, (n_cand + 1) * 8, st, &dends));
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
               hg::launch_window_scan_emit(plan, din, len, pr->window, pr->stride, pr->mask, pr->target, ws,
                                           (uint64_t *)cand, n_cand, st));
@@ -630,21 +644,26 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
               hg::launch_chunk_select((const uint64_t *)cand, &small[0], n_cand, pr->window, len,
                                       pr->min_chunk, sel, (uint64_t *)dends, n_cand + 1, &small[1], st));
+    // The chunk count sizes the outputs; the digests are enqueued after it.
+    uint64_t nc;
+    HG_TRY(read_u64(ctx, &small[1], st, &nc));
+    const uint64_t k = std::min(nc, capacity);
+    if (!ends_direct) HG_TRY(copy_out(ctx, ends, dends, k * 8, out_dev, st));
     if (chunk_digests) {
+        // Straight into the caller's device buffer when it holds them all.
+        const bool direct = out_dev && capacity >= nc;
+        void *ddig = chunk_digests;
+        if (!direct) HG_TRY(ensure(ctx, SLOT_DIG, (nc + 1) * (uint64_t)dd, st, &ddig));
         void *segs;
         HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(n_cand + 1), st, &segs));
         HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
                   hg::launch_segment_digests(pr->chunk_digest, din, len, nullptr, (const uint64_t *)dends,
                                              &small[1], n_cand + 1, (uint8_t *)ddig, segs, st));
+        if (!direct) HG_TRY(copy_out(ctx, chunk_digests, ddig, k * (uint64_t)dd, out_dev, st));
     }
-    uint64_t nc;
-    HG_TRY(read_u64(ctx, &small[1], st, &nc));
-    const uint64_t k = std::min(nc, capacity);
-    HG_TRY(copy_out(ctx, ends, dends, k * 8, out_dev, st));
-    if (chunk_digests) HG_TRY(copy_out(ctx, chunk_digests, ddig, k * (uint64_t)dd, out_dev, st));
-    if (out_dev) HG_TRY(copy_out(ctx, n_chunks, &small[1], 8, true, st));
-    HG_HIP(ctx, hipStreamSynchronize(st));
-    if (!out_dev) *n_chunks = nc;
+    if (out_dev && !count_host) HG_TRY(copy_out(ctx, n_chunks, &small[1], 8, true, st));
+    else *n_chunks = nc;
+    if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return nc > capacity ? fail(ctx, HG_ETRUNC, "%llu chunks, capacity %llu", (unsigned long long)nc,
                                 (unsigned long long)capacity)
                          : HG_OK;
@@ -706,8 +725,34 @@ int hg_timing_reset(hg_ctx *ctx) {
     for (int k = 0; k < HG_K_COUNT; k++) {
         ctx->t_launches[k] = 0;
         ctx->t_ms[k] = 0.0;
+        ctx->t_start[k].clear();
+        ctx->t_end[k].clear();
     }
     return HG_OK;
+}
+
+int hg_timing_origin(hg_ctx *ctx, void *event) {
+    if (!ctx) return HG_EINVAL;
+    HG_TRY(resolve_timing(ctx));
+    ctx->t_origin = (hipEvent_t)event;
+    return HG_OK;
+}
+
+int hg_timing_intervals(hg_ctx *ctx, int kernel_class, double *start_ms, double *end_ms, uint64_t capacity,
+                        uint64_t *count) {
+    if (!ctx) return HG_EINVAL;
+    if (kernel_class < 0 || kernel_class >= HG_K_COUNT)
+        return fail(ctx, HG_EINVAL, "unknown kernel class %d", kernel_class);
+    if (!count || (capacity && (!start_ms || !end_ms))) return fail(ctx, HG_EINVAL, "NULL output");
+    HG_TRY(resolve_timing(ctx));
+    const std::vector<double> &a = ctx->t_start[kernel_class], &b = ctx->t_end[kernel_class];
+    *count = a.size();
+    const size_t k = std::min<size_t>(a.size(), capacity);
+    for (size_t i = 0; i < k; i++) {
+        start_ms[i] = a[i];
+        end_ms[i] = b[i];
+    }
+    return a.size() > capacity ? fail(ctx, HG_ETRUNC, "%zu intervals", a.size()) : HG_OK;
 }
 
 }  // extern "C"

@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 HG_MD5, HG_SHA1 = 0, 1
 HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
-HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS, HG_BACKGROUND = 1, 2, 4, 8, 16
+HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS, HG_BACKGROUND, HG_COUNT_HOST = 1, 2, 4, 8, 16, 32
 HG_MAX_WINDOW = 4096
 DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
 
@@ -116,6 +116,8 @@ hg_timing_enable = _declare("hg_timing_enable", _int, [_vp, _int])
 hg_timing_read = _declare("hg_timing_read", _int,
                           [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
 hg_timing_reset = _declare("hg_timing_reset", _int, [_vp])
+hg_timing_origin = _declare("hg_timing_origin", _int, [_vp, _vp])
+hg_timing_intervals = _declare("hg_timing_intervals", _int, [_vp, _int, _vp, _vp, _u64, ctypes.POINTER(_u64)])
 hg_server_start = _declare("hg_server_start", _int, [_int, ctypes.POINTER(hg_server_cfg), ctypes.POINTER(_vp)])
 hg_submit = _declare("hg_submit", _int,
                      [_vp, ctypes.POINTER(hg_request), HG_SERVER_CB, _vp, ctypes.POINTER(_u64)])
@@ -134,7 +136,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_timing_enable", "hg_timing_read", "hg_timing_reset", "hg_batch_create",
             "hg_batch_destroy", "hg_batch_layout", "hg_batch_run", "hg_batch_capture",
             "hg_batch_replay", "hg_batch_tune", "hg_server_start", "hg_submit", "hg_wait",
-            "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop"]
+            "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop",
+            "hg_timing_origin", "hg_timing_intervals"]
 
 
 class HashGpuError(RuntimeError):
@@ -239,43 +242,47 @@ class Context:
 
     def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
               window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
-              capacity: int | None = None, stream=None, out=None):
+              capacity: int | None = None, stream=None, out=None, asynchronous: bool = False):
         """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks.
-        With out = (ends, digests, count) preallocated CUDA tensors (capacity
-        = len(ends)) the results are written there and views returned."""
+        With out = (ends, digests) preallocated CUDA tensors (capacity =
+        len(ends)) the results are written there and views returned; with
+        asynchronous=True as well, the call returns once the chunk digests
+        are enqueued (the views are valid when `stream` has completed)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = data.numel()
         p = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
         d = DIGEST_SIZE[chunk_digest]
+        total = _u64(0)
         if out is not None:
-            ends, dig, cnt = out
-            flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+            ends, dig = out
+            flags = HG_OUT_DEVICE | HG_COUNT_HOST | (HG_IN_DEVICE if data.is_cuda else 0)
+            if asynchronous:
+                flags |= HG_ASYNC
             st = hg_chunk(self.handle, data.data_ptr() if n else None, n, ctypes.byref(p),
-                          ends.data_ptr(), ends.numel(), cnt.data_ptr(),
+                          ends.data_ptr(), ends.numel(), ctypes.addressof(total),
                           dig.data_ptr() if digests else None, flags, _stream_handle(stream))
             self._check(st)
-            total = int(cnt.item())
-            return ends[:total], (dig[:total] if digests else None)
+            k = int(total.value)
+            return ends[:k], (dig[:k] if digests else None)
         if capacity is None:
             nwin = (n - window) // stride + 1 if n >= window else 0
             capacity = 1 + min(nwin, 4096 + nwin // 1024)
             if min_chunk:
                 capacity = min(capacity, n // min_chunk + 1)
-        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
         for _ in range(2):
             ends = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
             dig = torch.empty((max(capacity, 1), d), dtype=torch.uint8, device=dev) if digests else None
-            flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+            flags = HG_OUT_DEVICE | HG_COUNT_HOST | (HG_IN_DEVICE if data.is_cuda else 0)
             st = hg_chunk(self.handle, data.data_ptr() if n else None, n, ctypes.byref(p),
-                          ends.data_ptr(), capacity, cnt.data_ptr(),
+                          ends.data_ptr(), capacity, ctypes.addressof(total),
                           dig.data_ptr() if dig is not None else None, flags,
                           _stream_handle(stream))
             self._check(st, allow_trunc=True)
-            total = int(cnt.item())
-            if total <= capacity:
-                return ends[:total], (dig[:total] if dig is not None else None)
-            capacity = total
+            k = int(total.value)
+            if k <= capacity:
+                return ends[:k], (dig[:k] if dig is not None else None)
+            capacity = k
         raise HashGpuError(HG_ETRUNC, "chunk count changed between calls")
 
     # ------------------------------------------------------------- timing --
@@ -284,6 +291,23 @@ class Context:
 
     def timing_reset(self):
         self._check(hg_timing_reset(self.handle))
+
+    def timing_origin(self, event):
+        """Time axis for timing_intervals: a recorded torch.cuda.Event with
+        timing (kept alive by the caller), or None."""
+        self._check(hg_timing_origin(self.handle, event.cuda_event if event is not None else None))
+
+    def timing_intervals(self, name: str):
+        """(start_ms, end_ms) numpy arrays of the class's launches after the
+        origin event."""
+        import numpy as np
+        k = HG_K[name]
+        n = _u64(0)
+        self._check(hg_timing_intervals(self.handle, k, None, None, 0, ctypes.byref(n)), allow_trunc=True)
+        a = np.zeros(max(int(n.value), 1))
+        b = np.zeros_like(a)
+        self._check(hg_timing_intervals(self.handle, k, a.ctypes.data, b.ctypes.data, a.size, ctypes.byref(n)))
+        return a[:int(n.value)], b[:int(n.value)]
 
     def timing_read(self, name: str):
         """(launches, total_ms) of a kernel class since the last reset."""

@@ -258,6 +258,27 @@ def test_chunk_truncation(ctx, hg):
     assert np.array_equal(host(dg), exp_dig[:5])
 
 
+def test_chunk_async_with_host_count(ctx, hg):
+    data = inputs.uniform_bytes(403, 3 * MiB + 77)
+    exp_ends, exp_dig = _oracle_chunks(data, 20, 1, 0xFFF, 0, 2048)
+    d = dev(data)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    ends = torch.zeros(4096, dtype=torch.int64, device="cuda")
+    dig = torch.zeros((4096, 20), dtype=torch.uint8, device="cuda")
+    note("chunk async, host count")
+    e, g = ctx.chunk(d, 20, 1, 0xFFF, 0, 2048, stream=s, out=(ends, dig), asynchronous=True)
+    s.synchronize()
+    assert np.array_equal(host(e).astype(np.uint64), exp_ends)
+    assert np.array_equal(host(g), exp_dig)
+    n = ctypes.c_uint64(0)
+    p = hg.hg_chunk_params(20, 1, 0xFFF, 0, 2048, 0, 0, 1)
+    # HG_ASYNC needs device outputs.
+    assert hg.hg_chunk(ctx.handle, d.data_ptr(), d.numel(), ctypes.byref(p), ends.data_ptr(), 4096,
+                       ctypes.addressof(n), None, hg.HG_IN_DEVICE | hg.HG_ASYNC | hg.HG_COUNT_HOST,
+                       s.cuda_stream) == hg.HG_EINVAL
+
+
 # ------------------------------------------------------------ similarity --
 @pytest.mark.parametrize("kind", KINDS)
 def test_similarity_constructed(ctx, kind):
