@@ -262,25 +262,43 @@ def pct(xs, p):
 
 def cpu_baseline(data_np, prev_np, mib):
     """The oracle on the host cores, over the first `mib` MiB of the step's
-    input (the same seven passes plus the similarity lookup)."""
+    input (the same seven passes plus the similarity lookup), sharded over
+    up to 16 threads; and on one thread over an eighth of that sample."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import numpy as np
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
+
+    def passes(n, th):
+        sample, prev = data_np[:n], prev_np[:n]
+        # The previous version's block-map is an input of the step: built untimed.
+        _, _, prev_dig = oracle.chunk(oracle.MD5, oracle.SHA1, prev, 20, 1, 0xFFF, 0, 2 * KiB, th)
+        t0 = time.perf_counter()
+        for k, b in BLOCK_JOBS:
+            lv = oracle.leaves_sharded(k, sample, b, th)
+            oracle.root(k, lv)
+        _, ends, dig = oracle.chunk(oracle.MD5, oracle.SHA1, sample, 20, 1, 0xFFF, 0, 2 * KiB, th)
+        oracle.similarity(oracle.SHA1, prev_dig, dig, np.diff(ends, prepend=np.uint64(0)))
+        return time.perf_counter() - t0
+
     n = mib * MiB
-    sample, prev = data_np[:n], prev_np[:n]
-    # The previous version's block-map is an input of the step: built untimed.
-    _, _, prev_dig = oracle.chunk(oracle.MD5, oracle.SHA1, prev, 20, 1, 0xFFF, 0, 2 * KiB, threads)
-    t0 = time.perf_counter()
-    for k, b in BLOCK_JOBS:
-        lv = oracle.leaves_sharded(k, sample, b, threads)
-        oracle.root(k, lv)
-    _, ends, dig = oracle.chunk(oracle.MD5, oracle.SHA1, sample, 20, 1, 0xFFF, 0, 2 * KiB, threads)
-    import numpy as np
-    lens = np.diff(ends, prepend=np.uint64(0))
-    oracle.similarity(oracle.SHA1, prev_dig, dig, lens)
-    dt = time.perf_counter() - t0
+    dt = passes(n, threads)
+    n1 = max(MiB, n // 8)
+    dt1 = passes(n1, 1)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(7 * n / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {mib} MiB of the step input (7 passes + similarity), {dt:.2f} s wall"}
+            "sample": f"first {mib} MiB of the step input (7 passes + similarity), {dt:.2f} s wall on "
+                      f"{threads} threads",
+            "single_thread_value": round(7 * n1 / dt1 / 1e9, 4),
+            "single_thread_sample": f"first {n1 // MiB} MiB, {dt1:.2f} s",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def breakdown(torch, hg, data, host_pinned):
@@ -303,13 +321,34 @@ def breakdown(torch, hg, data, host_pinned):
         return ts
 
     n = data.numel()
+    peak = INT32_PEAK_TOPS * 1e12
     for k, b in BLOCK_JOBS:
         name = f"{'sha1' if k else 'md5'}_{b // KiB}k"
         t_leaf = statistics.median(timed(lambda: ctx.block_hash(data, b, k, root=False)))
         t_all = timed(lambda: ctx.block_hash(data, b, k))
+        chains = n // b
+        ops = chains * padded_blocks(b) * BLOCK_OPS[k]
+        frac = ops / (t_leaf / 1e3) / peak
+        # One sequential chain per segment: filling the ALU takes one wave
+        # per SIMD (65,536 lanes), so fewer segments cap the attainable rate.
+        cap = min(1.0, chains / 65536)
         res[name] = {"leaves_GBps": round(n / t_leaf / 1e6, 1), "leaves_ms": round(t_leaf, 3),
+                     "alu_frac": round(frac, 4), "parallelism_cap": round(cap, 4),
+                     "capped_frac": round(frac / cap, 4),
                      "with_root_ms_p50": round(pct(t_all, 50), 3),
                      "with_root_ms_p99": round(pct(t_all, 99), 3)}
+    # Fused MD5 + SHA-1: one pass over the input, both digests.
+    for b in (4 * KiB, 64 * KiB, MiB):
+        t = statistics.median(timed(lambda: ctx.block_hash_dual(data, b, root=False)))
+        chains = n // b
+        ops = chains * padded_blocks(b) * (BLOCK_OPS[0] + BLOCK_OPS[1])
+        frac = ops / (t / 1e3) / peak
+        # Two chains per lane, but a wave issues at most one instruction per
+        # four cycles, so the cap is set by lanes (segments) as above.
+        cap = min(1.0, chains / 65536)
+        res[f"md5+sha1_{b // KiB}k"] = {"leaves_GBps": round(n / t / 1e6, 1), "leaves_ms": round(t, 3),
+                                        "alu_frac": round(frac, 4), "parallelism_cap": round(cap, 4),
+                                        "capped_frac": round(frac / cap, 4)}
     for st in (1, 4):
         t = statistics.median(timed(lambda: ctx.window_scan(data, 20, st, 0xFFF, 0), reps=3))
         res[f"window_md5_w20_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1),
@@ -322,6 +361,9 @@ def breakdown(torch, hg, data, host_pinned):
         res[f"{'sha1' if k else 'md5'}_64k_with_h2d"] = {
             "GBps": round(n / statistics.median(ts) / 1e6, 1),
             "ms_p50": round(pct(ts, 50), 2), "ms_p99": round(pct(ts, 99), 2)}
+    # Measured ceilings beside the data-sheet ones.
+    res["probes"] = {"int32_Tops_measured": round(ctx.probe_alu(), 2), "int32_Tops_spec": round(INT32_PEAK_TOPS, 2),
+                     "hbm_read_GBps_measured": round(ctx.probe_read(data), 1), "hbm_GBps_spec": 8000.0}
     ctx.close()
     return res
 

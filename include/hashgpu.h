@@ -127,6 +127,14 @@ int hg_host_free(hg_ctx *ctx, void *p);
 int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, int digest,
                   void *leaf_out, void *root_out, uint32_t flags, void *stream);
 
+/* Both digests in one pass over the input: the MD5 and the SHA-1 direct
+ * hash of the block (the same segments; each byte is read once).  Equal to
+ * hg_block_hash with HG_MD5 and with HG_SHA1.  Outputs as there; each may
+ * be NULL, not all four. */
+int hg_block_hash_dual(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, void *md5_leaf_out,
+                       void *md5_root_out, void *sha1_leaf_out, void *sha1_root_out, uint32_t flags,
+                       void *stream);
+
 /* ------------------------------------------------- batched direct hash -- */
 
 /* One direct-hash job of a batch.  All pointers are device pointers. */
@@ -437,6 +445,15 @@ int hg_timing_reset(hg_ctx *ctx);
  * reset (HG_ETRUNC when that exceeds capacity).  Contexts given the same
  * origin share one time axis, so their intervals can be merged. */
 int hg_timing_origin(hg_ctx *ctx, void *event);
+
+/* Measured ceilings (synchronous, best of three timed runs after a warm-up).
+ * hg_probe_alu: int32 VALU issue rate in Tops/s, from independent chains of
+ * rotate, add and three-input logic ops (the hash rounds' mix) on every
+ * SIMD.  hg_probe_read: HBM read rate in GB/s (1e9 B/s), 16-byte loads over
+ * the device buffer buf of len bytes (len >= 16; use one larger than the
+ * caches). */
+int hg_probe_alu(hg_ctx *ctx, double *tops, void *stream);
+int hg_probe_read(hg_ctx *ctx, const void *buf, uint64_t len, double *gbps, void *stream);
 int hg_timing_intervals(hg_ctx *ctx, int kernel_class, double *start_ms, double *end_ms, uint64_t capacity,
                         uint64_t *count);
 

@@ -28,6 +28,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void l
     store_digest<KIND>(out + k * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 
+// Both digests of every segment in one pass over the input.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void leaf_dual_kernel(
+    const uint8_t *__restrict__ in, uint64_t len, uint64_t block, uint64_t n_leaves, uint8_t *__restrict__ out_md5,
+    uint8_t *__restrict__ out_sha1) {
+    uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_leaves) return;
+    uint64_t start = k * block;
+    uint64_t n = len - start < block ? len - start : block;
+    uint32_t sm[5], ss[5];
+    hash_range_dual(in + start, n, in + len, sm, ss);
+    store_digest<KIND_MD5>(out_md5 + k * 16, sm);
+    store_digest<KIND_SHA1>(out_sha1 + k * 20, ss);
+}
+
+hipError_t launch_leaves_dual(const uint8_t *in, uint64_t len, uint64_t block, uint64_t n_leaves,
+                              uint8_t *out_md5, uint8_t *out_sha1, hipStream_t s) {
+    if (n_leaves == 0) return hipSuccess;
+    unsigned tpb = n_leaves < 256ull * 1024 ? 64u : 256u;
+    uint64_t grid = (n_leaves + tpb - 1) / tpb;
+    leaf_dual_kernel<<<dim3((unsigned)grid), dim3(tpb), 0, s>>>(in, len, block, n_leaves, out_md5, out_sha1);
+    return hipGetLastError();
+}
+
 hipError_t launch_leaves(int kind, const uint8_t *in, uint64_t len, uint64_t block,
                          uint64_t n_leaves, uint8_t *out, hipStream_t s) {
     if (n_leaves == 0) return hipSuccess;

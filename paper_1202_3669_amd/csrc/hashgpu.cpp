@@ -30,6 +30,7 @@ enum Slot {
     SLOT_IN2,      // device copy of dig_b
     SLOT_IN3,      // device copy of len_b
     SLOT_LEAVES,   // segment digests
+    SLOT_LEAVES2,  // second digest's segment digests (fused direct hash)
     SLOT_WS,       // window-scan tile bookkeeping
     SLOT_CAND,     // candidate starts
     SLOT_ENDS,     // chunk ends
@@ -476,6 +477,61 @@ int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size
     return HG_OK;
 }
 
+int hg_block_hash_dual(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, void *md5_leaf_out,
+                       void *md5_root_out, void *sha1_leaf_out, void *sha1_root_out, uint32_t flags,
+                       void *stream) {
+    HG_TRY(enter(ctx));
+    HG_TRY(check_flags(ctx, flags, true));
+    if (block_size == 0) return fail(ctx, HG_EINVAL, "block_size must be >= 1");
+    if (!md5_leaf_out && !md5_root_out && !sha1_leaf_out && !sha1_root_out)
+        return fail(ctx, HG_EINVAL, "all outputs are NULL");
+    if (len && !in) return fail(ctx, HG_EINVAL, "in is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    const uint64_t n = len ? (len + block_size - 1) / block_size : 0;
+    uint8_t *lm, *ls;
+    void *p;
+    if (md5_leaf_out && out_dev) {
+        lm = (uint8_t *)md5_leaf_out;
+    } else {
+        HG_TRY(ensure(ctx, SLOT_LEAVES, n * 16, st, &p));
+        lm = (uint8_t *)p;
+    }
+    if (sha1_leaf_out && out_dev) {
+        ls = (uint8_t *)sha1_leaf_out;
+    } else {
+        HG_TRY(ensure(ctx, SLOT_LEAVES2, n * 20, st, &p));
+        ls = (uint8_t *)p;
+    }
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    uint8_t *rm = (md5_root_out && out_dev) ? (uint8_t *)md5_root_out : (uint8_t *)small;
+    uint8_t *rs = (sha1_root_out && out_dev) ? (uint8_t *)sha1_root_out : (uint8_t *)(small + 4);
+    if (in_dev || len == 0) {
+        HG_LAUNCH(ctx, HG_K_LEAVES, st, hg::launch_leaves_dual((const uint8_t *)in, len, block_size, n, lm, ls, st));
+    } else {
+        HG_TRY(ensure(ctx, SLOT_IN, len, st, &p));
+        uint8_t *din = (uint8_t *)p;
+        HG_TRY(stream_in(ctx, din, (const uint8_t *)in, len, block_size, st,
+                         [&](uint64_t off, uint64_t plen) -> int {
+                             const uint64_t k0 = off / block_size;
+                             const uint64_t k1 = (off + plen + block_size - 1) / block_size;
+                             HG_LAUNCH(ctx, HG_K_LEAVES, st,
+                                       hg::launch_leaves_dual(din + off, plen, block_size, k1 - k0, lm + k0 * 16,
+                                                              ls + k0 * 20, st));
+                             return HG_OK;
+                         }));
+    }
+    if (md5_root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(HG_MD5, lm, n * 16, rm, st));
+    if (sha1_root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(HG_SHA1, ls, n * 20, rs, st));
+    if (md5_leaf_out && !out_dev) HG_TRY(copy_out(ctx, md5_leaf_out, lm, n * 16, false, st));
+    if (sha1_leaf_out && !out_dev) HG_TRY(copy_out(ctx, sha1_leaf_out, ls, n * 20, false, st));
+    if (md5_root_out && !out_dev) HG_TRY(copy_out(ctx, md5_root_out, rm, 16, false, st));
+    if (sha1_root_out && !out_dev) HG_TRY(copy_out(ctx, sha1_root_out, rs, 20, false, st));
+    if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
+    return HG_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -728,6 +784,66 @@ int hg_timing_reset(hg_ctx *ctx) {
         ctx->t_start[k].clear();
         ctx->t_end[k].clear();
     }
+    return HG_OK;
+}
+
+int hg_probe_alu(hg_ctx *ctx, double *tops, void *stream) {
+    HG_TRY(enter(ctx));
+    if (!tops) return fail(ctx, HG_EINVAL, "tops is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    // Eight waves per SIMD, about 5 ms at the data-sheet rate.
+    const uint32_t blocks = 2048, steps = 1000;
+    hipEvent_t a, b;
+    HG_HIP(ctx, hipEventCreate(&a));
+    HG_HIP(ctx, hipEventCreate(&b));
+    float best = 1e30f;
+    int st_ = HG_OK;
+    for (int r = 0; r < 4 && st_ == HG_OK; r++) {
+        if (hipEventRecord(a, st) != hipSuccess ||
+            hg::launch_alu_probe(blocks, steps, (uint32_t *)small, st) != hipSuccess ||
+            hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+            st_ = fail(ctx, HG_EDEVICE, "ALU probe failed: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (r > 0) best = std::min(best, ms);  // the first run warms up
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st_ != HG_OK) return st_;
+    *tops = (double)hg::alu_probe_ops(blocks, steps) / (best * 1e-3) / 1e12;
+    return HG_OK;
+}
+
+int hg_probe_read(hg_ctx *ctx, const void *buf, uint64_t len, double *gbps, void *stream) {
+    HG_TRY(enter(ctx));
+    if (!gbps || !buf || len < 16) return fail(ctx, HG_EINVAL, "need a device buffer of at least 16 bytes");
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    hipEvent_t a, b;
+    HG_HIP(ctx, hipEventCreate(&a));
+    HG_HIP(ctx, hipEventCreate(&b));
+    float best = 1e30f;
+    int st_ = HG_OK;
+    for (int r = 0; r < 4 && st_ == HG_OK; r++) {
+        if (hipEventRecord(a, st) != hipSuccess ||
+            hg::launch_read_probe((const uint8_t *)buf, len, (uint32_t *)small, st) != hipSuccess ||
+            hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+            st_ = fail(ctx, HG_EDEVICE, "read probe failed: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (r > 0) best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st_ != HG_OK) return st_;
+    *gbps = (double)(len / 16 * 16) / (best * 1e-3) / 1e9;
     return HG_OK;
 }
 

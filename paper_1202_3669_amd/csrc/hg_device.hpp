@@ -341,6 +341,51 @@ __device__ __forceinline__ void hash_range(const uint8_t *p, uint64_t n, const u
     finish_tail<KIND>(st, X, rem, n);
 }
 
+// MD5 and SHA-1 of the same n bytes in one pass (each block is read once
+// and compressed by both; SHA-1 overwrites the block's words, so MD5 goes
+// first).
+__device__ __forceinline__ void dual_block(uint32_t sm[5], uint32_t ss[5], uint32_t X[16]) {
+    Hash<KIND_MD5>::block(sm, X);
+    Hash<KIND_SHA1>::block(ss, X);
+}
+
+__device__ __forceinline__ void hash_range_dual(const uint8_t *p, uint64_t n, const uint8_t *buf_end,
+                                                uint32_t sm[5], uint32_t ss[5]) {
+    Hash<KIND_MD5>::init(sm);
+    Hash<KIND_SHA1>::init(ss);
+    const uint64_t full = n >> 6, pairs = full >> 1;
+    uint32_t X[32], Y[32];
+    uint64_t q = 0;
+    if (pairs > 0) load_pair(p, X);
+    while (q + 1 < pairs) {
+        load_pair(p + ((q + 1) << 7), Y);
+        __builtin_amdgcn_sched_barrier(0);
+        dual_block(sm, ss, X);
+        dual_block(sm, ss, X + 16);
+        const uint64_t nq = q + 2 < pairs ? q + 2 : pairs - 1;
+        load_pair(p + (nq << 7), X);
+        __builtin_amdgcn_sched_barrier(0);
+        dual_block(sm, ss, Y);
+        dual_block(sm, ss, Y + 16);
+        q += 2;
+    }
+    if (q < pairs) {
+        dual_block(sm, ss, X);
+        dual_block(sm, ss, X + 16);
+    }
+    if (full & 1) {
+        load_block(p + ((full - 1) << 6), X);
+        dual_block(sm, ss, X);
+    }
+    const int rem = (int)(n & 63);
+    load_tail(p + (full << 6), rem, buf_end, X);
+    uint32_t T[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) T[j] = X[j];
+    finish_tail<KIND_MD5>(sm, T, rem, n);
+    finish_tail<KIND_SHA1>(ss, X, rem, n);
+}
+
 // Store a digest at `out` (any alignment).
 template <int KIND>
 __device__ __forceinline__ void store_digest(uint8_t *out, const uint32_t st[5]) {

@@ -17,6 +17,11 @@ namespace hg {
 hipError_t launch_leaves(int kind, const uint8_t *in, uint64_t len, uint64_t block,
                          uint64_t n_leaves, uint8_t *out, hipStream_t s);
 
+// MD5 and SHA-1 segment digests in one pass over the input (16-byte and
+// 20-byte records, segment order).
+hipError_t launch_leaves_dual(const uint8_t *in, uint64_t len, uint64_t block, uint64_t n_leaves,
+                              uint8_t *out_md5, uint8_t *out_sha1, hipStream_t s);
+
 // One digest of a whole device byte range (used for the second level of the
 // direct hash, whose input is the leaf-digest buffer).
 hipError_t launch_hash_one(int kind, const uint8_t *in, uint64_t len, uint8_t *out, hipStream_t s);
@@ -148,6 +153,13 @@ hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *p
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
                              const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
                              int log2_slots, unsigned long long *counters, hipStream_t s);
+
+// ---------------------------------------------------------------- probes --
+// int32 VALU issue-rate and HBM read-rate microbenchmarks (out: a 4-byte
+// device word that the kernels may write).
+uint64_t alu_probe_ops(uint32_t blocks, uint32_t steps);
+hipError_t launch_alu_probe(uint32_t blocks, uint32_t steps, uint32_t *out, hipStream_t s);
+hipError_t launch_read_probe(const uint8_t *p, uint64_t len, uint32_t *out, hipStream_t s);
 
 // Fill n 32-bit words with v (a kernel, so that captured graphs hold no
 // memset nodes).

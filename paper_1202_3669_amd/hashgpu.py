@@ -117,6 +117,9 @@ hg_timing_read = _declare("hg_timing_read", _int,
                           [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
 hg_timing_reset = _declare("hg_timing_reset", _int, [_vp])
 hg_timing_origin = _declare("hg_timing_origin", _int, [_vp, _vp])
+hg_probe_alu = _declare("hg_probe_alu", _int, [_vp, ctypes.POINTER(ctypes.c_double), _vp])
+hg_probe_read = _declare("hg_probe_read", _int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_double), _vp])
+hg_block_hash_dual = _declare("hg_block_hash_dual", _int, [_vp, _vp, _u64, _u64, _vp, _vp, _vp, _vp, _u32, _vp])
 hg_timing_intervals = _declare("hg_timing_intervals", _int, [_vp, _int, _vp, _vp, _u64, ctypes.POINTER(_u64)])
 hg_server_start = _declare("hg_server_start", _int, [_int, ctypes.POINTER(hg_server_cfg), ctypes.POINTER(_vp)])
 hg_submit = _declare("hg_submit", _int,
@@ -137,7 +140,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_batch_destroy", "hg_batch_layout", "hg_batch_run", "hg_batch_capture",
             "hg_batch_replay", "hg_batch_tune", "hg_server_start", "hg_submit", "hg_wait",
             "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop",
-            "hg_timing_origin", "hg_timing_intervals"]
+            "hg_timing_origin", "hg_timing_intervals", "hg_probe_alu", "hg_probe_read",
+            "hg_block_hash_dual"]
 
 
 class HashGpuError(RuntimeError):
@@ -215,6 +219,36 @@ class Context:
                            _stream_handle(stream))
         self._check(st)
         return lv, rt
+
+    def block_hash_dual(self, data, block_size: int, leaves: bool = True, root: bool = True, stream=None):
+        """(md5 leaves, md5 root, sha1 leaves, sha1 root) of a uint8 tensor in
+        one pass (CUDA tensors; None where not asked for)."""
+        torch = _torch()
+        n = (data.numel() + block_size - 1) // block_size if data.numel() else 0
+        dev = torch.device("cuda", self.device)
+        lm = torch.empty((n, 16), dtype=torch.uint8, device=dev) if leaves else None
+        ls = torch.empty((n, 20), dtype=torch.uint8, device=dev) if leaves else None
+        rm = torch.empty(16, dtype=torch.uint8, device=dev) if root else None
+        rs = torch.empty(20, dtype=torch.uint8, device=dev) if root else None
+        flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+        ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None
+        self._check(hg_block_hash_dual(self.handle, data.data_ptr() if data.numel() else None, data.numel(),
+                                       block_size, ptr(lm), ptr(rm), ptr(ls), ptr(rs), flags,
+                                       _stream_handle(stream)))
+        return lm, rm, ls, rs
+
+    def probe_alu(self, stream=None) -> float:
+        """Measured int32 VALU rate (Tops/s)."""
+        v = ctypes.c_double(0.0)
+        self._check(hg_probe_alu(self.handle, ctypes.byref(v), _stream_handle(stream)))
+        return v.value
+
+    def probe_read(self, data, stream=None) -> float:
+        """Measured HBM read rate (GB/s) over a CUDA tensor."""
+        v = ctypes.c_double(0.0)
+        self._check(hg_probe_read(self.handle, data.data_ptr(), data.numel() * data.element_size(),
+                                  ctypes.byref(v), _stream_handle(stream)))
+        return v.value
 
     # ----------------------------------------------------- sliding window --
     def window_scan(self, data, window: int, stride: int, mask: int, target: int,

@@ -92,6 +92,34 @@ def test_block_hash_edge_cases(ctx, kind, length, block, offset):
     assert bytes(host(rt)) == oracle.root(kind, exp_lv)
 
 
+@pytest.mark.parametrize("length,block,offset", EDGE)
+def test_block_hash_dual_edge_cases(ctx, length, block, offset):
+    data = inputs.uniform_bytes(200 + length % 89, length)
+    note(f"block_hash_dual edge len={length} B={block} off={offset}")
+    lm, rm, ls, rs = ctx.block_hash_dual(dev(data, offset), block)
+    torch.cuda.synchronize()
+    for kind, lv, rt in ((oracle.MD5, lm, rm), (oracle.SHA1, ls, rs)):
+        exp_lv = oracle.leaves(kind, data, block)
+        assert np.array_equal(host(lv), exp_lv)
+        assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+
+
+def test_block_hash_dual_streams_host_input(ctx):
+    # Host input in pinned staging pieces (two 64 MiB pieces and a tail),
+    # root-only outputs for MD5 and leaves-only for SHA-1.
+    data = inputs.uniform_bytes(211, 130 * MiB + 4097)
+    note("block_hash_dual host input")
+    rm = np.zeros(16, dtype=np.uint8)
+    ls = np.zeros(((data.size + 65535) // 65536, 20), dtype=np.uint8)
+    from paper_1202_3669_amd import hashgpu as hgm
+    st = hgm.hg_block_hash_dual(ctx.handle, data.ctypes.data, data.size, 65536, None, rm.ctypes.data,
+                                ls.ctypes.data, None, 0, torch.cuda.current_stream().cuda_stream)
+    assert st == 0
+    exp_m = oracle.leaves_sharded(oracle.MD5, data, 65536, THREADS)
+    assert bytes(rm) == oracle.root(oracle.MD5, exp_m)
+    assert np.array_equal(ls, oracle.leaves_sharded(oracle.SHA1, data, 65536, THREADS))
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_block_hash_root_only_and_leaves_only(ctx, kind):
     data = inputs.uniform_bytes(7, 300_000)
@@ -334,6 +362,15 @@ def test_block_hash_large_workload(ctx, block):
         exp_lv = oracle.leaves_sharded(kind, data, block, THREADS)
         assert np.array_equal(host(lv), exp_lv)
         assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+        _LARGE[(kind, block)] = (exp_lv, oracle.root(kind, exp_lv))
+    # Fused: both digests in one pass equal the oracle's.
+    note(f"block_hash_dual 1GiB B={block}")
+    lm, rm, ls, rs = ctx.block_hash_dual(d, block)
+    torch.cuda.synchronize()
+    for kind, lv, rt in ((oracle.MD5, lm, rm), (oracle.SHA1, ls, rs)):
+        exp_lv, exp_rt = _LARGE.pop((kind, block))
+        assert np.array_equal(host(lv), exp_lv)
+        assert bytes(host(rt)) == exp_rt
 
 
 _LARGE = {}
@@ -445,3 +482,15 @@ def test_leaves_and_roots_batches_from_device_table(ctx, hg):
         exp = oracle.leaves(kind, data, block)
         assert np.array_equal(host(lv), exp)
         assert bytes(host(rt)) == oracle.root(kind, exp)
+
+
+# ------------------------------------------------------------------ probes --
+def test_probes_report_plausible_ceilings(ctx, hg):
+    note("ALU and HBM probes")
+    tops = ctx.probe_alu()
+    assert 1.0 < tops < 60.0, tops  # data sheet: 39.32 Tops/s int32
+    buf = torch.zeros(256 * MiB, dtype=torch.uint8, device="cuda")
+    gbps = ctx.probe_read(buf)
+    assert 100.0 < gbps < 12000.0, gbps  # data sheet: 8 TB/s
+    v = ctypes.c_double(0.0)
+    assert hg.hg_probe_read(ctx.handle, None, 0, ctypes.byref(v), None) == hg.HG_EINVAL
