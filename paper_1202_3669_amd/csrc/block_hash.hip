@@ -28,6 +28,87 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void l
     store_digest<KIND>(out + k * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 
+// Segments read through LDS.  With one lane per segment, a 16-byte load
+// instruction of a wave touches 64 lines (one per lane).  Here the wave loads
+// its 64 segments' next 128-byte lines together: in load instruction j, lane
+// l reads 16-byte piece (l & 7) of segment 8j + (l >> 3), so each
+// instruction reads 8 whole lines; the pieces go to an LDS tile (one
+// 144-byte row per segment: 16 bytes of padding make both the row writes and
+// the per-lane row reads conflict-free) and every lane then reads its own
+// row.  The next line pair is loaded while the current one is compressed.
+// The wave does this for as many pairs of blocks as all its segments have;
+// each lane finishes the rest of its segment on its own.
+constexpr int LDS_ROW = 9;  // 16-byte units per row: 8 of data, 1 of padding
+
+// 16 bytes at offset `off` of segment `seg` (zeros past the last segment).
+__device__ __forceinline__ uint4 lds_piece(const uint8_t *in, uint64_t block, uint64_t n_leaves, uint64_t seg,
+                                           uint64_t off) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (seg < n_leaves) __builtin_memcpy(&v, in + seg * block + off, 16);
+    return v;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) void leaf_lds_kernel(const uint8_t *__restrict__ in, uint64_t len, uint64_t block,
+                                                      uint64_t n_leaves, uint8_t *__restrict__ out) {
+    __shared__ uint4 tile[64 * LDS_ROW];
+    const int lane = threadIdx.x;
+    const uint64_t k0 = (uint64_t)blockIdx.x * 64, k = k0 + lane;
+    const bool active = k < n_leaves;
+    const uint64_t n = active ? (len - k * block < block ? len - k * block : block) : 0;
+    // Pairs of blocks that every active segment of the wave has.
+    uint64_t m = active ? n >> 7 : ~0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(m, off, 64);
+        m = o < m ? o : m;
+    }
+    const int piece = lane & 7, row0 = lane >> 3;
+    uint4 R[8];
+    uint32_t st[5];
+    Hash<KIND>::init(st);
+    if (m > 0) {
+#pragma unroll
+        for (int j = 0; j < 8; j++) R[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, piece * 16);
+#pragma unroll
+        for (int j = 0; j < 8; j++) tile[(8 * j + row0) * LDS_ROW + piece] = R[j];
+        __syncthreads();
+    }
+    for (uint64_t q = 0; q < m; q++) {
+        uint32_t X[32];
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const uint4 v = tile[lane * LDS_ROW + i];
+            X[4 * i] = v.x;
+            X[4 * i + 1] = v.y;
+            X[4 * i + 2] = v.z;
+            X[4 * i + 3] = v.w;
+        }
+        __syncthreads();  // every row read before the tile is refilled
+        const bool more = q + 1 < m;
+        if (more) {
+            const uint64_t off = (q + 1) * 128 + piece * 16;
+#pragma unroll
+            for (int j = 0; j < 8; j++) R[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, off);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        Hash<KIND>::block(st, X);
+        Hash<KIND>::block(st, X + 16);
+        // The tile writes wait for the loads: keep them after the rounds
+        // (the compiler would otherwise merge them into the load branch).
+        asm volatile("" : "+v"(st[0]), "+v"(st[1]), "+v"(st[2]), "+v"(st[3]) : : "memory");
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) tile[(8 * j + row0) * LDS_ROW + piece] = R[j];
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    const uint64_t done = m * 128;
+    hash_rest<KIND>(in + k * block + done, n - done, n, in + len, st);
+    store_digest<KIND>(out + k * (uint64_t)Hash<KIND>::DIGEST, st);
+}
+
 // Both digests of every segment in one pass over the input.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void leaf_dual_kernel(
     const uint8_t *__restrict__ in, uint64_t len, uint64_t block, uint64_t n_leaves, uint8_t *__restrict__ out_md5,
@@ -54,6 +135,13 @@ hipError_t launch_leaves_dual(const uint8_t *in, uint64_t len, uint64_t block, u
 hipError_t launch_leaves(int kind, const uint8_t *in, uint64_t len, uint64_t block,
                          uint64_t n_leaves, uint8_t *out, hipStream_t s) {
     if (n_leaves == 0) return hipSuccess;
+    if (kind == KIND_MD5 && block >= 256 && n_leaves >= 64 * 1024) {
+        // MD5 needs more bytes per op than HBM delivers with one line per
+        // lane per load: read whole lines per instruction through LDS.
+        const uint64_t grid = (n_leaves + 63) / 64;
+        leaf_lds_kernel<KIND_MD5><<<dim3((unsigned)grid), dim3(64), 0, s>>>(in, len, block, n_leaves, out);
+        return hipGetLastError();
+    }
     // Few long segments: 64-lane workgroups spread the chains over more CUs.
     unsigned tpb = n_leaves < 256ull * 1024 ? 64u : 256u;
     uint64_t grid = (n_leaves + tpb - 1) / tpb;

@@ -298,16 +298,17 @@ __device__ __forceinline__ void load_pair(const uint8_t *p, uint32_t X[32]) {
 }
 
 // Hash the n bytes at p with one lane (p: any alignment; buf_end bounds the
-// readable buffer).  Bytes are read in pairs of blocks, i.e. whole 128-byte
+// readable buffer); hash_rest continues a message of `total` bytes whose
+// `rest` last bytes start at p (the state holds everything before).  Bytes
+// are read in pairs of blocks, i.e. whole 128-byte
 // lines for aligned input: with one lane per segment, the lanes of a wave
 // read 64 different lines at a time, and a line read in two halves at
 // different times is easily evicted from L2 in between and fetched twice.
 // The loop double-buffers: pair q+1 is in flight while pair q is compressed.
 template <int KIND>
-__device__ __forceinline__ void hash_range(const uint8_t *p, uint64_t n, const uint8_t *buf_end,
-                                           uint32_t st[5]) {
-    Hash<KIND>::init(st);
-    const uint64_t full = n >> 6, pairs = full >> 1;
+__device__ __forceinline__ void hash_rest(const uint8_t *p, uint64_t rest, uint64_t total, const uint8_t *buf_end,
+                                          uint32_t st[5]) {
+    const uint64_t full = rest >> 6, pairs = full >> 1;
     uint32_t X[32], Y[32];
     uint64_t q = 0;
     if (pairs > 0) load_pair(p, X);
@@ -336,9 +337,16 @@ __device__ __forceinline__ void hash_range(const uint8_t *p, uint64_t n, const u
         load_block(p + ((full - 1) << 6), X);
         Hash<KIND>::block(st, X);
     }
-    const int rem = (int)(n & 63);
+    const int rem = (int)(rest & 63);
     load_tail(p + (full << 6), rem, buf_end, X);
-    finish_tail<KIND>(st, X, rem, n);
+    finish_tail<KIND>(st, X, rem, total);
+}
+
+template <int KIND>
+__device__ __forceinline__ void hash_range(const uint8_t *p, uint64_t n, const uint8_t *buf_end,
+                                           uint32_t st[5]) {
+    Hash<KIND>::init(st);
+    hash_rest<KIND>(p, n, n, buf_end, st);
 }
 
 // MD5 and SHA-1 of the same n bytes in one pass (each block is read once

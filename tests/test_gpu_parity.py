@@ -92,6 +92,25 @@ def test_block_hash_edge_cases(ctx, kind, length, block, offset):
     assert bytes(host(rt)) == oracle.root(kind, exp_lv)
 
 
+# Many segments: MD5 goes through the LDS-staged kernel (whole lines per
+# load instruction); ragged last segments, partial last waves, unaligned
+# bases and segment sizes that are not whole line pairs.
+MANY = [(65536 * 256 + 77, 256, 3), (70000 * 320 + 5, 320, 1), (65536 * 4096 - 1000, 4096, 0),
+        (65600 * 200, 200, 0), (65537 * 1000 + 999, 1000, 7)]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("length,block,offset", MANY)
+def test_block_hash_many_segments(ctx, kind, length, block, offset):
+    data = inputs.uniform_bytes(300 + length % 83, length)
+    note(f"block_hash many kind={kind} len={length} B={block} off={offset}")
+    lv, rt = ctx.block_hash(dev(data, offset), block, kind)
+    torch.cuda.synchronize()
+    exp_lv = oracle.leaves_sharded(kind, data, block, THREADS)
+    assert np.array_equal(host(lv), exp_lv)
+    assert bytes(host(rt)) == oracle.root(kind, exp_lv)
+
+
 @pytest.mark.parametrize("length,block,offset", EDGE)
 def test_block_hash_dual_edge_cases(ctx, length, block, offset):
     data = inputs.uniform_bytes(200 + length % 89, length)
