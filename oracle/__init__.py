@@ -83,6 +83,8 @@ def _bind(path: str):
     lib.oracle_window_scan_range.restype = _u64
     lib.oracle_chunk_select.argtypes = [_vp, _u64, _u64, _u64, _u64, _vp, _u64]
     lib.oracle_chunk_select.restype = _u64
+    lib.oracle_chunk_select_max.argtypes = [_vp, _u64, _u64, _u64, _u64, _u64, _vp, _u64]
+    lib.oracle_chunk_select_max.restype = _u64
     lib.oracle_chunk_digests.argtypes = [_int, _vp, _vp, _u64, _vp]
     lib.oracle_chunk_digests.restype = _int
     lib.oracle_similarity.argtypes = [_int, _vp, _u64, _vp, _vp, _u64, _vp]
@@ -190,13 +192,23 @@ def window_scan(kind: int, data, window: int, stride: int, mask: int, target: in
     return out[:total].copy()
 
 
-def chunk_select(starts: np.ndarray, window: int, length: int, min_chunk: int) -> np.ndarray:
-    """Chunk end offsets (uint64, last == length) from ascending candidates."""
+def chunk_select(starts: np.ndarray, window: int, length: int, min_chunk: int,
+                 max_chunk: int = 0) -> np.ndarray:
+    """Chunk end offsets (uint64, last == length) from ascending candidates;
+    with max_chunk > 0, forced cuts keep every chunk at most that long."""
     lib = _load()
     st = np.ascontiguousarray(starts, dtype=np.uint64)
-    cap = st.size + 1
+    if max_chunk == 0:
+        cap = st.size + 1
+        out = np.zeros(cap, dtype=np.uint64)
+        m = lib.oracle_chunk_select(_ptr(st), st.size, window, length, min_chunk, _ptr(out), cap)
+        return out[:m].copy()
+    cap = st.size + 2 + length // max_chunk
     out = np.zeros(cap, dtype=np.uint64)
-    m = lib.oracle_chunk_select(_ptr(st), st.size, window, length, min_chunk, _ptr(out), cap)
+    m = lib.oracle_chunk_select_max(_ptr(st), st.size, window, length, min_chunk, max_chunk, _ptr(out), cap)
+    if m == (1 << 64) - 1:
+        raise ValueError("max_chunk must be 0 or at least max(min_chunk, 1)")
+    assert m <= cap
     return out[:m].copy()
 
 
@@ -226,11 +238,11 @@ def similarity(kind: int, dig_a: np.ndarray, dig_b: np.ndarray, len_b=None):
 
 
 def chunk(kind_window: int, kind_chunk: int, data, window: int, stride: int, mask: int,
-          target: int, min_chunk: int, threads: int = 1):
+          target: int, min_chunk: int, threads: int = 1, max_chunk: int = 0):
     """Whole content-based chunking path: candidates, ends, chunk digests."""
     buf = _bytes_view(data)
     starts = window_scan_sharded(kind_window, buf, window, stride, mask, target, threads)
-    ends = chunk_select(starts, window, buf.size, min_chunk)
+    ends = chunk_select(starts, window, buf.size, min_chunk, max_chunk)
     return starts, ends, chunk_digests(kind_chunk, buf, ends)
 
 

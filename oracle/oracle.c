@@ -307,6 +307,43 @@ uint64_t oracle_chunk_select(const uint64_t *starts, uint64_t n, uint64_t w, uin
     return m;
 }
 
+/* Boundary decision with a minimum and a maximum chunk size (Sec. 4.3 names
+ * both as system parameters; the reading here: the maximum is kept by forced
+ * cuts).  step = max(min_chunk, 1).  From the previous cut `last`, the next
+ * natural cut is the first candidate end e = start + w with e >= last + step
+ * and e < len (or, when there is none, the end of the block).  If that lies
+ * more than max_chunk past `last`, a cut is forced at last + max_chunk and
+ * the search starts again from there; otherwise the natural cut is taken.
+ * The final chunk ends at len.  max_chunk = 0: no maximum (the same result as
+ * oracle_chunk_select).  Returns the number of chunk ends (writes up to cap),
+ * or UINT64_MAX when 0 < max_chunk < step. */
+uint64_t oracle_chunk_select_max(const uint64_t *starts, uint64_t n, uint64_t w, uint64_t len,
+                                 uint64_t min_chunk, uint64_t max_chunk, uint64_t *ends, uint64_t cap) {
+    const uint64_t step = min_chunk > 0 ? min_chunk : 1;
+    uint64_t last = 0, m = 0, j = 0;
+    if (max_chunk != 0 && max_chunk < step) return UINT64_MAX;
+    if (len == 0) return 0;
+    for (;;) {
+        while (j < n && starts[j] + w < last + step) j++;
+        const int natural = j < n && starts[j] + w < len;
+        const uint64_t next = natural ? starts[j] + w : len;
+        if (max_chunk != 0 && next - last > max_chunk) {
+            last += max_chunk;
+            if (m < cap) ends[m] = last;
+            m++;
+            continue;
+        }
+        if (!natural) break;
+        if (m < cap) ends[m] = next;
+        m++;
+        last = next;
+        j++;
+    }
+    if (m < cap) ends[m] = len;
+    m++;
+    return m;
+}
+
 /* Direct hash of every chunk [ends[j-1], ends[j]) with ends[-1] = 0. */
 int oracle_chunk_digests(int kind, const uint8_t *in, const uint64_t *ends, uint64_t n,
                          uint8_t *out) {

@@ -14,7 +14,11 @@ The oracle is checked against things other than itself:
   candidate density against its binomial expectation on random bytes.
 * The greedy chunk selection against the properties that characterise it
   (partition, minimum size, ends are candidate ends, no skipped eligible
-  candidate), and its degenerate cases.
+  candidate), and its degenerate cases; with a maximum chunk size, against
+  the step-by-step characterisation of each cut (the first eligible
+  candidate end within reach, else a forced cut exactly max past the
+  previous one), the closed form without candidates, and the reduction to
+  no maximum when no chunk can reach it.
 * Chunk digests against ``hashlib`` per chunk; similarity against constructed
   digest sets with a known overlap.
 """
@@ -213,6 +217,65 @@ def test_chunk_select_degenerate():
     assert oracle.chunk_select(st, 70, 100, 0).tolist() == [70, 75, 79, 100]
     # min larger than the block: one chunk
     assert oracle.chunk_select(st, 4, 100, 1000).tolist() == [100]
+
+
+def _check_greedy_max(starts, w, length, min_chunk, max_chunk, ends):
+    """Every cut is the unique choice of the rule with a maximum: from the
+    previous cut p, the first candidate end c with p + step <= c < length if
+    it lies within p + max, else the forced cut p + max (step = max(min, 1))."""
+    ends = [int(e) for e in ends]
+    if length == 0:
+        assert ends == []
+        return
+    step = max(min_chunk, 1)
+    cand_ends = sorted({int(s) + w for s in starts})
+    assert ends[-1] == length
+    assert all(b > a for a, b in zip([0] + ends, ends)), "ends strictly increase"
+    assert all(b - a <= max_chunk for a, b in zip([0] + ends, ends)), "no chunk longer than max"
+    p = 0
+    for e in ends[:-1]:
+        eligible = [c for c in cand_ends if p + step <= c < length]
+        first = eligible[0] if eligible else None
+        if first is not None and first - p <= max_chunk:
+            assert e == first, "the first eligible candidate end within reach is the cut"
+        else:
+            assert e == p + max_chunk, "forced cut exactly max past the previous cut"
+        p = e
+    eligible = [c for c in cand_ends if p + step <= c < length]
+    assert not (eligible and eligible[0] - p <= max_chunk), "a natural cut after the last one was missed"
+    assert length - p <= max_chunk
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_chunk_select_max_properties(seed):
+    rng = np.random.default_rng(300 + seed)
+    length = int(rng.integers(1, 100_000))
+    w = int(rng.integers(1, 64))
+    n = int(rng.integers(0, 300))
+    starts = np.unique(rng.integers(0, max(length - w + 1, 1), size=n)).astype(np.uint64)
+    for min_chunk in [0, 1, 100, 2048]:
+        for max_chunk in [max(min_chunk, 1), 2 * max(min_chunk, 1) + 7, 5000, 40_000]:
+            ends = oracle.chunk_select(starts, w, length, min_chunk, max_chunk)
+            _check_greedy_max(starts, w, length, min_chunk, max_chunk, ends)
+
+
+def test_chunk_select_max_reductions():
+    rng = np.random.default_rng(399)
+    for _ in range(20):
+        length = int(rng.integers(1, 50_000))
+        starts = np.unique(rng.integers(0, length, size=int(rng.integers(0, 200)))).astype(np.uint64)
+        starts = starts[starts + 20 <= length] if length >= 20 else starts[:0]
+        for mn in [0, 64, 3000]:
+            base = oracle.chunk_select(starts, 20, length, mn)
+            # a maximum no chunk can reach changes nothing
+            assert np.array_equal(oracle.chunk_select(starts, 20, length, mn, max(length + 1, mn)), base)
+    # no candidates: forced cuts every max bytes (closed form)
+    L, M = 100_001, 7_000
+    assert oracle.chunk_select(np.zeros(0, np.uint64), 20, L, 0, M).tolist() == \
+        list(range(M, L, M)) + [L]
+    # max < min is rejected
+    with pytest.raises(ValueError):
+        oracle.chunk_select(np.zeros(0, np.uint64), 20, 1000, 100, 50)
 
 
 # --------------------------------------------------------- chunk digests --

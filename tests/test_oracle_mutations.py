@@ -41,6 +41,11 @@ MUTATIONS = {
                           "if (e > last && e - last >= min_chunk && e <= len) {"),
     "greedy_last_not_updated": ("            last = e;\n", "\n"),
     "chunk_start_off_by_one": ("        start = ends[j];\n", "        start = ends[j] - 1;\n"),
+    "forced_cut_long": ("            last += max_chunk;\n", "            last += max_chunk + 1;\n"),
+    "forced_cut_ignores_min": ("        while (j < n && starts[j] + w < last + step) j++;",
+                               "        while (j < n && starts[j] + w <= last) j++;"),
+    "max_checked_with_ge": ("if (max_chunk != 0 && next - last > max_chunk) {",
+                            "if (max_chunk != 0 && next - last >= max_chunk) {"),
     "similarity_bytes_wrong_index": ("if (len_b) bytes += len_b[j];",
                                      "if (len_b) bytes += len_b[0];"),
 }
@@ -63,6 +68,9 @@ def _pin_suite():
     for seed in range(4):
         pins.test_chunk_select_properties(seed)
     pins.test_chunk_select_degenerate()
+    for seed in range(3):
+        pins.test_chunk_select_max_properties(seed)
+    pins.test_chunk_select_max_reductions()
     pins.test_similarity_multiplicity_and_identity()
 
 
