@@ -199,7 +199,7 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
 typedef struct {
     uint32_t window, stride, mask, target; /* as for hg_window_scan */
     uint64_t min_chunk;   /* minimum chunk size in bytes (0 = none) */
-    uint64_t max_chunk;   /* must be 0: forced cuts are not supported */
+    uint64_t max_chunk;   /* maximum chunk size in bytes (0 = none; else >= max(min_chunk, 1)) */
     int32_t window_digest; /* digest of the sliding windows */
     int32_t chunk_digest;  /* digest of each chunk */
 } hg_chunk_params;
@@ -210,6 +210,11 @@ typedef struct {
  * e = i + w; scanning candidates in ascending order, e becomes a cut iff
  * e < len and e - last >= max(min_chunk, 1), where last is the previous cut
  * (initially 0).  The final chunk ends at len.  len = 0 gives no chunks.
+ * With max_chunk > 0 (Sec. 4.3 names a maximum chunk size; this is the
+ * reading taken): whenever the next cut by that rule -- or len, when there
+ * is none -- lies more than max_chunk past `last`, a cut is forced at
+ * last + max_chunk and the rule applies again from there; so no chunk is
+ * longer than max_chunk, and at most len / max_chunk cuts are forced.
  *   ends           capacity entries of uint64: ascending chunk end offsets
  *                  (the last one is len).  Chunk j is [ends[j-1], ends[j])
  *                  with ends[-1] = 0.

@@ -28,6 +28,72 @@ __device__ __forceinline__ void file_cand_range(const FilesChunk &fc, uint64_t t
     c1 = t1 < fc.n_tiles ? fc.tile_off[t1] : total;
 }
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l) << 32) |
+           __builtin_amdgcn_readlane((uint32_t)v, l);
+}
+
+// One wavefront: the cuts of one block of length L from its ascending
+// candidate starts cand[c0, c1), with the minimum step and a maximum chunk
+// size maxc > 0 (forced cuts, see hg_chunk).  From the previous cut `last`,
+// a ballot finds the first candidate end e >= last + step; while it lies
+// more than maxc past `last`, cuts are forced at last + maxc.  A run of f
+// forced cuts ends when e comes within maxc (then e is the next cut) or
+// falls below last + step (then later candidates are looked at), so f is
+// known in closed form and the lanes write the run together.  Writes cut i
+// to out[i] for i < cap; returns the number of cuts.
+__device__ uint64_t walk_cuts_max(const uint64_t *__restrict__ cand, uint64_t c0, uint64_t c1, uint32_t w,
+                                  uint64_t L, uint64_t step, uint64_t maxc, uint64_t *__restrict__ out,
+                                  uint64_t cap) {
+    const int lane = threadIdx.x & 63;
+    uint64_t last = 0, m = 0;
+    for (uint64_t base = c0; base < c1; base += 64) {
+        const uint64_t j = base + lane;
+        const bool valid = j < c1;
+        const uint64_t e = valid ? cand[j] + w : ~0ull;
+        const bool usable = valid && e < L;
+        while (true) {
+            const uint64_t thr = last + step;  // last < L and step <= maxc: no overflow
+            const uint64_t elig = __ballot(usable && e >= thr);
+            if (elig == 0) break;
+            const uint64_t en = readlane64(e, __builtin_ctzll(elig));
+            const uint64_t d = en - last;
+            if (d > maxc) {
+                const uint64_t fa = (d - 1) / maxc;         // until en - last <= maxc
+                const uint64_t fb = (d - step) / maxc + 1;  // until en < last + step
+                const uint64_t f = fa < fb ? fa : fb;
+                for (uint64_t i = lane; i < f; i += 64)
+                    if (m + i < cap) out[m + i] = last + (i + 1) * maxc;
+                m += f;
+                last += f * maxc;
+                continue;
+            }
+            if (lane == 0 && m < cap) out[m] = en;
+            m++;
+            last = en;
+        }
+    }
+    if (L > 0) {
+        if (L - last > maxc) {
+            const uint64_t f = (L - last - 1) / maxc;
+            for (uint64_t i = lane; i < f; i += 64)
+                if (m + i < cap) out[m + i] = last + (i + 1) * maxc;
+            m += f;
+        }
+        if (lane == 0 && m < cap) out[m] = L;
+        m++;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(64) void select_max_kernel(const uint64_t *__restrict__ cand,
+                                                       const uint64_t *__restrict__ n_dev, uint32_t w, uint64_t L,
+                                                       uint64_t step, uint64_t maxc, uint64_t *__restrict__ ends,
+                                                       uint64_t cap, uint64_t *__restrict__ n_chunks) {
+    const uint64_t m = walk_cuts_max(cand, 0, *n_dev, w, L, step, maxc, ends, cap);
+    if (threadIdx.x == 0) *n_chunks = m;
+}
+
 __global__ __launch_bounds__(64) void files_select(FilesChunk fc, uint32_t w, uint64_t step,
                                                   uint64_t *__restrict__ status) {
     const uint32_t f = blockIdx.x;
@@ -43,7 +109,12 @@ __global__ __launch_bounds__(64) void files_select(FilesChunk fc, uint32_t w, ui
         if (c0 > c1) c0 = c1;
     }
     const uint64_t L = fc.len[f];
-    uint64_t *out = fc.slots + c0 + f;
+    uint64_t *out = fc.slots + c0 + f + (fc.extra ? fc.extra[f] : 0);
+    if (fc.max_chunk) {
+        const uint64_t m = walk_cuts_max(fc.cand, c0, c1, w, L, step, fc.max_chunk, out, ~0ull);
+        if (lane == 0) fc.cnt[f] = (uint32_t)m;
+        return;
+    }
     uint64_t last = 0, m = 0;
     for (uint64_t base = c0; base < c1; base += 64) {
         const uint64_t j = base + lane;
@@ -103,7 +174,7 @@ __global__ __launch_bounds__(64) void files_compact(FilesChunk fc, const uint64_
     uint64_t c0, c1;
     file_cand_range(fc, total, f, c0, c1);
     if (c0 > fc.cap_cand) c0 = fc.cap_cand;
-    const uint64_t *src = fc.slots + c0 + f;
+    const uint64_t *src = fc.slots + c0 + f + (fc.extra ? fc.extra[f] : 0);
     const uint64_t o = chunk_off[f], n = fc.cnt[f], base = fc.off[f];
     for (uint64_t j = threadIdx.x; j < n; j += 64) {
         const uint64_t e = src[j], b = j ? src[j - 1] : 0;
@@ -140,6 +211,14 @@ hipError_t launch_files_select(const FilesChunk &fc, uint32_t w, uint64_t min_ch
                                hipStream_t s) {
     if (fc.n_files == 0) return hipSuccess;
     files_select<<<fc.n_files, 64, 0, s>>>(fc, w, min_chunk ? min_chunk : 1, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_select_max(const uint64_t *starts, const uint64_t *n_starts_dev, uint32_t w, uint64_t len,
+                                   uint64_t min_chunk, uint64_t max_chunk, uint64_t *ends, uint64_t cap,
+                                   uint64_t *n_chunks_dev, hipStream_t s) {
+    select_max_kernel<<<1, 64, 0, s>>>(starts, n_starts_dev, w, len, min_chunk ? min_chunk : 1, max_chunk, ends, cap,
+                                       n_chunks_dev);
     return hipGetLastError();
 }
 

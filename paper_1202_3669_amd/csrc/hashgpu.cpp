@@ -664,7 +664,9 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     if (pr->window == 0 || pr->window > HG_MAX_WINDOW)
         return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
     if (pr->stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
-    if (pr->max_chunk != 0) return fail(ctx, HG_EINVAL, "max_chunk must be 0");
+    const uint64_t step = pr->min_chunk ? pr->min_chunk : 1;
+    if (pr->max_chunk != 0 && pr->max_chunk < step)
+        return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
     if (!n_chunks) return fail(ctx, HG_EINVAL, "n_chunks is NULL");
     if (capacity && !ends) return fail(ctx, HG_EINVAL, "ends is NULL with capacity > 0");
     if (len && !in) return fail(ctx, HG_EINVAL, "in is NULL");
@@ -686,20 +688,28 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
     uint64_t n_cand;
     HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
-    // Chunks <= candidates + 1: the boundary decision writes straight into
-    // the caller's device buffer when it is that large.
-    const bool ends_direct = out_dev && capacity >= n_cand + 1;
+    // Chunks <= candidates + 1 (+ len / max_chunk forced cuts): the boundary
+    // decision writes straight into the caller's device buffer when it is
+    // that large.
+    const uint64_t bound = n_cand + 1 + (pr->max_chunk ? 1 + len / pr->max_chunk : 0);
+    const bool ends_direct = out_dev && capacity >= bound;
     void *cand, *dends = ends;
     HG_TRY(ensure(ctx, SLOT_CAND, n_cand * 8, st, &cand));
-    if (!ends_direct) HG_TRY(ensure(ctx, SLOT_ENDS, (n_cand + 1) * 8, st, &dends));
+    if (!ends_direct) HG_TRY(ensure(ctx, SLOT_ENDS, bound * 8, st, &dends));
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
               hg::launch_window_scan_emit(plan, din, len, pr->window, pr->stride, pr->mask, pr->target, ws,
                                           (uint64_t *)cand, n_cand, st));
-    void *sel;
-    HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(n_cand), st, &sel));
-    HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
-              hg::launch_chunk_select((const uint64_t *)cand, &small[0], n_cand, pr->window, len,
-                                      pr->min_chunk, sel, (uint64_t *)dends, n_cand + 1, &small[1], st));
+    if (pr->max_chunk) {
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_chunk_select_max((const uint64_t *)cand, &small[0], pr->window, len, pr->min_chunk,
+                                              pr->max_chunk, (uint64_t *)dends, bound, &small[1], st));
+    } else {
+        void *sel;
+        HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(n_cand), st, &sel));
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_chunk_select((const uint64_t *)cand, &small[0], n_cand, pr->window, len,
+                                          pr->min_chunk, sel, (uint64_t *)dends, n_cand + 1, &small[1], st));
+    }
     // The chunk count sizes the outputs; the digests are enqueued after it.
     uint64_t nc;
     HG_TRY(read_u64(ctx, &small[1], st, &nc));
@@ -711,10 +721,10 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
         void *ddig = chunk_digests;
         if (!direct) HG_TRY(ensure(ctx, SLOT_DIG, (nc + 1) * (uint64_t)dd, st, &ddig));
         void *segs;
-        HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(n_cand + 1), st, &segs));
+        HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(bound), st, &segs));
         HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
                   hg::launch_segment_digests(pr->chunk_digest, din, len, nullptr, (const uint64_t *)dends,
-                                             &small[1], n_cand + 1, (uint8_t *)ddig, segs, st));
+                                             &small[1], bound, (uint8_t *)ddig, segs, st));
         if (!direct) HG_TRY(copy_out(ctx, chunk_digests, ddig, k * (uint64_t)dd, out_dev, st));
     }
     if (out_dev && !count_host) HG_TRY(copy_out(ctx, n_chunks, &small[1], 8, true, st));
@@ -888,6 +898,7 @@ struct hg_batch {
     std::vector<void *> allocs;
     // device tables
     uint64_t *d_off = nullptr, *d_len = nullptr, *d_leaf_first = nullptr, *d_first_tile = nullptr;
+    uint64_t *d_extra = nullptr;  // with a maximum chunk size: forced-cut slots before each file
     hg::FileTile *d_tiles = nullptr;
     uint32_t *d_order = nullptr;
     hg_block_job *d_jobs = nullptr;
@@ -961,7 +972,7 @@ int batch_chunk(hg_batch *b, const uint8_t *arena, const hg_batch_out *out, hipS
     hg::FilesChunk fc{b->d_off, b->d_len, b->d_first_tile,
                       hg::window_scan_tile_offsets(b->wsp, b->d_ws),
                       b->wsp.n_tiles, b->d_cand, b->cap_cand, b->d_slots, b->d_cnt, b->d_seg_start,
-                      b->d_seg_end, b->n};
+                      b->d_seg_end, b->n, c.max_chunk, b->d_extra};
     HG_HIP(b->ctx, hg::launch_files_select(fc, c.window, c.min_chunk, out->status, st));
     HG_HIP(b->ctx, hg::launch_files_compact(fc, out->chunk_off, out->chunk_ends, b->max_chunks, out->status, st));
     if (out->chunk_digests)
@@ -1017,7 +1028,8 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
             return fail(ctx, HG_EINVAL, "unknown chunk digest");
         if (p.chunk.window > HG_MAX_WINDOW) return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
         if (p.chunk.stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
-        if (p.chunk.max_chunk != 0) return fail(ctx, HG_EINVAL, "max_chunk must be 0");
+        if (p.chunk.max_chunk != 0 && p.chunk.max_chunk < std::max<uint64_t>(p.chunk.min_chunk, 1))
+            return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
     }
     hg_batch *b = new hg_batch();
     b->ctx = ctx;
@@ -1072,6 +1084,18 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
                                            : (uint64_t)(2.0 * prob * (double)b->total_windows) + 64ull * n_files + 4096;
             b->cap_cand = std::min<uint64_t>(b->cap_cand, b->total_windows);
             b->max_chunks = b->cap_cand + n_files;
+            if (p.chunk.max_chunk) {
+                // Each file also gets room for its forced cuts (at most
+                // len / max_chunk of them).
+                std::vector<uint64_t> extra(std::max<uint32_t>(n_files, 1), 0);
+                uint64_t acc = 0;
+                for (uint32_t f = 0; f < n_files; f++) {
+                    extra[f] = acc;
+                    acc += b->len[f] / p.chunk.max_chunk;
+                }
+                b->max_chunks += acc;
+                if ((st = batch_upload(b, extra, &b->d_extra)) != HG_OK) break;
+            }
             if ((st = batch_upload(b, first_tile, &b->d_first_tile)) != HG_OK) break;
             if ((st = batch_upload(b, tiles, &b->d_tiles)) != HG_OK) break;
             if ((st = batch_alloc(b, hg::window_scan_scratch_bytes(b->wsp), &b->d_ws)) != HG_OK) break;

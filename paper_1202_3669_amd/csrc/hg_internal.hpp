@@ -91,6 +91,11 @@ hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t 
 // for sizing the grids; scratch is chunk_select_scratch_bytes(n_starts).
 // Writes up to cap ends and *n_chunks_dev.
 size_t chunk_select_scratch_bytes(uint64_t n_starts);
+// The same decision with a maximum chunk size (forced cuts), by one
+// wavefront; cap >= n_starts + 2 + len / max_chunk holds every cut.
+hipError_t launch_chunk_select_max(const uint64_t *starts, const uint64_t *n_starts_dev, uint32_t w, uint64_t len,
+                                   uint64_t min_chunk, uint64_t max_chunk, uint64_t *ends, uint64_t cap,
+                                   uint64_t *n_chunks_dev, hipStream_t s);
 hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint64_t n_starts,
                                uint32_t w, uint64_t len, uint64_t min_chunk, void *scratch, uint64_t *ends,
                                uint64_t cap, uint64_t *n_chunks_dev, hipStream_t s);
@@ -121,6 +126,8 @@ struct FilesChunk {
     uint32_t *cnt;                    // chunks per file
     uint64_t *seg_start, *seg_end;    // absolute arena offsets, cap_cand + n_files
     uint32_t n_files;
+    uint64_t max_chunk;               // 0: no maximum chunk size
+    const uint64_t *extra;            // with max_chunk: extra slots before file f (forced cuts), else null
 };
 // status[0] = candidates (written by the prefix pass), status[1] = chunks,
 // status[2] = nonzero when the candidate capacity was exceeded.

@@ -223,7 +223,8 @@ int validate(const hg_request *r) {
     } else if (r->kind == HG_REQ_CHUNK) {
         const hg_chunk_params &c = r->chunk;
         if (dbytes(c.window_digest) < 0 || dbytes(c.chunk_digest) < 0) return HG_EINVAL;
-        if (c.window == 0 || c.window > HG_MAX_WINDOW || c.stride == 0 || c.max_chunk != 0) return HG_EINVAL;
+        if (c.window == 0 || c.window > HG_MAX_WINDOW || c.stride == 0) return HG_EINVAL;
+        if (c.max_chunk != 0 && c.max_chunk < (c.min_chunk ? c.min_chunk : 1)) return HG_EINVAL;
         if (!r->n_chunks || (r->capacity && !r->chunk_ends)) return HG_EINVAL;
     } else {
         return HG_EINVAL;
@@ -353,6 +354,9 @@ bool fits(const Group &g, const hg_server_cfg &cfg, const Req *q) {
     if (g.bytes + r.len > cfg.max_group_bytes) return false;
     const Need n = need_of(r);
     if (r.kind == HG_REQ_BLOCK) return g.leaf_used + n.leaf_bytes <= g.leaf_cap;
+    // A maximum chunk size needs per-file room for forced cuts: such
+    // requests are served alone.
+    if (r.chunk.max_chunk != 0) return false;
     if (!g.chunks.empty() && !same_chunk_params(g.cp, r.chunk)) return false;
     return g.tiles + n.tiles <= g.tile_cap && g.cand + n.cand <= g.cand_cap;
 }
@@ -493,7 +497,8 @@ int enqueue_chunks(Group &g, const uint8_t *arena, bool want_dig) {
     SV_HIP(hg::launch_window_scan_emit(wsp, nullptr, 0, c.window, c.stride, c.mask, c.target, g.d_ws, g.d_cand,
                                        g.cand_cap, st, &files));
     hg::FilesChunk fc{g.d_off, g.d_len, g.d_first_tile, hg::window_scan_tile_offsets(wsp, g.d_ws),
-                      wsp.n_tiles, g.d_cand, g.cand_cap, g.d_slots, g.d_cnt, g.d_seg_start, g.d_seg_end, n};
+                      wsp.n_tiles, g.d_cand, g.cand_cap, g.d_slots, g.d_cnt, g.d_seg_start, g.d_seg_end, n,
+                      0, nullptr};
     SV_HIP(hg::launch_files_select(fc, c.window, c.min_chunk, g.d_status, st));
     SV_HIP(hg::launch_files_compact(fc, g.d_chunk_off, g.d_ends, g.max_chunks, g.d_status, st));
     if (want_dig)

@@ -276,7 +276,8 @@ class Context:
 
     def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
               window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
-              capacity: int | None = None, stream=None, out=None, asynchronous: bool = False):
+              capacity: int | None = None, stream=None, out=None, asynchronous: bool = False,
+              max_chunk: int = 0):
         """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks.
         With out = (ends, digests) preallocated CUDA tensors (capacity =
         len(ends)) the results are written there and views returned; with
@@ -285,7 +286,7 @@ class Context:
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = data.numel()
-        p = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
+        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
         d = DIGEST_SIZE[chunk_digest]
         total = _u64(0)
         if out is not None:
@@ -304,6 +305,8 @@ class Context:
             capacity = 1 + min(nwin, 4096 + nwin // 1024)
             if min_chunk:
                 capacity = min(capacity, n // min_chunk + 1)
+            if max_chunk:
+                capacity += n // max_chunk + 1
         for _ in range(2):
             ends = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
             dig = torch.empty((max(capacity, 1), d), dtype=torch.uint8, device=dev) if digests else None
@@ -440,7 +443,7 @@ class Batch:
                  block_digest: int = HG_SHA1, roots: bool = True, window: int = 20, stride: int = 1,
                  mask: int = 0xFFF, target: int = 0, min_chunk: int = 2048,
                  window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
-                 max_candidates: int = 0):
+                 max_candidates: int = 0, max_chunk: int = 0):
         torch = _torch()
         import numpy as np
         self.ctx = ctx
@@ -448,7 +451,7 @@ class Batch:
         ln = np.ascontiguousarray(lengths, dtype=np.uint64)
         self.n = int(off.size)
         p = hg_batch_params(block_size, block_digest, 1 if roots else 0,
-                            hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest,
+                            hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest,
                                             chunk_digest), max_candidates)
         h = _vp()
         ctx._check(hg_batch_create(ctx.handle, off.ctypes.data if self.n else None,
@@ -588,19 +591,19 @@ class RequestSet:
     def __init__(self, pool_ptr: int, in_device: bool, specs, block_size: int = 64 * 1024,
                  window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
                  min_chunk: int = 2048, window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
-                 fail=()):
+                 fail=(), max_chunk: int = 0):
         import numpy as np
         specs = [(int(k), int(o), int(n)) for k, o, n in specs]
         self.specs = specs
         n = len(specs)
         self.reqs = (hg_request * max(n, 1))()
-        cp = hg_chunk_params(window, stride, mask, target, min_chunk, 0, window_digest, chunk_digest)
+        cp = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
         self.chunk_params = cp
         dc = DIGEST_SIZE[chunk_digest]
         leaf_n, cap = [], []
         for k, o, ln in specs:
             leaf_n.append((ln + block_size - 1) // block_size if k != 2 else 0)
-            cap.append(ln // max(min_chunk, 1) + 1 if k == 2 else 0)
+            cap.append(ln // max(min_chunk, 1) + 1 + (ln // max_chunk if max_chunk else 0) if k == 2 else 0)
         self._leaf_buf = np.zeros(max(sum(leaf_n) * 20, 1), dtype=np.uint8)
         self._root_buf = np.zeros((max(n, 1), 20), dtype=np.uint8)
         self._end_buf = np.zeros(max(sum(cap), 1), dtype=np.uint64)

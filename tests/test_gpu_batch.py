@@ -132,6 +132,24 @@ def test_batch_graph_replays_match_eager(ctx, hg):
     b.close()
 
 
+def test_batch_with_max_chunk(ctx, hg):
+    arena, off, ln = small_batch(906, 40)
+    d = torch.from_numpy(arena).cuda()
+    note("batch with a maximum chunk size")
+    b = hg.Batch(ctx, off, ln, max_chunk=3000)
+    b.run(d)
+    fetch(b)
+    assert b._st[2] == 0
+    for j in range(len(off)):
+        data = arena[int(off[j]):int(off[j]) + int(ln[j])]
+        starts = oracle.window_scan(oracle.MD5, data, 20, 1, 0xFFF, 0)
+        ends = oracle.chunk_select(starts, 20, data.size, 2048, 3000)
+        c0, c1 = int(b._co[j]), int(b._co[j + 1])
+        assert np.array_equal(b._ce[c0:c1].astype(np.uint64), ends), f"file {j} chunk ends"
+        assert np.array_equal(b._cd[c0:c1], oracle.chunk_digests(oracle.SHA1, data, ends)), f"file {j} digests"
+    b.close()
+
+
 def test_batch_reports_candidate_overflow(ctx, hg):
     arena, off, ln = small_batch(903, 20, extra_tiny=False)
     d = torch.from_numpy(arena).cuda()

@@ -285,6 +285,37 @@ def test_chunk_cases(ctx, case):
         assert np.array_equal(host(dig), exp_dig)
 
 
+# Maximum chunk size (forced cuts): (length, w, s, mask, target, min, max).
+MAX_CASES = [(0, 20, 1, 0xFF, 0, 2048, 4096), (100, 20, 1, 0xFF, 0, 0, 7),
+             (200_003, 20, 1, 0xFFF, 0, 2048, 8192), (200_003, 20, 1, 0xFF, 0, 2048, 2048),
+             (300_000, 20, 1, 0xFFFFF, 0, 0, 1000),          # almost no candidates: forced runs
+             (1_000_000, 20, 1, 0x3F, 0, 100, 150),          # dense candidates, tight max
+             (1_000_000, 20, 4, 0x7FF, 3, 3000, 5000), (2_000_003, 20, 1, 0xFFF, 0, 2048, 65536),
+             (777_777, 33, 2, 0x1FF, 1, 1, 1)]               # max = step = 1: every byte a chunk
+
+
+@pytest.mark.parametrize("case", MAX_CASES)
+def test_chunk_with_max(ctx, case):
+    length, w, s, mask, target, mn, mx = case
+    if mn == 1 and mx == 1:
+        length = 5000  # one chunk per byte: keep it small
+    data = inputs.uniform_bytes(450 + length % 97, length)
+    starts = oracle.window_scan_sharded(0, data, w, s, mask, target, THREADS)
+    exp_ends = oracle.chunk_select(starts, w, data.size, mn, mx)
+    exp_dig = oracle.chunk_digests(1, data, exp_ends)
+    for off in (0, 3):
+        note(f"chunk max case={case} off={off}")
+        ends, dig = ctx.chunk(dev(data, off), w, s, mask, target, mn, max_chunk=mx)
+        assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+        assert np.array_equal(host(dig), exp_dig)
+
+
+def test_chunk_max_rejects_max_below_min(ctx, hg):
+    d = dev(inputs.uniform_bytes(451, 1000))
+    with pytest.raises(hg.HashGpuError):
+        ctx.chunk(d, 20, 1, 0xF, 0, 100, max_chunk=50)
+
+
 def test_chunk_truncation(ctx, hg):
     data = inputs.uniform_bytes(402, 300_000)
     exp_ends, exp_dig = _oracle_chunks(data, 20, 1, 0xFF, 0, 1024)
@@ -453,7 +484,7 @@ def test_invalid_arguments(ctx, hg):
                              s) == hg.HG_EINVAL
     assert hg.hg_window_scan(ctx.handle, d.data_ptr(), 1000, 20, 1, 0, 0, 0, None, 0,
                              cnt.data_ptr(), hg.HG_ASYNC, s) == hg.HG_EINVAL
-    p = hg.hg_chunk_params(20, 1, 0, 0, 0, 4096, 0, 1)  # max_chunk unsupported
+    p = hg.hg_chunk_params(20, 1, 0, 0, 100, 50, 0, 1)  # max_chunk below min_chunk
     assert hg.hg_chunk(ctx.handle, d.data_ptr(), 1000, ctypes.byref(p), None, 0, cnt.data_ptr(),
                        None, fl, s) == hg.HG_EINVAL
     buf = ctypes.create_string_buffer(256)
