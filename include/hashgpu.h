@@ -246,6 +246,42 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
                   const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
                   uint64_t *matched_bytes, uint32_t flags, void *stream);
 
+/* ---------------------------------------------------- streaming chunker -- */
+
+/* Content-based chunking of a stream fed in pieces (Sec. 3.2.4: data is
+ * buffered, each buffer is chunked on the GPU, and the bytes after its last
+ * boundary carry over to the next buffer).  The concatenation of the chunks
+ * that all feeds and the finish return is exactly what hg_chunk returns for
+ * the whole stream with the same parameters.  The device holds only the
+ * carry (the bytes from the last decided cut, and w - 1 before it, to the end
+ * of the data fed) plus the piece being fed.  A chunker serves one caller at
+ * a time on its context. */
+typedef struct hg_chunker hg_chunker;
+
+int hg_chunker_create(hg_ctx *ctx, const hg_chunk_params *params, hg_chunker **out);
+void hg_chunker_destroy(hg_chunker *c);
+
+/* *bound = the most chunks one feed of len bytes (or the finish, len = 0)
+ * can return; the capacity passed must be at least this. */
+int hg_chunker_bound(const hg_chunker *c, uint64_t len, uint64_t *bound);
+
+/* Appends data[0, len) (HG_IN_DEVICE: device memory, else host memory) and
+ * returns the chunks the bytes known so far determine: *n_chunks of them,
+ * ends[] as absolute stream offsets ascending (a chunk starts where the
+ * previous one -- of this or an earlier call -- ended, the first at 0), and
+ * their digests (NULL: not wanted).  Outputs are device pointers with
+ * HG_OUT_DEVICE (then n_chunks too, unless HG_COUNT_HOST), host pointers
+ * otherwise.  Synchronous.  HG_EINVAL when capacity < hg_chunker_bound. */
+int hg_chunker_feed(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends,
+                    uint64_t capacity, uint64_t *n_chunks, void *chunk_digests, void *stream);
+
+/* Ends the stream: returns the remaining chunks, the last one ending at the
+ * stream's length.  Afterwards only hg_chunker_reset (start a new stream)
+ * or hg_chunker_destroy are accepted. */
+int hg_chunker_finish(hg_chunker *c, uint32_t flags, uint64_t *ends, uint64_t capacity, uint64_t *n_chunks,
+                      void *chunk_digests, void *stream);
+int hg_chunker_reset(hg_chunker *c);
+
 /* -------------------------------------------------------- file batches -- */
 
 /* A planned batch of many files held in one device arena: every file gets

@@ -505,6 +505,22 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void add_u64_kernel(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
+                               const uint64_t *__restrict__ n_dev, uint64_t add) {
+    const uint64_t n = *n_dev;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] + add;
+}
+
+hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_dev, uint64_t max_n, uint64_t add,
+                          hipStream_t s) {
+    if (max_n == 0) return hipSuccess;
+    uint64_t blocks = (max_n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    add_u64_kernel<<<(unsigned)blocks, 256, 0, s>>>(dst, src, n_dev, add);
+    return hipGetLastError();
+}
+
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
                              const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
                              int log2_slots, unsigned long long *counters, hipStream_t s) {

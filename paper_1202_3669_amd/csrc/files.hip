@@ -33,57 +33,88 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
            __builtin_amdgcn_readlane((uint32_t)v, l);
 }
 
-// One wavefront: the cuts of one block of length L from its ascending
-// candidate starts cand[c0, c1), with the minimum step and a maximum chunk
-// size maxc > 0 (forced cuts, see hg_chunk).  From the previous cut `last`,
-// a ballot finds the first candidate end e >= last + step; while it lies
-// more than maxc past `last`, cuts are forced at last + maxc.  A run of f
-// forced cuts ends when e comes within maxc (then e is the next cut) or
+// One wavefront: the cuts of a block of length L from its ascending
+// candidate starts cand[c0, c1) (each shifted by `add`), starting after a
+// cut at `last0`, with the minimum step and a maximum chunk size maxc
+// (0 = none; forced cuts, see hg_chunk).  From the previous cut `last`, a
+// ballot finds the first candidate end e >= last + step below L; while it
+// lies more than maxc past `last`, cuts are forced at last + maxc.  A run of
+// f forced cuts ends when e comes within maxc (then e is the next cut) or
 // falls below last + step (then later candidates are looked at), so f is
-// known in closed form and the lanes write the run together.  Writes cut i
-// to out[i] for i < cap; returns the number of cuts.
-__device__ uint64_t walk_cuts_max(const uint64_t *__restrict__ cand, uint64_t c0, uint64_t c1, uint32_t w,
-                                  uint64_t L, uint64_t step, uint64_t maxc, uint64_t *__restrict__ out,
-                                  uint64_t cap) {
+// known in closed form and the lanes write the run together.  With `final`
+// the remaining forced cuts before L and the end L itself follow; without
+// it the walk stops at the last cut it can decide below L.  Cut i is written
+// as (cut - last0) to out[i] for i < cap; returns the number of cuts and
+// leaves the last cut in *last_out.
+__device__ uint64_t walk_cuts(const uint64_t *__restrict__ cand, uint64_t c0, uint64_t c1, uint64_t add,
+                              uint32_t w, uint64_t L, uint64_t last0, uint64_t step, uint64_t maxc, bool final,
+                              uint64_t *__restrict__ out, uint64_t cap, uint64_t *last_out) {
     const int lane = threadIdx.x & 63;
-    uint64_t last = 0, m = 0;
+    uint64_t last = last0, m = 0;
     for (uint64_t base = c0; base < c1; base += 64) {
         const uint64_t j = base + lane;
         const bool valid = j < c1;
-        const uint64_t e = valid ? cand[j] + w : ~0ull;
+        const uint64_t e = valid ? cand[j] + add + w : ~0ull;
         const bool usable = valid && e < L;
         while (true) {
-            const uint64_t thr = last + step;  // last < L and step <= maxc: no overflow
+            const uint64_t thr = last + step;  // last < L and step <= L: no overflow
             const uint64_t elig = __ballot(usable && e >= thr);
             if (elig == 0) break;
             const uint64_t en = readlane64(e, __builtin_ctzll(elig));
             const uint64_t d = en - last;
-            if (d > maxc) {
+            if (maxc && d > maxc) {
                 const uint64_t fa = (d - 1) / maxc;         // until en - last <= maxc
                 const uint64_t fb = (d - step) / maxc + 1;  // until en < last + step
                 const uint64_t f = fa < fb ? fa : fb;
                 for (uint64_t i = lane; i < f; i += 64)
-                    if (m + i < cap) out[m + i] = last + (i + 1) * maxc;
+                    if (m + i < cap) out[m + i] = last + (i + 1) * maxc - last0;
                 m += f;
                 last += f * maxc;
                 continue;
             }
-            if (lane == 0 && m < cap) out[m] = en;
+            if (lane == 0 && m < cap) out[m] = en - last0;
             m++;
             last = en;
         }
     }
-    if (L > 0) {
-        if (L - last > maxc) {
-            const uint64_t f = (L - last - 1) / maxc;
-            for (uint64_t i = lane; i < f; i += 64)
-                if (m + i < cap) out[m + i] = last + (i + 1) * maxc;
-            m += f;
-        }
-        if (lane == 0 && m < cap) out[m] = L;
-        m++;
+    // Forced cuts before L: with `final` up to the end; otherwise only those
+    // that lie below L (the bytes up to L are known).
+    if (maxc && L > last && L - last > maxc) {
+        const uint64_t f = (L - last - 1) / maxc;
+        for (uint64_t i = lane; i < f; i += 64)
+            if (m + i < cap) out[m + i] = last + (i + 1) * maxc - last0;
+        m += f;
+        last += f * maxc;
     }
+    if (final && L > last0) {
+        if (lane == 0 && m < cap) out[m] = L - last0;
+        m++;
+        last = L;
+    }
+    *last_out = last;
     return m;
+}
+
+__device__ __forceinline__ uint64_t walk_cuts_max(const uint64_t *__restrict__ cand, uint64_t c0, uint64_t c1,
+                                                  uint32_t w, uint64_t L, uint64_t step, uint64_t maxc,
+                                                  uint64_t *__restrict__ out, uint64_t cap) {
+    uint64_t last;
+    return walk_cuts(cand, c0, c1, 0, w, L, 0, step, maxc, true, out, cap, &last);
+}
+
+// Streaming: cuts of a carried buffer whose first chunk starts at last0,
+// candidates at cand + add.  out_state[0] = number of cuts, [1] = last cut.
+__global__ __launch_bounds__(64) void stream_walk_kernel(const uint64_t *__restrict__ cand,
+                                                        const uint64_t *__restrict__ n_dev, uint64_t add, uint32_t w,
+                                                        uint64_t L, uint64_t last0, uint64_t step, uint64_t maxc,
+                                                        int final, uint64_t *__restrict__ out, uint64_t cap,
+                                                        uint64_t *__restrict__ out_state) {
+    uint64_t last;
+    const uint64_t m = walk_cuts(cand, 0, *n_dev, add, w, L, last0, step, maxc, final != 0, out, cap, &last);
+    if (threadIdx.x == 0) {
+        out_state[0] = m;
+        out_state[1] = last;
+    }
 }
 
 __global__ __launch_bounds__(64) void select_max_kernel(const uint64_t *__restrict__ cand,
@@ -219,6 +250,14 @@ hipError_t launch_chunk_select_max(const uint64_t *starts, const uint64_t *n_sta
                                    uint64_t *n_chunks_dev, hipStream_t s) {
     select_max_kernel<<<1, 64, 0, s>>>(starts, n_starts_dev, w, len, min_chunk ? min_chunk : 1, max_chunk, ends, cap,
                                        n_chunks_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_walk(const uint64_t *cand, const uint64_t *n_dev, uint64_t add, uint32_t w, uint64_t len,
+                              uint64_t last0, uint64_t min_chunk, uint64_t max_chunk, bool final, uint64_t *ends,
+                              uint64_t cap, uint64_t *state, hipStream_t s) {
+    stream_walk_kernel<<<1, 64, 0, s>>>(cand, n_dev, add, w, len, last0, min_chunk ? min_chunk : 1, max_chunk,
+                                        final ? 1 : 0, ends, cap, state);
     return hipGetLastError();
 }
 

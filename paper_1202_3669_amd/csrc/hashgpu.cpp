@@ -1249,3 +1249,206 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
 }
 
 }  // extern "C"
+
+// ============================================================ streaming chunker
+
+// Content-based chunking of a stream fed in pieces (Sec. 3.2.4: the written
+// data is buffered, each full buffer is chunked on the GPU, and the bytes
+// after the last boundary carry into the next buffer).  The device holds
+// only the carry -- the bytes from the last decided cut (and w - 1 before
+// it, for windows that straddle it) to the end of the data fed so far --
+// plus the new piece.  Each feed scans that buffer's windows on the stream's
+// absolute stride grid, decides every cut the known bytes determine, hashes
+// the completed chunks, and keeps the rest.
+struct hg_chunker {
+    hg_ctx *ctx = nullptr;
+    hg_chunk_params p{};
+    uint64_t pos = 0;       // bytes fed so far
+    uint64_t last = 0;      // last decided cut (absolute)
+    uint64_t base = 0;      // absolute offset of the first carried byte
+    uint8_t *buf[2] = {nullptr, nullptr};
+    uint64_t cap[2] = {0, 0};
+    int cur = 0;            // buffer holding [cur_start, pos)
+    uint64_t cur_start = 0; // absolute offset of buf[cur][0]
+    bool finished = false;
+};
+
+namespace {
+
+int chunker_grow(hg_chunker *c, int i, uint64_t bytes, hipStream_t st) {
+    if (c->cap[i] >= bytes) return HG_OK;
+    const uint64_t want = std::max<uint64_t>(bytes + bytes / 4, 1 << 20);
+    HG_HIP(c->ctx, hipStreamSynchronize(st));
+    if (c->buf[i]) HG_HIP(c->ctx, hipFree(c->buf[i]));
+    c->buf[i] = nullptr;
+    c->cap[i] = 0;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c->ctx, HG_ENOMEM, "chunker buffer of %llu bytes", (unsigned long long)want);
+    }
+    c->buf[i] = (uint8_t *)p;
+    c->cap[i] = want;
+    return HG_OK;
+}
+
+// Cuts one call can emit for `len` new bytes.
+uint64_t chunker_bound(const hg_chunker *c, uint64_t len) {
+    const uint64_t span = (c->pos - c->last) + len;
+    const uint64_t step = c->p.min_chunk ? c->p.min_chunk : 1;
+    return span / step + 2 + (c->p.max_chunk ? span / c->p.max_chunk + 1 : 0);
+}
+
+int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends, uint64_t capacity,
+                 uint64_t *n_out, void *digests, void *stream, bool final) {
+    hg_ctx *ctx = c->ctx;
+    HG_TRY(enter(ctx));
+    const bool count_host = flags & HG_COUNT_HOST;
+    flags &= ~(uint32_t)HG_COUNT_HOST;
+    HG_TRY(check_flags(ctx, flags, false));
+    if (c->finished) return fail(ctx, HG_EINVAL, "the stream is finished (hg_chunker_reset starts a new one)");
+    if (len && !data) return fail(ctx, HG_EINVAL, "data is NULL");
+    if (!n_out) return fail(ctx, HG_EINVAL, "n_chunks is NULL");
+    const uint64_t bound = chunker_bound(c, len);
+    if (capacity < bound)
+        return fail(ctx, HG_EINVAL, "capacity %llu below the bound %llu (hg_chunker_bound)",
+                    (unsigned long long)capacity, (unsigned long long)bound);
+    if (!ends) return fail(ctx, HG_EINVAL, "ends is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    const hg_chunk_params &p = c->p;
+    // The working buffer: carry [base, pos) then the new bytes.
+    const uint64_t carry = c->pos - c->base, wlen = carry + len;
+    const int nxt = 1 - c->cur;
+    HG_TRY(chunker_grow(c, nxt, wlen, st));
+    uint8_t *W = c->buf[nxt];
+    if (carry) HG_HIP(ctx, hipMemcpyAsync(W, c->buf[c->cur] + (c->base - c->cur_start), carry,
+                                           hipMemcpyDeviceToDevice, st));
+    if (len) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, in_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                        st));
+    const uint64_t a0 = c->base, last0 = c->last - a0;
+    // Windows on the stream's stride grid: the first at an absolute multiple
+    // of the stride at or after a0.
+    const uint64_t s_ = p.stride, b0 = (s_ - a0 % s_) % s_;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    uint64_t n_cand = 0;
+    void *cand = nullptr;
+    if (wlen >= b0 + p.window) {
+        const hg::WsPlan plan = hg::plan_window_scan(W + b0, wlen - b0, p.window, s_, p.window_digest);
+        void *ws;
+        HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
+        HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+                  hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));
+        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
+        HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
+        HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(n_cand, 1) * 8, st, &cand));
+        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
+                  hg::launch_window_scan_emit(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws,
+                                              (uint64_t *)cand, n_cand, st));
+    } else {
+        HG_TRY(ensure(ctx, SLOT_CAND, 8, st, &cand));
+        HG_HIP(ctx, hg::launch_fill_u32((uint32_t *)&small[0], 2, 0, st));
+    }
+    void *rel;
+    HG_TRY(ensure(ctx, SLOT_ENDS, bound * 8, st, &rel));
+    HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+              hg::launch_stream_walk((const uint64_t *)cand, &small[0], b0, p.window, wlen, last0, p.min_chunk,
+                                     p.max_chunk, final, (uint64_t *)rel, bound, &small[2], st));
+    HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, &small[2], 16, hipMemcpyDeviceToHost, st));
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    const uint64_t k = ctx->host_small[0], last_w = ctx->host_small[1];
+    if (k > bound) return fail(ctx, HG_EDEVICE, "internal: %llu cuts above the bound", (unsigned long long)k);
+    // Outputs: absolute ends, digests of the completed chunks.
+    const uint64_t abs_add = a0 + last0;
+    if (k) {
+        if (out_dev) {
+            HG_HIP(ctx, hg::launch_add_u64(ends, (const uint64_t *)rel, &small[2], bound, abs_add, st));
+        } else {
+            HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
+        }
+        if (digests) {
+            const int dd = digest_bytes(p.chunk_digest);
+            void *ddig = digests, *segs;
+            if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
+            HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(k), st, &segs));
+            HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
+                      hg::launch_segment_digests(p.chunk_digest, W + last0, wlen - last0, nullptr,
+                                                 (const uint64_t *)rel, &small[2], k, (uint8_t *)ddig, segs, st));
+            if (!out_dev) HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
+        }
+    }
+    if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &small[2], 8, hipMemcpyDeviceToDevice, st));
+    else *n_out = k;
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    if (!out_dev)
+        for (uint64_t i = 0; i < k; i++) ends[i] += abs_add;
+    // New carry: from w - 1 bytes before the last cut (windows straddling it).
+    c->cur = nxt;
+    c->cur_start = a0;
+    c->pos += len;
+    c->last = a0 + last_w;
+    const uint64_t pre = std::min<uint64_t>(p.window - 1, c->last);
+    c->base = c->last - pre;
+    if (final) c->finished = true;
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hg_chunker_create(hg_ctx *ctx, const hg_chunk_params *params, hg_chunker **out) {
+    HG_TRY(enter(ctx));
+    if (!params || !out) return fail(ctx, HG_EINVAL, "params or out is NULL");
+    *out = nullptr;
+    const hg_chunk_params &p = *params;
+    if (digest_bytes(p.window_digest) < 0 || digest_bytes(p.chunk_digest) < 0)
+        return fail(ctx, HG_EINVAL, "unknown digest");
+    if (p.window == 0 || p.window > HG_MAX_WINDOW)
+        return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
+    if (p.stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
+    if (p.max_chunk != 0 && p.max_chunk < std::max<uint64_t>(p.min_chunk, 1))
+        return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
+    hg_chunker *c = new hg_chunker();
+    c->ctx = ctx;
+    c->p = p;
+    *out = c;
+    return HG_OK;
+}
+
+int hg_chunker_bound(const hg_chunker *c, uint64_t len, uint64_t *bound) {
+    if (!c || !bound) return HG_EINVAL;
+    *bound = chunker_bound(c, len);
+    return HG_OK;
+}
+
+int hg_chunker_feed(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends,
+                    uint64_t capacity, uint64_t *n_chunks, void *chunk_digests, void *stream) {
+    if (!c) return HG_EINVAL;
+    return chunker_step(c, data, len, flags, ends, capacity, n_chunks, chunk_digests, stream, false);
+}
+
+int hg_chunker_finish(hg_chunker *c, uint32_t flags, uint64_t *ends, uint64_t capacity, uint64_t *n_chunks,
+                      void *chunk_digests, void *stream) {
+    if (!c) return HG_EINVAL;
+    return chunker_step(c, nullptr, 0, flags | HG_IN_DEVICE, ends, capacity, n_chunks, chunk_digests, stream, true);
+}
+
+int hg_chunker_reset(hg_chunker *c) {
+    if (!c) return HG_EINVAL;
+    c->pos = c->last = c->base = c->cur_start = 0;
+    c->finished = false;
+    return HG_OK;
+}
+
+void hg_chunker_destroy(hg_chunker *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < 2; i++)
+        if (c->buf[i]) (void)hipFree(c->buf[i]);
+    delete c;
+}
+
+}  // extern "C"

@@ -111,6 +111,15 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
                                   const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
                                   void *scratch, hipStream_t s);
 
+// Streaming boundary decision over a carried buffer of len bytes whose
+// first chunk starts at last0: candidate starts cand[i] + add (ascending,
+// *n_dev of them).  Writes the cuts it can decide (relative to last0) to
+// ends (up to cap) and state[0] = their number, state[1] = the last cut;
+// with `final` the chunk ending at len is included.
+hipError_t launch_stream_walk(const uint64_t *cand, const uint64_t *n_dev, uint64_t add, uint32_t w, uint64_t len,
+                              uint64_t last0, uint64_t min_chunk, uint64_t max_chunk, bool final, uint64_t *ends,
+                              uint64_t cap, uint64_t *state, hipStream_t s);
+
 // ---------------------------------------------------------------- files --
 // Content-based chunking of many files (see files.hip).  cand: candidate
 // starts (file-relative, files in order) with capacity cap_cand; the tile
@@ -167,6 +176,10 @@ hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const
 uint64_t alu_probe_ops(uint32_t blocks, uint32_t steps);
 hipError_t launch_alu_probe(uint32_t blocks, uint32_t steps, uint32_t *out, hipStream_t s);
 hipError_t launch_read_probe(const uint8_t *p, uint64_t len, uint32_t *out, hipStream_t s);
+
+// dst[i] = src[i] + add for i < *n_dev (<= max_n, which sizes the grid).
+hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_dev, uint64_t max_n, uint64_t add,
+                          hipStream_t s);
 
 // Fill n 32-bit words with v (a kernel, so that captured graphs hold no
 // memset nodes).

@@ -117,6 +117,12 @@ hg_timing_read = _declare("hg_timing_read", _int,
                           [_vp, _int, ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_double)])
 hg_timing_reset = _declare("hg_timing_reset", _int, [_vp])
 hg_timing_origin = _declare("hg_timing_origin", _int, [_vp, _vp])
+hg_chunker_create = _declare("hg_chunker_create", _int, [_vp, ctypes.POINTER(hg_chunk_params), ctypes.POINTER(_vp)])
+hg_chunker_destroy = _declare("hg_chunker_destroy", None, [_vp])
+hg_chunker_bound = _declare("hg_chunker_bound", _int, [_vp, _u64, ctypes.POINTER(_u64)])
+hg_chunker_feed = _declare("hg_chunker_feed", _int, [_vp, _vp, _u64, _u32, _vp, _u64, _vp, _vp, _vp])
+hg_chunker_finish = _declare("hg_chunker_finish", _int, [_vp, _u32, _vp, _u64, _vp, _vp, _vp])
+hg_chunker_reset = _declare("hg_chunker_reset", _int, [_vp])
 hg_probe_alu = _declare("hg_probe_alu", _int, [_vp, ctypes.POINTER(ctypes.c_double), _vp])
 hg_probe_read = _declare("hg_probe_read", _int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_double), _vp])
 hg_block_hash_dual = _declare("hg_block_hash_dual", _int, [_vp, _vp, _u64, _u64, _vp, _vp, _vp, _vp, _u32, _vp])
@@ -141,7 +147,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_batch_replay", "hg_batch_tune", "hg_server_start", "hg_submit", "hg_wait",
             "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop",
             "hg_timing_origin", "hg_timing_intervals", "hg_probe_alu", "hg_probe_read",
-            "hg_block_hash_dual"]
+            "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
+            "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset"]
 
 
 class HashGpuError(RuntimeError):
@@ -654,3 +661,63 @@ class RequestSet:
             return ("block", self.leaves[i].copy(), bytes(self.root[i]))
         m = int(self.n_chunks[i])
         return ("chunk", self.ends[i][:m].copy(), self.digests[i][:m].copy())
+
+
+class Chunker:
+    """A streaming content-based chunker (hg_chunker) on a Context.
+
+    feed(piece) takes a uint8 CUDA tensor or numpy array and returns
+    (ends, digests) numpy arrays of the chunks decided so far (absolute
+    stream offsets); finish() returns the rest.
+    """
+
+    def __init__(self, ctx: Context, window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
+                 min_chunk: int = 2048, max_chunk: int = 0, window_digest: int = HG_MD5,
+                 chunk_digest: int = HG_SHA1):
+        self.ctx = ctx
+        self.d = DIGEST_SIZE[chunk_digest]
+        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
+        h = _vp()
+        ctx._check(hg_chunker_create(ctx.handle, ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            hg_chunker_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, fn, data, stream):
+        import numpy as np
+        n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
+        b = _u64(0)
+        self.ctx._check(hg_chunker_bound(self.handle, n, ctypes.byref(b)))
+        cap = int(b.value)
+        ends = np.zeros(cap, dtype=np.uint64)
+        dig = np.zeros((cap, self.d), dtype=np.uint8)
+        cnt = _u64(0)
+        if fn == "feed":
+            is_dev = hasattr(data, "is_cuda") and data.is_cuda
+            ptr = (data.data_ptr() if is_dev else data.ctypes.data) if n else None
+            st = hg_chunker_feed(self.handle, ptr, n, HG_IN_DEVICE if is_dev else 0, ends.ctypes.data, cap,
+                                 ctypes.byref(cnt), dig.ctypes.data, _stream_handle(stream))
+        else:
+            st = hg_chunker_finish(self.handle, 0, ends.ctypes.data, cap, ctypes.byref(cnt), dig.ctypes.data,
+                                   _stream_handle(stream))
+        self.ctx._check(st)
+        k = int(cnt.value)
+        return ends[:k].copy(), dig[:k].copy()
+
+    def feed(self, data, stream=None):
+        return self._call("feed", data, stream)
+
+    def finish(self, stream=None):
+        return self._call("finish", None, stream)
+
+    def reset(self):
+        self.ctx._check(hg_chunker_reset(self.handle))

@@ -1,0 +1,141 @@
+"""GPU tests of the streaming chunker (hg_chunker_*): a stream fed in pieces
+-- random sizes, pieces shorter than a window, empty pieces, pieces that end
+on a cut, host and device memory -- gives exactly the chunks of the oracle's
+one-shot chunking of the whole stream (bit-exact ends and digests), for
+several window/stride/minimum/maximum settings.  Inputs: seeded uniform
+bytes, and bytes with long runs of zeros (no candidates for long stretches,
+so the carry grows and forced cuts happen)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_3669_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+THREADS = max(1, min(16, os.cpu_count() or 1))
+KiB, MiB = 1 << 10, 1 << 20
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hg():
+    from paper_1202_3669_amd import hashgpu
+    return hashgpu
+
+
+@pytest.fixture(scope="module")
+def ctx(hg):
+    c = hg.Context(0)
+    yield c
+    c.close()
+
+
+def one_shot(data, w, s, mask, target, mn, mx):
+    starts = oracle.window_scan_sharded(oracle.MD5, data, w, s, mask, target, THREADS)
+    ends = oracle.chunk_select(starts, w, data.size, mn, mx)
+    return ends, oracle.chunk_digests(oracle.SHA1, data, ends)
+
+
+def pieces(rng, n, cuts=()):
+    """Random split points of [0, n), including empty and tiny pieces and the
+    given offsets."""
+    pts = set(int(x) for x in rng.integers(0, n + 1, size=int(rng.integers(1, 12))))
+    pts |= {int(c) for c in cuts if 0 <= c <= n}
+    pts |= {min(n, 5), min(n, 5)}  # an early tiny piece and an empty one
+    pts = sorted(pts | {0, n})
+    out = [(a, b) for a, b in zip(pts[:-1], pts[1:])] or [(0, 0)]
+    out.insert(min(2, len(out)), (0, 0))  # an empty piece
+    return out
+
+
+CASES = [  # (length, w, s, mask, target, min, max)
+    (3 * MiB + 11, 20, 1, 0xFFF, 0, 2048, 0),
+    (1 * MiB + 5, 20, 1, 0xFF, 0, 0, 0),        # min below w: windows straddling a cut matter
+    (1 * MiB + 7, 48, 4, 0x1FF, 3, 100, 0),     # stride 4 on the absolute grid
+    (2 * MiB + 1, 20, 1, 0xFFF, 0, 2048, 8192),
+    (1 * MiB, 33, 3, 0x3F, 1, 10, 50),          # dense candidates, tight maximum
+    (0, 20, 1, 0xFFF, 0, 2048, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("device_input", [True, False])
+def test_stream_equals_one_shot(ctx, hg, case, device_input):
+    length, w, s, mask, target, mn, mx = case
+    data = inputs.uniform_bytes(500 + length % 89, length)
+    exp_ends, exp_dig = one_shot(data, w, s, mask, target, mn, mx)
+    rng = np.random.default_rng(501 + length % 13)
+    # include split points exactly at some cuts and just after them
+    cuts = exp_ends[:: max(1, exp_ends.size // 5)].tolist()
+    splits = pieces(rng, length, cuts + [c + 1 for c in cuts])
+    note(f"stream case={case} device={device_input} pieces={len(splits)}")
+    ch = hg.Chunker(ctx, w, s, mask, target, mn, mx)
+    dev = torch.from_numpy(data).cuda() if device_input else None
+    got_e, got_d = [], []
+    for a, b in splits:
+        piece = dev[a:b] if device_input else data[a:b]
+        e, d = ch.feed(piece)
+        got_e.append(e)
+        got_d.append(d)
+    e, d = ch.finish()
+    got_e.append(e)
+    got_d.append(d)
+    ends = np.concatenate(got_e)
+    dig = np.concatenate(got_d).reshape(-1, 20)
+    assert np.array_equal(ends, exp_ends)
+    assert np.array_equal(dig, exp_dig)
+    # reuse after reset: one piece
+    ch.reset()
+    e1, d1 = ch.feed(data)
+    e2, d2 = ch.finish()
+    assert np.array_equal(np.concatenate([e1, e2]), exp_ends)
+    ch.close()
+
+
+def test_stream_long_runs_without_candidates(ctx, hg):
+    # Zero runs: with a target that the all-zero window does not hit, no
+    # candidates for 3 MiB stretches; without a maximum the carry grows to
+    # the whole run, with one the cuts are forced.
+    zeros = np.zeros(64, dtype=np.uint8)
+    hit = {int(x) for x in range(4096) if oracle.window_scan(oracle.MD5, zeros, 20, 1, 0xFFF, x).size}
+    target = next(t for t in range(4096) if t not in hit)
+    rnd = inputs.uniform_bytes(510, 2 * MiB)
+    data = np.concatenate([rnd[:MiB], np.zeros(3 * MiB, np.uint8), rnd[MiB:]])
+    for mx in (0, 65536):
+        exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, target, 2048, mx)
+        ch = hg.Chunker(ctx, 20, 1, 0xFFF, target, 2048, mx)
+        note(f"zero runs max={mx}")
+        out_e, out_d = [], []
+        for a in range(0, data.size, 700_001):
+            e, d = ch.feed(data[a:a + 700_001])
+            out_e.append(e)
+            out_d.append(d)
+        e, d = ch.finish()
+        out_e.append(e)
+        out_d.append(d)
+        assert np.array_equal(np.concatenate(out_e), exp_ends)
+        assert np.array_equal(np.concatenate(out_d).reshape(-1, 20), exp_dig)
+        ch.close()
+
+
+def test_stream_rejects_small_capacity_and_use_after_finish(ctx, hg):
+    import ctypes
+    ch = hg.Chunker(ctx)
+    data = inputs.uniform_bytes(520, 100_000)
+    ends = np.zeros(4, dtype=np.uint64)
+    n = ctypes.c_uint64(0)
+    assert hg.hg_chunker_feed(ch.handle, data.ctypes.data, data.size, 0, ends.ctypes.data, 4,
+                              ctypes.byref(n), None, None) == hg.HG_EINVAL
+    ch.feed(data)
+    ch.finish()
+    with pytest.raises(hg.HashGpuError):
+        ch.feed(data)
+    ch.close()
