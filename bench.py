@@ -355,6 +355,22 @@ def breakdown(torch, hg, data, host_pinned):
                                         "Gwindows_per_s": round(((n - 20) // st + 1) / t / 1e6, 1)}
         t = statistics.median(timed(lambda: ctx.chunk(data, 20, st, 0xFFF, 0, 2 * KiB), reps=3))
         res[f"chunk_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1)}
+    # Streaming chunker: the 1 GiB fed in 64 MiB pieces (device-resident,
+    # and from pinned host memory: host-to-device copy included).
+    for where, src in (("device", data), ("pinned_host", host_pinned)):
+        def stream_all():
+            ch = hg.Chunker(ctx)
+            for a in range(0, n, 64 * MiB):
+                ch.feed(src[a:a + 64 * MiB] if where == "device" else src[a:a + 64 * MiB].numpy())
+            ch.finish()
+            ch.close()
+        stream_all()  # warm-up: scratch sized once
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stream_all()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[f"chunk_stream_64MiB_{where}"] = {"GBps": round(n / dt / 1e9, 1), "ms": round(dt * 1e3, 2)}
     # Host-to-device included: pinned host input streamed through the library.
     for k in (0, 1):
         ts = timed(lambda: ctx.block_hash(host_pinned, 64 * KiB, k, root=False), reps=5)
