@@ -66,7 +66,7 @@ enum {
     HG_EBUSY = -5    /* resource temporarily unavailable */
 };
 
-/* Flags.  HG_LEN_ENDS applies to hg_similarity only; HG_BACKGROUND to the
+/* Flags.  HG_LEN_ENDS applies to hg_similarity and hg_blockmap_write only; HG_BACKGROUND to the
  * batch calls only; HG_COUNT_HOST to hg_chunk only. */
 enum {
     HG_IN_DEVICE = 1u,
@@ -245,6 +245,32 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
 int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b,
                   const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
                   uint64_t *matched_bytes, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------ block map -- */
+
+/* The block-map of a content-addressable store (Sec. 3.2.1: written data is
+ * cut into chunks identified by their digests, and only chunks the store
+ * does not hold yet are stored): the digests of every chunk stored so far,
+ * kept on the device across writes. */
+typedef struct hg_blockmap hg_blockmap;
+
+/* capacity: the most digests the map will hold (1 .. 2^30). */
+int hg_blockmap_create(hg_ctx *ctx, int digest, uint64_t capacity, hg_blockmap **out);
+void hg_blockmap_destroy(hg_blockmap *m);
+int hg_blockmap_size(const hg_blockmap *m, uint64_t *n);
+
+/* Writes one version's n chunk digests, in order: chunk i is a duplicate iff
+ * its digest is in the map already or equals the digest of a chunk j < i of
+ * this write; every other chunk is new and its digest is added.  is_dup
+ * (n bytes, 1 = duplicate) may be NULL; *dup_chunks and *dup_bytes (host
+ * pointers, may be NULL) receive the number of duplicates and the sum of
+ * their lengths (len_b: n lengths, or with HG_LEN_ENDS the chunk end offsets
+ * hg_chunk returns; NULL: bytes not counted) -- the bytes a store need not
+ * write.  digests and len_b are device pointers with HG_IN_DEVICE, is_dup
+ * with HG_OUT_DEVICE.  Synchronous.  HG_EBUSY when the map could overflow
+ * (size + n > capacity); nothing is changed then. */
+int hg_blockmap_write(hg_blockmap *m, const void *digests, const uint64_t *len_b, uint64_t n, uint32_t flags,
+                      uint8_t *is_dup, uint64_t *dup_chunks, uint64_t *dup_bytes, void *stream);
 
 /* ---------------------------------------------------- streaming chunker -- */
 

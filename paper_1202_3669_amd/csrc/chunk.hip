@@ -421,25 +421,7 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
 }
 
 // ------------------------------------------------------------ similarity --
-// Digests are uniformly distributed, so their first 8 bytes serve as the
-// slot hash directly.
-template <int D>
-__device__ __forceinline__ uint64_t dig_hash(const uint8_t *d) {
-    uint64_t h;
-    __builtin_memcpy(&h, d, 8);
-    return h;
-}
-
-template <int D>
-__device__ __forceinline__ bool dig_equal(const uint8_t *x, const uint8_t *y) {
-    uint32_t a[D / 4], b[D / 4];
-    __builtin_memcpy(a, x, D);
-    __builtin_memcpy(b, y, D);
-    uint32_t diff = 0;
-#pragma unroll
-    for (int i = 0; i < D / 4; i++) diff |= a[i] ^ b[i];
-    return diff == 0;
-}
+// Digest keys and comparison: dig_hash / dig_equal (hg_device.hpp).
 
 template <int D>
 __global__ __launch_bounds__(256) void set_insert(const uint8_t *__restrict__ dig_a, uint64_t n_a,

@@ -1452,3 +1452,158 @@ void hg_chunker_destroy(hg_chunker *c) {
 }
 
 }  // extern "C"
+
+// ============================================================ block map
+
+struct hg_blockmap {
+    hg_ctx *ctx = nullptr;
+    int kind = 0, d = 0;
+    uint64_t capacity = 0, slots = 0, size = 0;
+    uint8_t *store = nullptr;
+    uint32_t *table = nullptr;
+    unsigned long long *words = nullptr;  // [0] stored digests, [1..2] counters of a write
+    // per-write scratch, grown on demand
+    uint64_t scratch_n = 0;
+    uint8_t *state = nullptr, *dup = nullptr, *dig_in = nullptr;
+    uint32_t *slot_of = nullptr;
+    uint64_t *pos_of = nullptr, *len_in = nullptr;
+};
+
+namespace {
+
+void blockmap_free_scratch(hg_blockmap *m) {
+    for (void *p : {(void *)m->state, (void *)m->dup, (void *)m->dig_in, (void *)m->slot_of, (void *)m->pos_of,
+                    (void *)m->len_in})
+        if (p) (void)hipFree(p);
+    m->state = m->dup = m->dig_in = nullptr;
+    m->slot_of = nullptr;
+    m->pos_of = m->len_in = nullptr;
+    m->scratch_n = 0;
+}
+
+int blockmap_scratch(hg_blockmap *m, uint64_t n, hipStream_t st) {
+    if (m->scratch_n >= n) return HG_OK;
+    HG_HIP(m->ctx, hipStreamSynchronize(st));
+    blockmap_free_scratch(m);
+    const uint64_t k = std::max<uint64_t>(n + n / 4, 4096);
+    void *p[6] = {};
+    const size_t bytes[6] = {k, k, k * (size_t)m->d, k * 4, k * 8, k * 8};
+    for (int i = 0; i < 6; i++) {
+        if (hipMalloc(&p[i], bytes[i]) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int j = 0; j < i; j++) (void)hipFree(p[j]);
+            return fail(m->ctx, HG_ENOMEM, "block-map scratch for %llu chunks", (unsigned long long)n);
+        }
+    }
+    m->state = (uint8_t *)p[0];
+    m->dup = (uint8_t *)p[1];
+    m->dig_in = (uint8_t *)p[2];
+    m->slot_of = (uint32_t *)p[3];
+    m->pos_of = (uint64_t *)p[4];
+    m->len_in = (uint64_t *)p[5];
+    m->scratch_n = k;
+    return HG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hg_blockmap_create(hg_ctx *ctx, int digest, uint64_t capacity, hg_blockmap **out) {
+    HG_TRY(enter(ctx));
+    if (!out) return fail(ctx, HG_EINVAL, "out is NULL");
+    *out = nullptr;
+    const int d = digest_bytes(digest);
+    if (d < 0) return fail(ctx, HG_EINVAL, "unknown digest %d", digest);
+    if (capacity == 0 || capacity > (1ull << 30)) return fail(ctx, HG_EINVAL, "capacity must be in [1, 2^30]");
+    hg_blockmap *m = new hg_blockmap();
+    m->ctx = ctx;
+    m->kind = digest;
+    m->d = d;
+    m->capacity = capacity;
+    m->slots = 1;
+    while (m->slots < 2 * capacity) m->slots <<= 1;  // load factor <= 1/2
+    void *a = nullptr, *b = nullptr, *c = nullptr;
+    if (hipMalloc(&a, capacity * (size_t)d) != hipSuccess || hipMalloc(&b, m->slots * 4) != hipSuccess ||
+        hipMalloc(&c, 64) != hipSuccess) {
+        (void)hipGetLastError();
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        delete m;
+        return fail(ctx, HG_ENOMEM, "block map of %llu digests", (unsigned long long)capacity);
+    }
+    m->store = (uint8_t *)a;
+    m->table = (uint32_t *)b;
+    m->words = (unsigned long long *)c;
+    int st = HG_OK;
+    if (hg::launch_fill_u32(m->table, m->slots, 0, nullptr) != hipSuccess ||
+        hg::launch_fill_u32((uint32_t *)m->words, 16, 0, nullptr) != hipSuccess ||
+        hipStreamSynchronize(nullptr) != hipSuccess)
+        st = fail(ctx, HG_EDEVICE, "block map initialisation failed");
+    if (st != HG_OK) {
+        (void)hipFree(a);
+        (void)hipFree(b);
+        (void)hipFree(c);
+        delete m;
+        return st;
+    }
+    *out = m;
+    return HG_OK;
+}
+
+void hg_blockmap_destroy(hg_blockmap *m) {
+    if (!m) return;
+    (void)hipSetDevice(m->ctx->device);
+    (void)hipDeviceSynchronize();
+    blockmap_free_scratch(m);
+    (void)hipFree(m->store);
+    (void)hipFree(m->table);
+    (void)hipFree(m->words);
+    delete m;
+}
+
+int hg_blockmap_size(const hg_blockmap *m, uint64_t *n) {
+    if (!m || !n) return HG_EINVAL;
+    *n = m->size;
+    return HG_OK;
+}
+
+int hg_blockmap_write(hg_blockmap *m, const void *digests, const uint64_t *len_b, uint64_t n, uint32_t flags,
+                      uint8_t *is_dup, uint64_t *dup_chunks, uint64_t *dup_bytes, void *stream) {
+    if (!m) return HG_EINVAL;
+    hg_ctx *ctx = m->ctx;
+    HG_TRY(enter(ctx));
+    const int len_is_ends = (flags & HG_LEN_ENDS) ? 1 : 0;
+    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_LEN_ENDS))
+        return fail(ctx, HG_EINVAL, "unknown flag bits 0x%x", flags);
+    if (n && !digests) return fail(ctx, HG_EINVAL, "digests is NULL");
+    if (m->size + n > m->capacity)
+        return fail(ctx, HG_EBUSY, "block map holds %llu of %llu digests; %llu more may not fit",
+                    (unsigned long long)m->size, (unsigned long long)m->capacity, (unsigned long long)n);
+    hipStream_t st = (hipStream_t)stream;
+    const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    HG_TRY(blockmap_scratch(m, std::max<uint64_t>(n, 1), st));
+    const uint8_t *dig = (const uint8_t *)digests;
+    const uint64_t *len = len_b;
+    if (!in_dev && n) {
+        HG_HIP(ctx, hipMemcpyAsync(m->dig_in, digests, n * (size_t)m->d, hipMemcpyHostToDevice, st));
+        dig = m->dig_in;
+        if (len_b) {
+            HG_HIP(ctx, hipMemcpyAsync(m->len_in, len_b, n * 8, hipMemcpyHostToDevice, st));
+            len = m->len_in;
+        }
+    }
+    uint8_t *dup_dev = is_dup ? (out_dev ? is_dup : m->dup) : nullptr;
+    hg::BlockMapView v{m->store, m->table, m->slots - 1, &m->words[0]};
+    HG_HIP(ctx, hg::launch_blockmap_write(m->kind, v, dig, n, len, len_is_ends, m->state, m->slot_of, m->pos_of,
+                                          dup_dev, &m->words[2], st));
+    if (is_dup && !out_dev && n) HG_HIP(ctx, hipMemcpyAsync(is_dup, m->dup, n, hipMemcpyDeviceToHost, st));
+    HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, m->words, 32, hipMemcpyDeviceToHost, st));
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    m->size = ctx->host_small[0];
+    if (dup_chunks) *dup_chunks = ctx->host_small[2];
+    if (dup_bytes) *dup_bytes = ctx->host_small[3];
+    return HG_OK;
+}
+
+}  // extern "C"

@@ -394,6 +394,26 @@ __device__ __forceinline__ void hash_range_dual(const uint8_t *p, uint64_t n, co
     finish_tail<KIND_SHA1>(ss, X, rem, n);
 }
 
+// Digests are uniformly distributed, so their first 8 bytes serve as a hash
+// table key directly.
+template <int D>
+__device__ __forceinline__ uint64_t dig_hash(const uint8_t *d) {
+    uint64_t h;
+    __builtin_memcpy(&h, d, 8);
+    return h;
+}
+
+template <int D>
+__device__ __forceinline__ bool dig_equal(const uint8_t *x, const uint8_t *y) {
+    uint32_t a[D / 4], b[D / 4];
+    __builtin_memcpy(a, x, D);
+    __builtin_memcpy(b, y, D);
+    uint32_t diff = 0;
+#pragma unroll
+    for (int i = 0; i < D / 4; i++) diff |= a[i] ^ b[i];
+    return diff == 0;
+}
+
 // Store a digest at `out` (any alignment).
 template <int KIND>
 __device__ __forceinline__ void store_digest(uint8_t *out, const uint32_t st[5]) {

@@ -177,6 +177,25 @@ uint64_t alu_probe_ops(uint32_t blocks, uint32_t steps);
 hipError_t launch_alu_probe(uint32_t blocks, uint32_t steps, uint32_t *out, hipStream_t s);
 hipError_t launch_read_probe(const uint8_t *p, uint64_t len, uint32_t *out, hipStream_t s);
 
+// -------------------------------------------------------------- block map --
+// The store's digests (capacity * digest size bytes), the open-addressing
+// table over them (slot_mask + 1 slots of uint32: 0 empty, k + 1 = stored
+// digest k) and the device count of stored digests.
+struct BlockMapView {
+    uint8_t *store;
+    uint32_t *table;
+    uint64_t slot_mask;
+    unsigned long long *size;
+};
+// One write of n chunk digests: is_dup[i] (optional) = 1 iff digest i was
+// stored before or equals that of a chunk j < i; counters[0] = duplicates,
+// counters[1] = their bytes (len: lengths, or ends with len_is_ends; may be
+// null).  Scratch: state (n bytes), slot_of (n x 4), pos_of (n x 8).  The
+// caller guarantees room for n more digests.
+hipError_t launch_blockmap_write(int kind, const BlockMapView &m, const uint8_t *dig, uint64_t n, const uint64_t *len,
+                                 int len_is_ends, uint8_t *state, uint32_t *slot_of, uint64_t *pos_of,
+                                 uint8_t *is_dup, unsigned long long *counters, hipStream_t s);
+
 // dst[i] = src[i] + add for i < *n_dev (<= max_n, which sizes the grid).
 hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_dev, uint64_t max_n, uint64_t add,
                           hipStream_t s);

@@ -123,6 +123,11 @@ hg_chunker_bound = _declare("hg_chunker_bound", _int, [_vp, _u64, ctypes.POINTER
 hg_chunker_feed = _declare("hg_chunker_feed", _int, [_vp, _vp, _u64, _u32, _vp, _u64, _vp, _vp, _vp])
 hg_chunker_finish = _declare("hg_chunker_finish", _int, [_vp, _u32, _vp, _u64, _vp, _vp, _vp])
 hg_chunker_reset = _declare("hg_chunker_reset", _int, [_vp])
+hg_blockmap_create = _declare("hg_blockmap_create", _int, [_vp, _int, _u64, ctypes.POINTER(_vp)])
+hg_blockmap_destroy = _declare("hg_blockmap_destroy", None, [_vp])
+hg_blockmap_size = _declare("hg_blockmap_size", _int, [_vp, ctypes.POINTER(_u64)])
+hg_blockmap_write = _declare("hg_blockmap_write", _int, [_vp, _vp, _vp, _u64, _u32, _vp, ctypes.POINTER(_u64),
+                                                         ctypes.POINTER(_u64), _vp])
 hg_probe_alu = _declare("hg_probe_alu", _int, [_vp, ctypes.POINTER(ctypes.c_double), _vp])
 hg_probe_read = _declare("hg_probe_read", _int, [_vp, _vp, _u64, ctypes.POINTER(ctypes.c_double), _vp])
 hg_block_hash_dual = _declare("hg_block_hash_dual", _int, [_vp, _vp, _u64, _u64, _vp, _vp, _vp, _vp, _u32, _vp])
@@ -148,7 +153,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_server_play", "hg_server_stats_read", "hg_server_stats_reset", "hg_server_stop",
             "hg_timing_origin", "hg_timing_intervals", "hg_probe_alu", "hg_probe_read",
             "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
-            "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset"]
+            "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset", "hg_blockmap_create",
+            "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write"]
 
 
 class HashGpuError(RuntimeError):
@@ -721,3 +727,49 @@ class Chunker:
 
     def reset(self):
         self.ctx._check(hg_chunker_reset(self.handle))
+
+
+class BlockMap:
+    """A persistent block-map (hg_blockmap) on a Context."""
+
+    def __init__(self, ctx: Context, digest: int = HG_SHA1, capacity: int = 1 << 22):
+        self.ctx = ctx
+        h = _vp()
+        ctx._check(hg_blockmap_create(ctx.handle, digest, capacity, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            hg_blockmap_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self) -> int:
+        n = _u64(0)
+        self.ctx._check(hg_blockmap_size(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def write(self, digests, ends=None, lengths=None, stream=None):
+        """Writes a version's chunk digests ((n, d) uint8 CUDA tensor or
+        numpy array); ends (chunk end offsets) or lengths, same placement.
+        Returns (is_dup numpy bool array, duplicate chunks, duplicate bytes)."""
+        import numpy as np
+        is_dev = hasattr(digests, "is_cuda") and digests.is_cuda
+        n = int(digests.shape[0])
+        lens = ends if ends is not None else lengths
+        flags = (HG_IN_DEVICE if is_dev else 0) | (HG_LEN_ENDS if ends is not None else 0)
+        ptr = (lambda a: (a.data_ptr() if is_dev else a.ctypes.data) if a is not None and n else None)
+        if lens is not None and not is_dev:
+            lens = np.ascontiguousarray(lens, dtype=np.uint64)
+        if not is_dev:
+            digests = np.ascontiguousarray(digests)
+        dup = np.zeros(max(n, 1), dtype=np.uint8)
+        c, b = _u64(0), _u64(0)
+        self.ctx._check(hg_blockmap_write(self.handle, ptr(digests), ptr(lens), n, flags, dup.ctypes.data,
+                                          ctypes.byref(c), ctypes.byref(b), _stream_handle(stream)))
+        return dup[:n].astype(bool), int(c.value), int(b.value)
