@@ -357,13 +357,13 @@ def breakdown(torch, hg, data, host_pinned):
         res[f"chunk_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1)}
     # Streaming chunker: the 1 GiB fed in 64 MiB pieces (device-resident,
     # and from pinned host memory: host-to-device copy included).
+    ch = hg.Chunker(ctx)
     for where, src in (("device", data), ("pinned_host", host_pinned)):
         def stream_all():
-            ch = hg.Chunker(ctx)
+            ch.reset()
             for a in range(0, n, 64 * MiB):
                 ch.feed(src[a:a + 64 * MiB] if where == "device" else src[a:a + 64 * MiB].numpy())
             ch.finish()
-            ch.close()
         stream_all()  # warm-up: scratch sized once
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -371,6 +371,7 @@ def breakdown(torch, hg, data, host_pinned):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[f"chunk_stream_64MiB_{where}"] = {"GBps": round(n / dt / 1e9, 1), "ms": round(dt * 1e3, 2)}
+    ch.close()
     # Host-to-device included: pinned host input streamed through the library.
     for k in (0, 1):
         ts = timed(lambda: ctx.block_hash(host_pinned, 64 * KiB, k, root=False), reps=5)

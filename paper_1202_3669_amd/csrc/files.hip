@@ -253,6 +253,61 @@ hipError_t launch_chunk_select_max(const uint64_t *starts, const uint64_t *n_sta
     return hipGetLastError();
 }
 
+// Streaming without a maximum: the candidates whose cut can never be taken
+// after last0 (end below last0 + step) form a prefix; the rest, shifted so
+// that last0 becomes 0, go to the parallel boundary decision.
+__global__ void stream_drop_kernel(const uint64_t *__restrict__ cand, const uint64_t *__restrict__ n_dev, uint64_t add,
+                                   uint32_t w, uint64_t limit, uint64_t *__restrict__ out_words) {
+    // One lane: binary search for the first candidate end >= limit.
+    const uint64_t n = *n_dev;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (cand[mid] + add + w < limit) lo = mid + 1;
+        else hi = mid;
+    }
+    out_words[0] = lo;      // dropped
+    out_words[1] = n - lo;  // kept
+}
+
+__global__ void stream_shift_kernel(const uint64_t *__restrict__ cand, const uint64_t *__restrict__ words,
+                                    uint64_t add, uint64_t last0, uint64_t *__restrict__ out) {
+    const uint64_t k = words[0], m = words[1];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+        out[i] = cand[k + i] + add - last0;
+}
+
+// The decided part of a parallel selection: the chunk count minus the
+// provisional final chunk (unless final), and the last decided end.
+__global__ void stream_tail_kernel(const uint64_t *__restrict__ n_chunks, const uint64_t *__restrict__ ends, int final,
+                                   uint64_t last0, uint64_t *__restrict__ state) {
+    const uint64_t nc = *n_chunks;
+    const uint64_t k = final ? nc : (nc ? nc - 1 : 0);
+    state[0] = k;
+    state[1] = last0 + (k ? ends[k - 1] : 0);
+}
+
+hipError_t launch_stream_drop(const uint64_t *cand, const uint64_t *n_dev, uint64_t add, uint32_t w, uint64_t limit,
+                              uint64_t *words, hipStream_t s) {
+    stream_drop_kernel<<<1, 1, 0, s>>>(cand, n_dev, add, w, limit, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_shift(const uint64_t *cand, const uint64_t *words, uint64_t max_m, uint64_t add,
+                               uint64_t last0, uint64_t *out, hipStream_t s) {
+    if (max_m == 0) return hipSuccess;
+    uint64_t blocks = (max_m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    stream_shift_kernel<<<(unsigned)blocks, 256, 0, s>>>(cand, words, add, last0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_tail(const uint64_t *n_chunks, const uint64_t *ends, bool final, uint64_t last0,
+                              uint64_t *state, hipStream_t s) {
+    stream_tail_kernel<<<1, 1, 0, s>>>(n_chunks, ends, final ? 1 : 0, last0, state);
+    return hipGetLastError();
+}
+
 hipError_t launch_stream_walk(const uint64_t *cand, const uint64_t *n_dev, uint64_t add, uint32_t w, uint64_t len,
                               uint64_t last0, uint64_t min_chunk, uint64_t max_chunk, bool final, uint64_t *ends,
                               uint64_t cap, uint64_t *state, hipStream_t s) {

@@ -42,6 +42,7 @@ enum Slot {
     SLOT_JOBS,     // device copy of a host job table
     SLOT_PLAN,     // batch plan
     SLOT_SMALL,    // counts and counters
+    SLOT_AUX,      // shifted candidate starts (streaming chunker)
     N_SLOTS
 };
 
@@ -1352,9 +1353,32 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     }
     void *rel;
     HG_TRY(ensure(ctx, SLOT_ENDS, bound * 8, st, &rel));
-    HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
-              hg::launch_stream_walk((const uint64_t *)cand, &small[0], b0, p.window, wlen, last0, p.min_chunk,
-                                     p.max_chunk, final, (uint64_t *)rel, bound, &small[2], st));
+    const uint64_t step = p.min_chunk ? p.min_chunk : 1;
+    if (p.max_chunk == 0 && n_cand > 0 && (step >= p.window || last0 == 0)) {
+        // The parallel boundary decision, on the candidates that can still
+        // be cuts, shifted so that the carried cut is offset 0; its final
+        // chunk is provisional unless the stream ends here.  (With step >= w
+        // no window that starts before the carried cut can still be a cut,
+        // so the shifted starts stay non-negative; otherwise the walk below
+        // decides.)
+        HG_HIP(ctx, hg::launch_stream_drop((const uint64_t *)cand, &small[0], b0, p.window, last0 + step, &small[4],
+                                           st));
+        uint64_t kept;
+        HG_TRY(read_u64(ctx, &small[5], st, &kept));
+        void *shifted, *sel;
+        HG_TRY(ensure(ctx, SLOT_AUX, std::max<uint64_t>(kept, 1) * 8, st, &shifted));
+        HG_HIP(ctx, hg::launch_stream_shift((const uint64_t *)cand, &small[4], kept, b0, last0, (uint64_t *)shifted,
+                                            st));
+        HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(kept), st, &sel));
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_chunk_select((const uint64_t *)shifted, &small[5], kept, p.window, wlen - last0,
+                                          p.min_chunk, sel, (uint64_t *)rel, bound, &small[6], st));
+        HG_HIP(ctx, hg::launch_stream_tail(&small[6], (const uint64_t *)rel, final, last0, &small[2], st));
+    } else {
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_stream_walk((const uint64_t *)cand, &small[0], b0, p.window, wlen, last0, p.min_chunk,
+                                         p.max_chunk, final, (uint64_t *)rel, bound, &small[2], st));
+    }
     HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, &small[2], 16, hipMemcpyDeviceToHost, st));
     HG_HIP(ctx, hipStreamSynchronize(st));
     const uint64_t k = ctx->host_small[0], last_w = ctx->host_small[1];

@@ -120,6 +120,19 @@ hipError_t launch_stream_walk(const uint64_t *cand, const uint64_t *n_dev, uint6
                               uint64_t last0, uint64_t min_chunk, uint64_t max_chunk, bool final, uint64_t *ends,
                               uint64_t cap, uint64_t *state, hipStream_t s);
 
+// Streaming without a maximum: words[0] = candidates whose end lies below
+// limit (a prefix), words[1] = the rest; stream_shift writes the rest as
+// starts relative to last0 (cand + add - last0); stream_tail turns a parallel
+// selection's count and ends (relative to last0) into state[0] = decided
+// chunks (the last one dropped unless final), state[1] = the last decided
+// end (last0 + ...; last0 when none).
+hipError_t launch_stream_drop(const uint64_t *cand, const uint64_t *n_dev, uint64_t add, uint32_t w, uint64_t limit,
+                              uint64_t *words, hipStream_t s);
+hipError_t launch_stream_shift(const uint64_t *cand, const uint64_t *words, uint64_t max_m, uint64_t add,
+                               uint64_t last0, uint64_t *out, hipStream_t s);
+hipError_t launch_stream_tail(const uint64_t *n_chunks, const uint64_t *ends, bool final, uint64_t last0,
+                              uint64_t *state, hipStream_t s);
+
 // ---------------------------------------------------------------- files --
 // Content-based chunking of many files (see files.hip).  cand: candidate
 // starts (file-relative, files in order) with capacity cap_cand; the tile
