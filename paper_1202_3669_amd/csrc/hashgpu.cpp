@@ -283,6 +283,49 @@ int device_input(hg_ctx *ctx, Slot s, const void *p, uint64_t n, bool on_device,
     return HG_OK;
 }
 
+// Window scan pass 1 over an input that is on the device or in host memory.
+// Host input is streamed into SLOT_IN in pieces; after each piece, the tiles
+// whose windows lie entirely in the bytes that have landed are launched, so
+// the copy of later pieces overlaps the hashing of earlier ones.
+int scan_tiles_from(hg_ctx *ctx, const void *in, uint64_t len, bool in_dev, uint32_t w, uint32_t s, uint32_t mask,
+                    uint32_t target, int kind, hipStream_t st, const uint8_t **din_out, hg::WsPlan *plan_out,
+                    void **ws_out) {
+    const uint8_t *din = (const uint8_t *)in;
+    if (!in_dev && len) {
+        void *p;
+        HG_TRY(ensure(ctx, SLOT_IN, len, st, &p));
+        din = (const uint8_t *)p;
+    }
+    const hg::WsPlan plan = hg::plan_window_scan(din, len, w, s, kind);
+    void *ws;
+    HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
+    if (in_dev || len == 0) {
+        HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st, hg::launch_window_scan_tiles(plan, din, len, w, s, mask, target, ws, st));
+    } else {
+        uint64_t t_done = 0;
+        HG_TRY(stream_in(ctx, (uint8_t *)din, (const uint8_t *)in, len, 1, st,
+                         [&](uint64_t off, uint64_t plen) -> int {
+                             const uint64_t avail = off + plen;
+                             uint64_t t_end = plan.n_tiles;
+                             if (avail < len) {
+                                 const uint64_t nw = avail >= w ? (avail - w) / s + 1 : 0;
+                                 t_end = std::min<uint64_t>(nw / plan.tile_windows, plan.n_tiles);
+                             }
+                             if (t_end > t_done) {
+                                 HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+                                           hg::launch_window_scan_tile_range(plan, din, len, w, s, mask, target, ws,
+                                                                             t_done, t_end, st));
+                                 t_done = t_end;
+                             }
+                             return HG_OK;
+                         }));
+    }
+    *din_out = din;
+    *plan_out = plan;
+    *ws_out = ws;
+    return HG_OK;
+}
+
 int check_flags(hg_ctx *ctx, uint32_t flags, bool async_ok) {
     if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC))
         return fail(ctx, HG_EINVAL, "unknown flag bits 0x%x", flags);
@@ -614,15 +657,12 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
     const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
 
     const uint8_t *din;
-    HG_TRY(device_input(ctx, SLOT_IN, in, len, in_dev, st, &din));
-    const hg::WsPlan plan = hg::plan_window_scan(din, len, window, stride, digest);
+    hg::WsPlan plan;
     void *ws;
-    HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
+    HG_TRY(scan_tiles_from(ctx, in, len, in_dev, window, stride, mask, target, digest, st, &din, &plan, &ws));
     uint64_t *small;
     HG_TRY(small_words(ctx, st, &small));
     uint64_t *total_dev = out_dev ? count : small;
-    HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
-              hg::launch_window_scan_tiles(plan, din, len, window, stride, mask, target, ws, st));
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, total_dev, st));
     if (out_dev) {
         HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
@@ -676,16 +716,13 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     const int dd = digest_bytes(pr->chunk_digest);
 
     const uint8_t *din;
-    HG_TRY(device_input(ctx, SLOT_IN, in, len, in_dev, st, &din));
+    hg::WsPlan plan;
+    void *ws;
+    HG_TRY(scan_tiles_from(ctx, in, len, in_dev, pr->window, pr->stride, pr->mask, pr->target, pr->window_digest, st,
+                           &din, &plan, &ws));
     uint64_t *small;
     HG_TRY(small_words(ctx, st, &small));
     // small[0]: candidate total, small[1]: chunk count.
-    const hg::WsPlan plan = hg::plan_window_scan(din, len, pr->window, pr->stride, pr->window_digest);
-    void *ws;
-    HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
-    HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
-              hg::launch_window_scan_tiles(plan, din, len, pr->window, pr->stride, pr->mask, pr->target,
-                                           ws, st));
     HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
     uint64_t n_cand;
     HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
@@ -1325,8 +1362,8 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     uint8_t *W = c->buf[nxt];
     if (carry) HG_HIP(ctx, hipMemcpyAsync(W, c->buf[c->cur] + (c->base - c->cur_start), carry,
                                            hipMemcpyDeviceToDevice, st));
-    if (len) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, in_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                        st));
+    const bool host_in = len && !in_dev;
+    if (len && in_dev) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, hipMemcpyDeviceToDevice, st));
     const uint64_t a0 = c->base, last0 = c->last - a0;
     // Windows on the stream's stride grid: the first at an absolute multiple
     // of the stride at or after a0.
@@ -1339,8 +1376,32 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         const hg::WsPlan plan = hg::plan_window_scan(W + b0, wlen - b0, p.window, s_, p.window_digest);
         void *ws;
         HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
-        HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
-                  hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));
+        if (host_in) {
+            // Host bytes arrive in pieces; the tiles whose windows have
+            // landed run while later pieces are copied.
+            uint64_t t_done = 0;
+            HG_TRY(stream_in(ctx, W + carry, (const uint8_t *)data, len, 1, st,
+                             [&](uint64_t off, uint64_t plen) -> int {
+                                 const uint64_t avail = carry + off + plen;
+                                 uint64_t t_end = plan.n_tiles;
+                                 if (avail < wlen) {
+                                     const uint64_t have = avail > b0 ? avail - b0 : 0;
+                                     const uint64_t nw = have >= p.window ? (have - p.window) / s_ + 1 : 0;
+                                     t_end = std::min<uint64_t>(nw / plan.tile_windows, plan.n_tiles);
+                                 }
+                                 if (t_end > t_done) {
+                                     HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+                                               hg::launch_window_scan_tile_range(plan, W + b0, wlen - b0, p.window,
+                                                                                 s_, p.mask, p.target, ws, t_done,
+                                                                                 t_end, st));
+                                     t_done = t_end;
+                                 }
+                                 return HG_OK;
+                             }));
+        } else {
+            HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+                      hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));
+        }
         HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
         HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
         HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(n_cand, 1) * 8, st, &cand));
@@ -1348,6 +1409,7 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                   hg::launch_window_scan_emit(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws,
                                               (uint64_t *)cand, n_cand, st));
     } else {
+        if (host_in) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, hipMemcpyHostToDevice, st));
         HG_TRY(ensure(ctx, SLOT_CAND, 8, st, &cand));
         HG_HIP(ctx, hg::launch_fill_u32((uint32_t *)&small[0], 2, 0, st));
     }

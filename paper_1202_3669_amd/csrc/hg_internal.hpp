@@ -71,6 +71,12 @@ const uint64_t *window_scan_tile_offsets(const WsPlan &p, const void *scratch);
 hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
                                     uint32_t s, uint32_t mask, uint32_t target, void *scratch,
                                     hipStream_t st, const WsFiles *files = nullptr);
+// Pass 1 for tiles [t0, t1) only (single buffer): a caller whose input
+// arrives in pieces runs the tiles whose windows have landed.
+hipError_t launch_window_scan_tile_range(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w, uint32_t s,
+                                         uint32_t mask, uint32_t target, void *scratch, uint64_t t0, uint64_t t1,
+                                         hipStream_t st);
+
 // Pass 2: exclusive scan of the tile counts, total to *total_dev, list of
 // overflowed tiles.
 hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev,

@@ -90,7 +90,8 @@ struct TileView {
 struct SingleSrc {
     const uint8_t *in;
     uint64_t len, nwin, tile_windows;
-    __device__ TileView view(uint64_t t) const { return {in, len, nwin, t * tile_windows}; }
+    uint64_t t0;  // first tile of the launch (a launch may cover a range of tiles)
+    __device__ TileView view(uint64_t t) const { return {in, len, nwin, (t0 + t) * tile_windows}; }
 };
 
 struct FileSrc {
@@ -488,8 +489,8 @@ WsPlan plan_window_scan_files(uint64_t n_tiles, uint64_t total_windows, uint32_t
 
 template <class Src>
 static hipError_t launch_tiles(const WsPlan &p, Src src, uint32_t w, uint32_t s, uint32_t mask, uint32_t target,
-                               const WsScratch &sc, hipStream_t st) {
-    const dim3 grid((unsigned)p.n_tiles), blk(WS_TPB);
+                               const WsScratch &sc, uint64_t n_tiles, hipStream_t st) {
+    const dim3 grid((unsigned)n_tiles), blk(WS_TPB);
     if (p.variant == 1) {
         ws_reg_count<20, 1, Src><<<grid, blk, 0, st>>>(src, mask, target, sc.tile_count, sc.bucket);
     } else if (p.variant == 2) {
@@ -510,8 +511,20 @@ hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t
     if (p.n_tiles == 0) return hipSuccess;
     WsScratch sc = carve(p, scratch);
     if (files) return launch_tiles(p, FileSrc{files->arena, files->off, files->len, files->tiles, w, s}, w, s,
-                                   mask, target, sc, st);
-    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows}, w, s, mask, target, sc, st);
+                                   mask, target, sc, p.n_tiles, st);
+    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows, 0}, w, s, mask, target, sc, p.n_tiles, st);
+}
+
+hipError_t launch_window_scan_tile_range(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w, uint32_t s,
+                                         uint32_t mask, uint32_t target, void *scratch, uint64_t t0, uint64_t t1,
+                                         hipStream_t st) {
+    if (t1 > p.n_tiles) t1 = p.n_tiles;
+    if (t0 >= t1) return hipSuccess;
+    WsScratch sc = carve(p, scratch);
+    // The kernels index their outputs by the launch's own tile number.
+    sc.tile_count += t0;
+    sc.bucket += t0 * WS_CAP;
+    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows, t0}, w, s, mask, target, sc, t1 - t0, st);
 }
 
 hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev, hipStream_t st) {
@@ -559,7 +572,7 @@ hipError_t launch_window_scan_emit(const WsPlan &p, const uint8_t *in, uint64_t 
     WsScratch sc = carve(p, scratch);
     if (files) return launch_emit(p, FileSrc{files->arena, files->off, files->len, files->tiles, w, s}, w, s,
                                   mask, target, sc, out, cap, st);
-    return launch_emit(p, SingleSrc{in, len, p.nwin, p.tile_windows}, w, s, mask, target, sc, out, cap, st);
+    return launch_emit(p, SingleSrc{in, len, p.nwin, p.tile_windows, 0}, w, s, mask, target, sc, out, cap, st);
 }
 
 }  // namespace hg
