@@ -20,14 +20,14 @@ second-level hash of a job is one sequential chain (for 4 KiB SHA-1 segments
 of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
 sequential chains per job.  Per step, chunking runs on stream SA[step % 3]
 (the window scan is the throughput engine; while one stream waits for its
-counts or runs its chunk digests, the others' window scans run) and the 4 KiB / 64 KiB segments on
-stream SB; for a group of G steps, the 1 MiB segments run as one batched
-launch on stream S1 and all second levels as one batched launch on stream
-S2, while the other streams carry on with the next group.  A step's latency
-therefore ends when its group's roots are done.  Five busy streams need as
-many hardware queues: HIP shares its default four queues among all streams
-of the process, so the benchmark asks for eight (GPU_MAX_HW_QUEUES, read
-when the HIP runtime starts).
+counts or runs its chunk digests, the others' window scans run) and the
+4 KiB / 64 KiB segments on stream SB; for a group of G = 24 steps, the 1 MiB
+segments run as one batched launch on stream S1 and all second levels as one
+batched launch on stream S2[group % 2], while the other streams carry on
+with the next group.  A step's latency therefore ends when its group's roots
+are done.  Seven busy streams need as many hardware queues: HIP shares its
+default four queues among all streams of the process, so the benchmark asks
+for eight (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
 
 value = hashed bytes per second: each of the 7 primitive passes (6 direct
 hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
@@ -75,7 +75,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=12)
-    ap.add_argument("--group", type=int, default=12, help="steps per long-chain batch")
+    ap.add_argument("--group", type=int, default=24, help="steps per long-chain batch")
+    ap.add_argument("--chunk-streams", type=int, default=CHUNK_STREAMS,
+                    help="chunking streams (steps go round-robin over them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=128)
@@ -108,11 +110,14 @@ class Pipeline:
         self.sa = [torch.cuda.Stream() for _ in range(self.NA)]
         self.sb = torch.cuda.Stream()
         self.s1 = torch.cuda.Stream()
-        self.s2 = torch.cuda.Stream()
+        # Second levels: two streams, alternating by group, so that the
+        # single-lane chains of consecutive groups (about 0.1 s for the 4 KiB
+        # SHA-1 one) overlap instead of queueing.
+        self.s2s = [torch.cuda.Stream(), torch.cuda.Stream()]
         self.ctxa = [hg.Context(0) for _ in range(self.NA)]
         self.ctx0 = hg.Context(0)
         self.ctx1 = hg.Context(0)
-        self.ctx2 = hg.Context(0)
+        self.ctx2 = [hg.Context(0), hg.Context(0)]
         self.ctx3 = hg.Context(0)
         dev = data.device
         n = data.numel()
@@ -139,7 +144,7 @@ class Pipeline:
         for parity in range(2):
             slots = range(parity * group, parity * group + group)
             self.long_tables.append(table(self.ctx1, [self.recs[s][0][j] for s in slots for j in LONG]))
-            self.early_tables.append(table(self.ctx2, [self.recs[s][0][j] for j in ROOT_EARLY for s in slots]))
+            self.early_tables.append(table(self.ctx2[parity], [self.recs[s][0][j] for j in ROOT_EARLY for s in slots]))
             self.late_tables.append(table(self.ctx3, [self.recs[s][0][j] for j in ROOT_LATE for s in slots]))
         self.group_done = {}
         self.issue_ev = {}
@@ -190,19 +195,20 @@ class Pipeline:
         parity = g % 2
         short_done = torch.cuda.Event()
         short_done.record(self.sb)
+        s2 = self.s2s[parity]
         self.s1.wait_event(short_done)
-        self.s2.wait_event(short_done)
+        s2.wait_event(short_done)
         lt, ln = self.long_tables[parity]
         et, en = self.early_tables[parity]
         zt, zn = self.late_tables[parity]
-        self.ctx2.run_batch(et, en, "roots", stream=self.s2)
+        self.ctx2[parity].run_batch(et, en, "roots", stream=s2)
         self.ctx1.run_batch(lt, ln, "leaves", stream=self.s1, background=True)
         self.ctx3.run_batch(zt, zn, "roots", stream=self.s1)
         s1_done = torch.cuda.Event()
         s1_done.record(self.s1)
-        self.s2.wait_event(s1_done)
+        s2.wait_event(s1_done)
         done = torch.cuda.Event(enable_timing=True)
-        done.record(self.s2)
+        done.record(s2)
         self.group_done[g] = done
 
     def run(self, first, count):
@@ -540,8 +546,9 @@ def main():
         sys.exit(2)
     # Three concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
-    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8:
-        os.environ["GPU_MAX_HW_QUEUES"] = "8"
+    queues = max(8, args.chunk_streams + 5)  # chunking streams + SB, S1, two S2, default
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import numpy as np
     import torch
     root = os.path.dirname(os.path.abspath(__file__))
@@ -579,6 +586,8 @@ def main():
     del prev
     torch.cuda.synchronize()
 
+    global CHUNK_STREAMS
+    CHUNK_STREAMS = args.chunk_streams
     pipe = Pipeline(torch, hg, data, prev_dig, args.group)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     pipe.run(0, args.warmup)
