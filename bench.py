@@ -84,6 +84,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-file batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the similarity workload and block-size sweep")
     ap.add_argument("--leaf-probe", action="store_true",
                     help="only hash the 1 GiB input with one lane per segment (MD5/SHA-1, 4 KiB and "
                          "64 KiB segments, 3 launches each, no second level), for counter runs")
@@ -436,6 +437,75 @@ def batched(torch, hg, inputs, data):
             "chunks": int(st[1]), "candidates": int(st[0]), "tuner": report}
 
 
+def similarity_sweep(torch, hg, inputs):
+    """Two versions of a 256 MiB file (seed 3; the second with 256 seeded
+    1-4 KiB inserts, deletes and overwrites, seed 4).  First the similarity
+    workload itself: content-based chunking (MD5 w=20, low 12 bits, min
+    2 KiB) at stride 1 and 4, count- and byte-weighted similarity.  Then the
+    block-size sweep of the checkpoint study (Fig. 11): fixed segments of
+    256 KiB, 1 MiB and 4 MiB (direct hash, SHA-1) against content-based
+    chunks tuned to a similar mean, with the system's bounds scaled from
+    256 KB / 4 MB around a 1 MB block (Sec. 4.3): min = size/4, max =
+    4 size, boundary mask of log2(size) bits.  Content-based chunk digests
+    are timed both as standard digests and as two-level direct hashes."""
+    a_np = inputs.uniform_bytes(3, 256 * MiB)
+    b_np, _ = inputs.edited_version(a_np, 4, 256)
+    a = torch.from_numpy(a_np).cuda()
+    b = torch.from_numpy(b_np).cuda()
+    nb = b.numel()
+    del a_np, b_np
+    ctx = hg.Context(0)
+    res = {"bytes_a": int(a.numel()), "bytes_b": int(nb), "edits": 256}
+
+    def cb(w_mask, mn, mx, st=1, seg=0):
+        ea, da = ctx.chunk(a, 20, st, w_mask, 0, mn, max_chunk=mx, chunk_segment=seg)
+        eb, db = ctx.chunk(b, 20, st, w_mask, 0, mn, max_chunk=mx, chunk_segment=seg)
+        m, mb = ctx.similarity(da, db, ends_b=eb)
+        ms = timed_ms(torch, lambda: ctx.chunk(b, 20, st, w_mask, 0, mn, max_chunk=mx, chunk_segment=seg),
+                      reps=3)
+        return {"chunks_b": int(eb.numel()), "mean_chunk_bytes": round(nb / max(int(eb.numel()), 1)),
+                "similarity": round(m / max(int(eb.numel()), 1), 4), "similarity_bytes": round(mb / nb, 4),
+                "chunk_ms": round(ms, 3), "chunk_GBps": round(nb / ms / 1e6, 1)}
+
+    for st in (1, 4):
+        res[f"cdc_min2k_s{st}"] = cb(0xFFF, 2 * KiB, 0, st)
+    sweep = {}
+    for size in (256 * KiB, MiB, 4 * MiB):
+        la = ctx.block_hash(a, size, hg.HG_SHA1, root=False)[0]
+        lb = ctx.block_hash(b, size, hg.HG_SHA1, root=False)[0]
+        lens = torch.full((lb.shape[0],), size, dtype=torch.int64, device=lb.device)
+        lens[-1] = nb - size * (lb.shape[0] - 1)
+        m, mb = ctx.similarity(la, lb, len_b=lens)
+        ms = timed_ms(torch, lambda: ctx.block_hash(b, size, hg.HG_SHA1))
+        fixed = {"blocks_b": int(lb.shape[0]), "similarity": round(m / lb.shape[0], 4),
+                 "similarity_bytes": round(mb / nb, 4), "hash_ms": round(ms, 3),
+                 "hash_GBps": round(nb / ms / 1e6, 1)}
+        # Each fixed block direct-hashed by the two-level construction (4 KiB
+        # segments): one batched call over all blocks, the roots are the ids.
+        specs = [(b[o:o + size], 4 * KiB, hg.HG_SHA1) for o in range(0, nb, size)]
+        _, roots_b = ctx.block_hash_batch(specs)
+        _, roots_a = ctx.block_hash_batch([(a[o:o + size], 4 * KiB, hg.HG_SHA1)
+                                           for o in range(0, a.numel(), size)])
+        m2, _ = ctx.similarity(torch.stack(roots_a), torch.stack(roots_b), len_b=lens)
+        ms2 = timed_ms(torch, lambda: ctx.block_hash_batch(specs))
+        fixed2 = {"similarity": round(m2 / lb.shape[0], 4), "hash_ms": round(ms2, 3),
+                  "hash_GBps": round(nb / ms2 / 1e6, 1)}
+        bits = size.bit_length() - 1
+        # Chunk digests as the standard digest of each chunk (one sequential
+        # chain per chunk), and as each chunk's two-level direct hash with
+        # 4 KiB segments (same boundaries and similarity, parallel digests).
+        sweep[f"{size // KiB}k"] = {
+            "fixed": fixed,
+            "fixed_two_level_4k": fixed2,
+            "content_based": dict(cb((1 << bits) - 1, size // 4, 4 * size), mask_bits=bits, min=size // 4,
+                                  max=4 * size),
+            "content_based_two_level_4k": cb((1 << bits) - 1, size // 4, 4 * size, seg=4 * KiB)}
+    res["block_size_sweep"] = sweep
+    ctx.close()
+    del a, b
+    return res
+
+
 def serving(torch, hg, inputs, data, host_pinned, n_req):
     """The serving loop under the request stream (seed 6): log-normal sizes
     4 KiB-256 MiB (median 1 MiB, sigma 1.85), mix 50% block SHA-1 / 30% block
@@ -683,6 +753,9 @@ def main():
     if not args.no_batched:
         print("[bench] batched files (4096, one captured graph)", file=sys.stderr, flush=True)
         line["batched"] = batched(torch, hg, inputs, data)
+    if not args.no_sweep:
+        print("[bench] similarity workload and block-size sweep", file=sys.stderr, flush=True)
+        line["similarity_sweep"] = similarity_sweep(torch, hg, inputs)
     if not args.no_serving:
         print(f"[bench] serving loop ({args.serve_requests} requests per point)", file=sys.stderr, flush=True)
         line["serving"] = serving(torch, hg, inputs, data, host_pinned, args.serve_requests)

@@ -202,6 +202,15 @@ typedef struct {
     uint64_t max_chunk;   /* maximum chunk size in bytes (0 = none; else >= max(min_chunk, 1)) */
     int32_t window_digest; /* digest of the sliding windows */
     int32_t chunk_digest;  /* digest of each chunk */
+    uint64_t chunk_segment; /* 0: a chunk's digest is the standard digest of its
+                             * bytes.  S > 0: each chunk is direct-hashed by the
+                             * parallel construction (Sec. 3.2.2, applied to every
+                             * detected chunk as in Sec. 3.2.4): cut into segments
+                             * of S bytes from its start (the last one shorter),
+                             * digest = H(H(seg_0) || ... || H(seg_m-1)), m =
+                             * ceil(len / S) -- what hg_block_hash gives as the
+                             * root of the chunk's bytes at block size S.  Not
+                             * available in file batches (HG_EINVAL). */
 } hg_chunk_params;
 
 /* Content-based chunking of one block: window scan, boundary decision and

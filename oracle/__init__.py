@@ -15,7 +15,9 @@ Every routine follows a passage of "GPUs as Storage System Accelerators":
                       Sec. 2.1 ("Content-based chunking") and Sec. 3.2.2.
 * ``chunk_select``    boundary decision with a minimum chunk size (Sec. 3.2.2
                       last stage; min/max chunk sizes of Sec. 4.3).
-* ``chunk_digests``   direct hash of each chunk (Fig. 3 legend, Sec. 3.2.4).
+* ``chunk_digests``   digest of each chunk (Fig. 3 legend, Sec. 3.2.4): the
+                      standard digest of its bytes, or its two-level direct
+                      hash (Sec. 3.2.2) with a segment size.
 * ``similarity``      block-map lookup of Sec. 3.2.1 (similarity % of Sec. 4.3).
 
 ``map_ranges`` shards independent units (segments, windows) over threads and
@@ -212,14 +214,23 @@ def chunk_select(starts: np.ndarray, window: int, length: int, min_chunk: int,
     return out[:m].copy()
 
 
-def chunk_digests(kind: int, data, ends: np.ndarray) -> np.ndarray:
+def chunk_digests(kind: int, data, ends: np.ndarray, segment: int = 0) -> np.ndarray:
+    """Digest of each chunk [ends[j-1], ends[j]).  segment = 0: the standard
+    digest of the chunk's bytes.  segment = S > 0: the chunk direct-hashed by
+    the parallel construction of Sec. 3.2.2 (as Sec. 3.2.4 hashes every
+    detected chunk): its S-byte segment digests, then the digest of those."""
     lib = _load()
     buf = _bytes_view(data)
     e = np.ascontiguousarray(ends, dtype=np.uint64)
     d = DIGEST_SIZE[kind]
     out = np.zeros((e.size, d), dtype=np.uint8)
-    if e.size:
+    if e.size and segment == 0:
         lib.oracle_chunk_digests(kind, _ptr(buf), _ptr(e), e.size, _ptr(out))
+    prev = 0
+    for j in range(e.size if segment else 0):
+        _, r = direct_hash(kind, buf[prev:int(e[j])], segment)
+        out[j] = np.frombuffer(r, dtype=np.uint8)
+        prev = int(e[j])
     return out
 
 
@@ -238,12 +249,12 @@ def similarity(kind: int, dig_a: np.ndarray, dig_b: np.ndarray, len_b=None):
 
 
 def chunk(kind_window: int, kind_chunk: int, data, window: int, stride: int, mask: int,
-          target: int, min_chunk: int, threads: int = 1, max_chunk: int = 0):
+          target: int, min_chunk: int, threads: int = 1, max_chunk: int = 0, segment: int = 0):
     """Whole content-based chunking path: candidates, ends, chunk digests."""
     buf = _bytes_view(data)
     starts = window_scan_sharded(kind_window, buf, window, stride, mask, target, threads)
     ends = chunk_select(starts, window, buf.size, min_chunk, max_chunk)
-    return starts, ends, chunk_digests(kind_chunk, buf, ends)
+    return starts, ends, chunk_digests(kind_chunk, buf, ends, segment)
 
 
 def map_ranges(fn, n: int, threads: int, min_per_range: int = 1):

@@ -420,6 +420,81 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
     return hipGetLastError();
 }
 
+// ------------------------------------------------- two-level chunk digests --
+// Each chunk direct-hashed by the parallel construction (Sec. 3.2.2, applied
+// to every detected chunk as Sec. 3.2.4 describes): the chunk is cut into
+// segments of S bytes (the last one shorter), the segment digests are laid
+// out in one buffer, and the chunk digest is the digest of that buffer.
+//
+// Layout without a prefix sum: chunk j's segment digests occupy the slots
+// first_j = floor(start_j / S) + j onward.  With start_j = aS + r and length
+// len_j, first_{j+1} - first_j = floor((r + len_j) / S) + 1 >= ceil(len_j / S),
+// so consecutive chunks never share a slot, and the slot count is at most
+// floor(len / S) + n + 1.
+
+__device__ __forceinline__ uint64_t tl_first(const uint64_t *ends, uint64_t j, uint64_t S) {
+    return (j ? ends[j - 1] : 0) / S + j;
+}
+
+// One lane per slot p: the chunk whose range of slots holds p (the largest j
+// with first_j <= p, by binary search), then that chunk's segment.
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void tl_leaf_kernel(
+    const uint8_t *__restrict__ in, uint64_t len, const uint64_t *__restrict__ ends,
+    const uint64_t *__restrict__ n_dev, uint64_t S, uint64_t n_slots, uint8_t *__restrict__ leaves) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = *n_dev;
+    if (p >= n_slots || n == 0) return;
+    uint64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint64_t mid = hi - ((hi - lo) >> 1);
+        if (tl_first(ends, mid, S) <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint64_t start = lo ? ends[lo - 1] : 0, clen = ends[lo] - start;
+    const uint64_t k = p - tl_first(ends, lo, S);
+    if (k >= (clen + S - 1) / S) return;  // a slot between two chunks' ranges
+    const uint64_t s0 = start + k * S;
+    const uint64_t sl = clen - k * S < S ? clen - k * S : S;
+    uint32_t st[5];
+    hash_range<KIND>(in + s0, sl, in + len, st);
+    store_digest<KIND>(leaves + p * (uint64_t)Hash<KIND>::DIGEST, st);
+}
+
+// One lane per chunk: the digest of its ceil(len_j / S) segment digests.
+template <int KIND>
+__global__ __launch_bounds__(256) void tl_root_kernel(const uint8_t *__restrict__ leaves, uint64_t n_slots,
+                                                      const uint64_t *__restrict__ ends,
+                                                      const uint64_t *__restrict__ n_dev, uint64_t S,
+                                                      uint8_t *__restrict__ out) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= *n_dev) return;
+    constexpr uint64_t D = Hash<KIND>::DIGEST;
+    const uint64_t start = j ? ends[j - 1] : 0, clen = ends[j] - start;
+    const uint8_t *p = leaves + tl_first(ends, j, S) * D;
+    uint32_t st[5];
+    hash_range<KIND>(p, (clen + S - 1) / S * D, leaves + n_slots * D, st);
+    store_digest<KIND>(out + j * D, st);
+}
+
+uint64_t two_level_slots(uint64_t len, uint64_t max_n, uint64_t S) { return len / S + max_n + 1; }
+
+hipError_t launch_chunk_digests_two_level(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
+                                          const uint64_t *n_dev, uint64_t max_n, uint64_t S, uint8_t *leaves,
+                                          uint8_t *out, hipStream_t s) {
+    if (max_n == 0) return hipSuccess;
+    const uint64_t slots = two_level_slots(len, max_n, S);
+    const unsigned lgrid = (unsigned)((slots + 255) / 256), rgrid = (unsigned)((max_n + 255) / 256);
+    if (kind == KIND_MD5) {
+        tl_leaf_kernel<KIND_MD5><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, S, slots, leaves);
+        tl_root_kernel<KIND_MD5><<<rgrid, 256, 0, s>>>(leaves, slots, ends, n_dev, S, out);
+    } else {
+        tl_leaf_kernel<KIND_SHA1><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, S, slots, leaves);
+        tl_root_kernel<KIND_SHA1><<<rgrid, 256, 0, s>>>(leaves, slots, ends, n_dev, S, out);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ similarity --
 // Digest keys and comparison: dig_hash / dig_equal (hg_device.hpp).
 

@@ -43,6 +43,7 @@ enum Slot {
     SLOT_PLAN,     // batch plan
     SLOT_SMALL,    // counts and counters
     SLOT_AUX,      // shifted candidate starts (streaming chunker)
+    SLOT_TLEAF,    // segment digests of two-level chunk digests
     N_SLOTS
 };
 
@@ -356,6 +357,28 @@ int read_u64(hg_ctx *ctx, const uint64_t *dev, hipStream_t st, uint64_t *v) {
 int copy_out(hg_ctx *ctx, void *dst, const void *src, size_t n, bool dst_device, hipStream_t st) {
     if (n == 0) return HG_OK;
     HG_HIP(ctx, hipMemcpyAsync(dst, src, n, dst_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    return HG_OK;
+}
+
+// Digests of the chunks [ends[j-1], ends[j]) of in[0, len) (*n_dev <= max_n
+// of them): the standard digest of each chunk's bytes, or with chunk_segment
+// the two-level direct hash of each chunk.
+int chunk_digests_of(hg_ctx *ctx, const hg_chunk_params &p, const uint8_t *in, uint64_t len, const uint64_t *ends,
+                     const uint64_t *n_dev, uint64_t max_n, uint8_t *out, hipStream_t st) {
+    if (max_n == 0) return HG_OK;
+    if (p.chunk_segment) {
+        void *leaves;
+        const uint64_t slots = hg::two_level_slots(len, max_n, p.chunk_segment);
+        HG_TRY(ensure(ctx, SLOT_TLEAF, slots * (uint64_t)digest_bytes(p.chunk_digest), st, &leaves));
+        HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
+                  hg::launch_chunk_digests_two_level(p.chunk_digest, in, len, ends, n_dev, max_n, p.chunk_segment,
+                                                     (uint8_t *)leaves, out, st));
+        return HG_OK;
+    }
+    void *segs;
+    HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(max_n), st, &segs));
+    HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
+              hg::launch_segment_digests(p.chunk_digest, in, len, nullptr, ends, n_dev, max_n, out, segs, st));
     return HG_OK;
 }
 
@@ -758,11 +781,7 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
         const bool direct = out_dev && capacity >= nc;
         void *ddig = chunk_digests;
         if (!direct) HG_TRY(ensure(ctx, SLOT_DIG, (nc + 1) * (uint64_t)dd, st, &ddig));
-        void *segs;
-        HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(bound), st, &segs));
-        HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
-                  hg::launch_segment_digests(pr->chunk_digest, din, len, nullptr, (const uint64_t *)dends,
-                                             &small[1], bound, (uint8_t *)ddig, segs, st));
+        HG_TRY(chunk_digests_of(ctx, *pr, din, len, (const uint64_t *)dends, &small[1], nc, (uint8_t *)ddig, st));
         if (!direct) HG_TRY(copy_out(ctx, chunk_digests, ddig, k * (uint64_t)dd, out_dev, st));
     }
     if (out_dev && !count_host) HG_TRY(copy_out(ctx, n_chunks, &small[1], 8, true, st));
@@ -1068,6 +1087,8 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
         if (p.chunk.stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
         if (p.chunk.max_chunk != 0 && p.chunk.max_chunk < std::max<uint64_t>(p.chunk.min_chunk, 1))
             return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
+        if (p.chunk.chunk_segment != 0)
+            return fail(ctx, HG_EINVAL, "two-level chunk digests (chunk_segment) are not available in file batches");
     }
     hg_batch *b = new hg_batch();
     b->ctx = ctx;
@@ -1455,12 +1476,10 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         }
         if (digests) {
             const int dd = digest_bytes(p.chunk_digest);
-            void *ddig = digests, *segs;
+            void *ddig = digests;
             if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
-            HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(k), st, &segs));
-            HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
-                      hg::launch_segment_digests(p.chunk_digest, W + last0, wlen - last0, nullptr,
-                                                 (const uint64_t *)rel, &small[2], k, (uint8_t *)ddig, segs, st));
+            HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, (const uint64_t *)rel, &small[2], k,
+                                    (uint8_t *)ddig, st));
             if (!out_dev) HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
         }
     }

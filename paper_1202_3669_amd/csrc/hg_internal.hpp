@@ -117,6 +117,15 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
                                   const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
                                   void *scratch, hipStream_t s);
 
+// Two-level chunk digests (each chunk direct-hashed with segments of S
+// bytes): chunk j is [ends[j-1], ends[j]) of in (ends[-1] = 0, *n_dev <=
+// max_n chunks, reads below in + len).  leaves is scratch of
+// two_level_slots(len, max_n, S) * digest bytes; out gets n digests.
+uint64_t two_level_slots(uint64_t len, uint64_t max_n, uint64_t S);
+hipError_t launch_chunk_digests_two_level(int kind, const uint8_t *in, uint64_t len, const uint64_t *ends,
+                                          const uint64_t *n_dev, uint64_t max_n, uint64_t S, uint8_t *leaves,
+                                          uint8_t *out, hipStream_t s);
+
 // Streaming boundary decision over a carried buffer of len bytes whose
 // first chunk starts at last0: candidate starts cand[i] + add (ascending,
 // *n_dev of them).  Writes the cuts it can decide (relative to last0) to

@@ -118,7 +118,7 @@ uint64_t n_leaves(const hg_request &r) { return r.len ? (r.len + r.block_size - 
 bool same_chunk_params(const hg_chunk_params &a, const hg_chunk_params &b) {
     return a.window == b.window && a.stride == b.stride && a.mask == b.mask && a.target == b.target &&
            a.min_chunk == b.min_chunk && a.max_chunk == b.max_chunk && a.window_digest == b.window_digest &&
-           a.chunk_digest == b.chunk_digest;
+           a.chunk_digest == b.chunk_digest && a.chunk_segment == b.chunk_segment;
 }
 
 // A request's footprint inside a group.
@@ -354,9 +354,9 @@ bool fits(const Group &g, const hg_server_cfg &cfg, const Req *q) {
     if (g.bytes + r.len > cfg.max_group_bytes) return false;
     const Need n = need_of(r);
     if (r.kind == HG_REQ_BLOCK) return g.leaf_used + n.leaf_bytes <= g.leaf_cap;
-    // A maximum chunk size needs per-file room for forced cuts: such
-    // requests are served alone.
-    if (r.chunk.max_chunk != 0) return false;
+    // A maximum chunk size needs per-file room for forced cuts, and two-level
+    // chunk digests a per-file segment layout: such requests are served alone.
+    if (r.chunk.max_chunk != 0 || r.chunk.chunk_segment != 0) return false;
     if (!g.chunks.empty() && !same_chunk_params(g.cp, r.chunk)) return false;
     return g.tiles + n.tiles <= g.tile_cap && g.cand + n.cand <= g.cand_cap;
 }

@@ -35,7 +35,8 @@ _p_u64 = ctypes.POINTER(ctypes.c_uint64)
 class hg_chunk_params(ctypes.Structure):
     _fields_ = [("window", _u32), ("stride", _u32), ("mask", _u32), ("target", _u32),
                 ("min_chunk", _u64), ("max_chunk", _u64),
-                ("window_digest", ctypes.c_int32), ("chunk_digest", ctypes.c_int32)]
+                ("window_digest", ctypes.c_int32), ("chunk_digest", ctypes.c_int32),
+                ("chunk_segment", _u64)]
 
 
 class hg_block_job(ctypes.Structure):
@@ -290,16 +291,19 @@ class Context:
     def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
               window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
               capacity: int | None = None, stream=None, out=None, asynchronous: bool = False,
-              max_chunk: int = 0):
+              max_chunk: int = 0, chunk_segment: int = 0):
         """(ends int64, digests (n, d) uint8) CUDA tensors of the chunks.
         With out = (ends, digests) preallocated CUDA tensors (capacity =
         len(ends)) the results are written there and views returned; with
         asynchronous=True as well, the call returns once the chunk digests
-        are enqueued (the views are valid when `stream` has completed)."""
+        are enqueued (the views are valid when `stream` has completed).
+        chunk_segment > 0 selects two-level chunk digests (segments of that
+        many bytes)."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = data.numel()
-        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
+        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest,
+                            chunk_segment)
         d = DIGEST_SIZE[chunk_digest]
         total = _u64(0)
         if out is not None:
@@ -604,13 +608,14 @@ class RequestSet:
     def __init__(self, pool_ptr: int, in_device: bool, specs, block_size: int = 64 * 1024,
                  window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
                  min_chunk: int = 2048, window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
-                 fail=(), max_chunk: int = 0):
+                 fail=(), max_chunk: int = 0, chunk_segment: int = 0):
         import numpy as np
         specs = [(int(k), int(o), int(n)) for k, o, n in specs]
         self.specs = specs
         n = len(specs)
         self.reqs = (hg_request * max(n, 1))()
-        cp = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
+        cp = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest,
+                             chunk_segment)
         self.chunk_params = cp
         dc = DIGEST_SIZE[chunk_digest]
         leaf_n, cap = [], []
@@ -679,10 +684,11 @@ class Chunker:
 
     def __init__(self, ctx: Context, window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
                  min_chunk: int = 2048, max_chunk: int = 0, window_digest: int = HG_MD5,
-                 chunk_digest: int = HG_SHA1):
+                 chunk_digest: int = HG_SHA1, chunk_segment: int = 0):
         self.ctx = ctx
         self.d = DIGEST_SIZE[chunk_digest]
-        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest)
+        p = hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest, chunk_digest,
+                            chunk_segment)
         h = _vp()
         ctx._check(hg_chunker_create(ctx.handle, ctypes.byref(p), ctypes.byref(h)))
         self.handle = h

@@ -35,6 +35,31 @@ def test_library_exports_every_declared_symbol():
     assert sorted(hashgpu.EXPORTED) == sorted(_declared_functions())
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    # The ctypes mirrors of the header's structs: every field at the offset
+    # and every struct of the size a C compiler gives them.
+    from paper_1202_3669_amd import hashgpu as hg
+    structs = [hg.hg_chunk_params, hg.hg_block_job, hg.hg_batch_params, hg.hg_batch_out, hg.hg_request,
+               hg.hg_server_cfg, hg.hg_server_stats]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    expect = []
+    for cls in structs:
+        c = cls.__name__
+        lines.append(f'printf("%zu\\n", sizeof({c}));')
+        expect.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            name = "in" if f[0] == "in_" else f[0]
+            lines.append(f'printf("%zu\\n", offsetof({c}, {name}));')
+            expect.append(getattr(cls, f[0]).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
+
+
 def test_status_text_and_digest_sizes():
     from paper_1202_3669_amd import hashgpu as hg
     assert hg.hg_strerror(hg.HG_OK) == b"ok"

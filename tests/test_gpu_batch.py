@@ -8,6 +8,7 @@ sigma 1.5, capped at 64 MiB, 4096 files; smaller variants for the quick
 cases), plus empty files and files shorter than a window, packed without
 alignment.
 """
+import ctypes
 import os
 import sys
 
@@ -148,6 +149,18 @@ def test_batch_with_max_chunk(ctx, hg):
         assert np.array_equal(b._ce[c0:c1].astype(np.uint64), ends), f"file {j} chunk ends"
         assert np.array_equal(b._cd[c0:c1], oracle.chunk_digests(oracle.SHA1, data, ends)), f"file {j} digests"
     b.close()
+
+
+def test_batch_rejects_two_level_chunk_digests(ctx, hg):
+    arena, off, ln = small_batch(907, 4)
+    note("batch rejects two-level chunk digests")
+    p = hg.hg_batch_params(64 * 1024, hg.HG_SHA1, 1,
+                           hg.hg_chunk_params(20, 1, 0xFFF, 0, 2048, 0, hg.HG_MD5, hg.HG_SHA1, 4096), 0)
+    h = ctypes.c_void_p()
+    o = np.ascontiguousarray(off, dtype=np.uint64)
+    n = np.ascontiguousarray(ln, dtype=np.uint64)
+    st = hg.hg_batch_create(ctx.handle, o.ctypes.data, n.ctypes.data, len(off), ctypes.byref(p), ctypes.byref(h))
+    assert st == hg.HG_EINVAL and not h.value
 
 
 def test_batch_reports_candidate_overflow(ctx, hg):

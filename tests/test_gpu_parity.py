@@ -310,6 +310,51 @@ def test_chunk_with_max(ctx, case):
         assert np.array_equal(host(dig), exp_dig)
 
 
+TWO_LEVEL_CASES = [  # (length, mask, min, max, segment)
+    (3 * 2**20 + 5, 0xFFF, 2048, 0, 4096),           # ~6 KiB chunks: one or two segments each
+    (8 * 2**20 + 3, 0xFFFFF, 256 * 1024, 4 * 2**20, 4096),  # ~1.3 MB chunks, forced cuts
+    (2**20 + 1, 0xFFF, 2048, 0, 64),                 # one padded block per segment
+    (300_000, 0xFF, 0, 0, 1),                        # one-byte segments
+    (2 * 2**20, 0xFFF, 2048, 0, 1 << 40),            # one segment per chunk: H(H(chunk))
+    (777, 0xF, 10, 0, 100),
+    (0, 0xFFF, 2048, 0, 4096),
+]
+
+
+@pytest.mark.parametrize("case", TWO_LEVEL_CASES)
+@pytest.mark.parametrize("kind", [0, 1])
+def test_chunk_two_level_digests(ctx, case, kind):
+    length, mask, mn, mx, seg = case
+    data = inputs.uniform_bytes(480 + length % 89, length)
+    starts = oracle.window_scan_sharded(0, data, 20, 1, mask, 0, THREADS)
+    exp_ends = oracle.chunk_select(starts, 20, data.size, mn, mx)
+    exp_dig = oracle.chunk_digests(kind, data, exp_ends, seg)
+    for off in (0, 3):
+        note(f"two-level chunk digests case={case} kind={kind} off={off}")
+        ends, dig = ctx.chunk(dev(data, off), 20, 1, mask, 0, mn, chunk_digest=kind, max_chunk=mx,
+                              chunk_segment=seg)
+        assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+        assert np.array_equal(host(dig), exp_dig)
+
+
+def test_chunk_two_level_host_input_and_small_capacity(ctx, hg):
+    data = inputs.uniform_bytes(489, 5 * 2**20 + 17)
+    starts = oracle.window_scan_sharded(0, data, 20, 1, 0xFFF, 0, THREADS)
+    exp_ends = oracle.chunk_select(starts, 20, data.size, 2048)
+    exp_dig = oracle.chunk_digests(1, data, exp_ends, 4096)
+    note("two-level chunk digests, host input")
+    ends, dig = ctx.chunk(torch.from_numpy(data), 20, 1, 0xFFF, 0, 2048, chunk_segment=4096)
+    assert np.array_equal(host(ends).astype(np.uint64), exp_ends)
+    assert np.array_equal(host(dig), exp_dig)
+    note("two-level chunk digests, capacity below the chunk count")
+    e = torch.zeros(10, dtype=torch.int64, device="cuda")
+    d = torch.zeros((10, 20), dtype=torch.uint8, device="cuda")
+    with pytest.raises(hg.HashGpuError):
+        ctx.chunk(dev(data), 20, 1, 0xFFF, 0, 2048, out=(e, d), chunk_segment=4096)
+    assert np.array_equal(host(e).astype(np.uint64), exp_ends[:10])
+    assert np.array_equal(host(d), exp_dig[:10])
+
+
 def test_chunk_max_rejects_max_below_min(ctx, hg):
     d = dev(inputs.uniform_bytes(451, 1000))
     with pytest.raises(hg.HashGpuError):

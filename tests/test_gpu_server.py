@@ -183,6 +183,24 @@ def test_chunk_requests_with_max_chunk(ctx, hg, pool):
             assert np.array_equal(got[2], oracle.chunk_digests(oracle.SHA1, data, ends))
 
 
+def test_chunk_requests_with_two_level_digests(ctx, hg, pool):
+    host, dev = pool
+    specs = [(2, 0, 1 * MiB), (0, 5, 300 * KiB), (2, 50, 2 * MiB + 3), (2, 77, 10)]
+    rs = hg.RequestSet(dev.data_ptr(), True, specs, chunk_segment=1024)
+    note("chunk requests with two-level chunk digests")
+    with hg.Server(0, slots=2, max_requests=8, device_budget=8 * MiB, max_group_bytes=8 * MiB) as srv:
+        _, sts = srv.play(rs, np.zeros(len(specs)))
+    assert np.all(sts == hg.HG_OK)
+    for i, (k, o, n) in enumerate(specs):
+        got = rs.result(i)
+        if k == 2:
+            data = host[o:o + n]
+            starts = oracle.window_scan(oracle.MD5, data, 20, 1, 0xFFF, 0)
+            ends = oracle.chunk_select(starts, 20, n, 2048)
+            assert np.array_equal(got[1], ends)
+            assert np.array_equal(got[2], oracle.chunk_digests(oracle.SHA1, data, ends, 1024))
+
+
 def test_truncation_and_injected_failure(ctx, hg, pool):
     host, dev = pool
     specs = [(2, 0, 1 * MiB), (0, 5, 300 * KiB), (2, 50, 2 * MiB), (1, 9, 1 * MiB)]

@@ -38,10 +38,10 @@ def ctx(hg):
     c.close()
 
 
-def one_shot(data, w, s, mask, target, mn, mx):
+def one_shot(data, w, s, mask, target, mn, mx, seg=0):
     starts = oracle.window_scan_sharded(oracle.MD5, data, w, s, mask, target, THREADS)
     ends = oracle.chunk_select(starts, w, data.size, mn, mx)
-    return ends, oracle.chunk_digests(oracle.SHA1, data, ends)
+    return ends, oracle.chunk_digests(oracle.SHA1, data, ends, seg)
 
 
 def pieces(rng, n, cuts=()):
@@ -124,6 +124,27 @@ def test_stream_long_runs_without_candidates(ctx, hg):
         assert np.array_equal(np.concatenate(out_e), exp_ends)
         assert np.array_equal(np.concatenate(out_d).reshape(-1, 20), exp_dig)
         ch.close()
+
+
+@pytest.mark.parametrize("device_input", [True, False])
+def test_stream_two_level_digests(ctx, hg, device_input):
+    data = inputs.uniform_bytes(515, 3 * MiB + 9)
+    for mx, seg in ((0, 4096), (65536, 1000)):
+        exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, mx, seg)
+        ch = hg.Chunker(ctx, 20, 1, 0xFFF, 0, 2048, mx, chunk_segment=seg)
+        note(f"stream two-level max={mx} segment={seg} device={device_input}")
+        src = torch.from_numpy(data).cuda() if device_input else data
+        out_e, out_d = [], []
+        for a in range(0, data.size, 500_001):
+            e, d = ch.feed(src[a:a + 500_001])
+            out_e.append(e)
+            out_d.append(d)
+        e, d = ch.finish()
+        out_e.append(e)
+        out_d.append(d)
+        ch.close()
+        assert np.array_equal(np.concatenate(out_e), exp_ends)
+        assert np.array_equal(np.concatenate(out_d).reshape(-1, 20), exp_dig)
 
 
 def test_stream_rejects_small_capacity_and_use_after_finish(ctx, hg):

@@ -290,6 +290,25 @@ def test_chunk_digests_vs_hashlib(kind):
         prev = e
 
 
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("segment", [1, 7, 64, 1000, 4096])
+def test_chunk_digests_two_level_vs_hashlib(kind, segment):
+    # Each chunk direct-hashed (Sec. 3.2.2 applied per chunk, Sec. 3.2.4):
+    # closed form with hashlib -- the digest of the concatenated digests of
+    # the chunk's segment-size pieces, the last piece shorter.
+    data = _rand(22, 12_000).tobytes()
+    ends = np.array([1, 2, 64, 65, 1000, 1056, 5000, 11_999, 12_000], dtype=np.uint64)
+    dig = oracle.chunk_digests(kind, data, ends, segment)
+    prev = 0
+    for j, e in enumerate(ends.tolist()):
+        c = data[prev:e]
+        leaves = b"".join(H[kind](c[k:k + segment]).digest() for k in range(0, len(c), segment))
+        assert bytes(dig[j]) == H[kind](leaves).digest()
+        if segment >= len(c):  # one segment: the digest of the chunk's digest
+            assert bytes(dig[j]) == H[kind](H[kind](c).digest()).digest()
+        prev = e
+
+
 def test_chunk_pipeline_partitions_input():
     data = _rand(21, 300_000)
     starts, ends, dig = oracle.chunk(oracle.MD5, oracle.SHA1, data, 20, 1, 0xFF, 0, 2048, 4)
