@@ -123,9 +123,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void l
     store_digest<KIND_SHA1>(out_sha1 + k * 20, ss);
 }
 
+// Segment ranges of at most LAUNCH_LANES segments: segments [k0, k1) of
+// the whole are segments [0, k1 - k0) of in + k0 * block; every range but
+// the last holds whole segments only, so its reads stay inside it.
+template <class F>
+static hipError_t by_ranges(const uint8_t *in, uint64_t len, uint64_t block, uint64_t n_leaves, F launch) {
+    for (uint64_t k0 = 0; k0 < n_leaves; k0 += LAUNCH_LANES) {
+        const uint64_t k1 = n_leaves - k0 > LAUNCH_LANES ? k0 + LAUNCH_LANES : n_leaves;
+        const uint64_t off = k0 * block, sub = k1 < n_leaves ? (k1 - k0) * block : len - off;
+        const hipError_t e = launch(in + off, sub, k0, k1 - k0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_leaves_dual(const uint8_t *in, uint64_t len, uint64_t block, uint64_t n_leaves,
                               uint8_t *out_md5, uint8_t *out_sha1, hipStream_t s) {
     if (n_leaves == 0) return hipSuccess;
+    if (n_leaves > LAUNCH_LANES)
+        return by_ranges(in, len, block, n_leaves, [&](const uint8_t *p, uint64_t l, uint64_t k0, uint64_t n) {
+            return launch_leaves_dual(p, l, block, n, out_md5 + k0 * 16, out_sha1 + k0 * 20, s);
+        });
     unsigned tpb = n_leaves < 256ull * 1024 ? 64u : 256u;
     uint64_t grid = (n_leaves + tpb - 1) / tpb;
     leaf_dual_kernel<<<dim3((unsigned)grid), dim3(tpb), 0, s>>>(in, len, block, n_leaves, out_md5, out_sha1);
@@ -135,6 +153,12 @@ hipError_t launch_leaves_dual(const uint8_t *in, uint64_t len, uint64_t block, u
 hipError_t launch_leaves(int kind, const uint8_t *in, uint64_t len, uint64_t block,
                          uint64_t n_leaves, uint8_t *out, hipStream_t s) {
     if (n_leaves == 0) return hipSuccess;
+    if (n_leaves > LAUNCH_LANES) {
+        const uint64_t d = kind == KIND_MD5 ? 16 : 20;
+        return by_ranges(in, len, block, n_leaves, [&](const uint8_t *p, uint64_t l, uint64_t k0, uint64_t n) {
+            return launch_leaves(kind, p, l, block, n, out + k0 * d, s);
+        });
+    }
     if (kind == KIND_MD5 && block >= 256 && n_leaves >= 64 * 1024) {
         // MD5 needs more bytes per op than HBM delivers with one line per
         // lane per load: read whole lines per instruction through LDS.

@@ -28,9 +28,12 @@ __device__ __forceinline__ void file_cand_range(const FilesChunk &fc, uint64_t t
     c1 = t1 < fc.n_tiles ? fc.tile_off[t1] : total;
 }
 
+// The builtin returns int: each half goes through uint32_t, so that a low
+// word with bit 31 set is not sign-extended into the high word.
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l) << 32) |
-           __builtin_amdgcn_readlane((uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // One wavefront: the cuts of a block of length L from its ascending
@@ -158,8 +161,7 @@ __global__ __launch_bounds__(64) void files_select(FilesChunk fc, uint32_t w, ui
             const uint64_t elig = __ballot(usable && e >= thr);
             if (elig == 0) break;
             const int l = __builtin_ctzll(elig);
-            last = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(e >> 32), l) << 32) |
-                   __builtin_amdgcn_readlane((uint32_t)e, l);
+            last = readlane64(e, l);
             sel |= 1ull << l;
         }
         if ((sel >> lane) & 1ull) out[m + __builtin_popcountll(sel & ((1ull << lane) - 1ull))] = e;

@@ -369,6 +369,9 @@ int chunk_digests_of(hg_ctx *ctx, const hg_chunk_params &p, const uint8_t *in, u
     if (p.chunk_segment) {
         void *leaves;
         const uint64_t slots = hg::two_level_slots(len, max_n, p.chunk_segment);
+        if (slots >= hg::MAX_LANES)
+            return fail(ctx, HG_EINVAL, "%llu segments (limit 2^31 per call): use a larger chunk_segment",
+                        (unsigned long long)slots);
         HG_TRY(ensure(ctx, SLOT_TLEAF, slots * (uint64_t)digest_bytes(p.chunk_digest), st, &leaves));
         HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
                   hg::launch_chunk_digests_two_level(p.chunk_digest, in, len, ends, n_dev, max_n, p.chunk_segment,
@@ -753,6 +756,9 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
     // decision writes straight into the caller's device buffer when it is
     // that large.
     const uint64_t bound = n_cand + 1 + (pr->max_chunk ? 1 + len / pr->max_chunk : 0);
+    if (bound >= hg::MAX_LANES)
+        return fail(ctx, HG_EINVAL, "%llu candidates (limit 2^31 per call): split the input or use a wider mask",
+                    (unsigned long long)n_cand);
     const bool ends_direct = out_dev && capacity >= bound;
     void *cand, *dends = ends;
     HG_TRY(ensure(ctx, SLOT_CAND, n_cand * 8, st, &cand));
@@ -803,7 +809,8 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
     if (d < 0) return fail(ctx, HG_EINVAL, "unknown digest %d", digest);
     if (!matched) return fail(ctx, HG_EINVAL, "matched is NULL");
     if ((n_a && !dig_a) || (n_b && !dig_b)) return fail(ctx, HG_EINVAL, "NULL digest array");
-    if (n_a >= (1ull << 31)) return fail(ctx, HG_EINVAL, "n_a too large");
+    if (n_a >= hg::MAX_LANES || n_b >= hg::MAX_LANES)
+        return fail(ctx, HG_EINVAL, "n_a and n_b must be below 2^31");
     hipStream_t st = (hipStream_t)stream;
     const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
     const uint8_t *da, *db, *dl = nullptr;
@@ -1155,6 +1162,11 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
                 b->max_chunks += acc;
                 if ((st = batch_upload(b, extra, &b->d_extra)) != HG_OK) break;
             }
+            if (b->max_chunks >= hg::MAX_LANES) {
+                st = fail(ctx, HG_EINVAL, "%llu chunks possible in one batch (limit 2^31): split the files",
+                          (unsigned long long)b->max_chunks);
+                break;
+            }
             if ((st = batch_upload(b, first_tile, &b->d_first_tile)) != HG_OK) break;
             if ((st = batch_upload(b, tiles, &b->d_tiles)) != HG_OK) break;
             if ((st = batch_alloc(b, hg::window_scan_scratch_bytes(b->wsp), &b->d_ws)) != HG_OK) break;
@@ -1425,6 +1437,9 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         }
         HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
         HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
+        if (n_cand >= hg::MAX_LANES)
+            return fail(ctx, HG_EINVAL, "%llu candidates in one feed (limit 2^31): feed smaller pieces",
+                        (unsigned long long)n_cand);
         HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(n_cand, 1) * 8, st, &cand));
         HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
                   hg::launch_window_scan_emit(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws,

@@ -11,6 +11,14 @@
 
 namespace hg {
 
+// A dispatch holds fewer than 2^32 work-items per dimension.  Kernels with
+// one lane per unit are launched over at most LAUNCH_LANES units at a time
+// (segments, window tiles are split into several launches); the public calls
+// reject work that would need more than MAX_LANES lanes in one launch of a
+// kernel that cannot be split (candidates, chunks, digests).
+constexpr uint64_t LAUNCH_LANES = 1ull << 30;
+constexpr uint64_t MAX_LANES = 1ull << 31;
+
 // ----------------------------------------------------------- block hash --
 // Segment (leaf) digests: leaf k = H(in[k*block, min((k+1)*block, len))),
 // written to out + k*digest_size.  n_leaves = ceil(len / block).

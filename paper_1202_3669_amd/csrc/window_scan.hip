@@ -505,26 +505,41 @@ static hipError_t launch_tiles(const WsPlan &p, Src src, uint32_t w, uint32_t s,
     return hipGetLastError();
 }
 
-hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
-                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
-                                    hipStream_t st, const WsFiles *files) {
-    if (p.n_tiles == 0) return hipSuccess;
-    WsScratch sc = carve(p, scratch);
-    if (files) return launch_tiles(p, FileSrc{files->arena, files->off, files->len, files->tiles, w, s}, w, s,
-                                   mask, target, sc, p.n_tiles, st);
-    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows, 0}, w, s, mask, target, sc, p.n_tiles, st);
-}
-
 hipError_t launch_window_scan_tile_range(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w, uint32_t s,
                                          uint32_t mask, uint32_t target, void *scratch, uint64_t t0, uint64_t t1,
                                          hipStream_t st) {
     if (t1 > p.n_tiles) t1 = p.n_tiles;
-    if (t0 >= t1) return hipSuccess;
-    WsScratch sc = carve(p, scratch);
-    // The kernels index their outputs by the launch's own tile number.
-    sc.tile_count += t0;
-    sc.bucket += t0 * WS_CAP;
-    return launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows, t0}, w, s, mask, target, sc, t1 - t0, st);
+    // At most LAUNCH_LANES / WS_TPB tiles per launch.
+    constexpr uint64_t MAX_TILES = LAUNCH_LANES / WS_TPB;
+    for (; t0 < t1; t0 += MAX_TILES) {
+        const uint64_t n = t1 - t0 < MAX_TILES ? t1 - t0 : MAX_TILES;
+        WsScratch sc = carve(p, scratch);
+        // The kernels index their outputs by the launch's own tile number.
+        sc.tile_count += t0;
+        sc.bucket += t0 * WS_CAP;
+        const hipError_t e =
+            launch_tiles(p, SingleSrc{in, len, p.nwin, p.tile_windows, t0}, w, s, mask, target, sc, n, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_window_scan_tiles(const WsPlan &p, const uint8_t *in, uint64_t len, uint32_t w,
+                                    uint32_t s, uint32_t mask, uint32_t target, void *scratch,
+                                    hipStream_t st, const WsFiles *files) {
+    if (p.n_tiles == 0) return hipSuccess;
+    if (!files) return launch_window_scan_tile_range(p, in, len, w, s, mask, target, scratch, 0, p.n_tiles, st);
+    constexpr uint64_t MAX_TILES = LAUNCH_LANES / WS_TPB;
+    for (uint64_t t0 = 0; t0 < p.n_tiles; t0 += MAX_TILES) {
+        const uint64_t n = p.n_tiles - t0 < MAX_TILES ? p.n_tiles - t0 : MAX_TILES;
+        WsScratch sc = carve(p, scratch);
+        sc.tile_count += t0;
+        sc.bucket += t0 * WS_CAP;
+        const hipError_t e = launch_tiles(p, FileSrc{files->arena, files->off, files->len, files->tiles + t0, w, s},
+                                          w, s, mask, target, sc, n, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_window_scan_prefix(const WsPlan &p, void *scratch, uint64_t *total_dev, hipStream_t st) {
