@@ -28,6 +28,10 @@
  *     once the stream has completed, and truncation can then only be seen by
  *     comparing the written count with the capacity (hg_chunk still waits
  *     for its counts, see there).
+ *   - Sizes: lengths and offsets are 64-bit; inputs may exceed 4 GiB.  Work
+ *     that needs 2^31 or more candidates, chunks, two-level chunk segments
+ *     or similarity digests in one call is refused with HG_EINVAL (split the
+ *     input); segment counts and window counts have no such limit.
  *   - Ownership: the caller owns every buffer it passes and keeps it alive
  *     until the results are valid; the library retains no caller pointer
  *     after that.  A context owns its device scratch, pinned staging memory
