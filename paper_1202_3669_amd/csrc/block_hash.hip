@@ -30,83 +30,128 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void l
 
 // Segments read through LDS.  With one lane per segment, a 16-byte load
 // instruction of a wave touches 64 lines (one per lane).  Here the wave loads
-// its 64 segments' next 128-byte lines together: in load instruction j, lane
-// l reads 16-byte piece (l & 7) of segment 8j + (l >> 3), so each
-// instruction reads 8 whole lines; the pieces go to an LDS tile (one
+// its segments' next 128-byte lines together: in load instruction j, lane l
+// reads 16-byte piece (l & 7) of segment 8j + (l >> 3) of a group of 64, so
+// each instruction reads 8 whole lines; the pieces go to an LDS tile (one
 // 144-byte row per segment: 16 bytes of padding make both the row writes and
 // the per-lane row reads conflict-free) and every lane then reads its own
 // row.  The next line pair is loaded while the current one is compressed.
-// The wave does this for as many pairs of blocks as all its segments have;
-// each lane finishes the rest of its segment on its own.
+//
+// Segments of one size start at multiples of that size, so lanes that all
+// read pair q of their segments hit addresses equal modulo the segment size,
+// which HBM serves at about three quarters of its streaming rate.  Each lane
+// therefore runs two chains, segments k0 + lane (group A) and k0 + 64 + lane
+// (group B), with B half a segment behind A: the wave reads two offsets at a
+// time.  The work is the same; the first and last half of the pairs have
+// one chain per lane instead of two.  Each lane finishes the rest of its two
+// segments (beyond the pairs all segments of the wave have) on its own.
 constexpr int LDS_ROW = 9;  // 16-byte units per row: 8 of data, 1 of padding
 
-// 16 bytes at offset `off` of segment `seg` (zeros past the last segment).
+// 16 bytes at offset `off` of segment `seg`.  Past the last segment (only in
+// the last wave, which then holds that segment, so `off` lies inside it) the
+// last segment is read instead: the row belongs to an inactive lane and is
+// not used.
 __device__ __forceinline__ uint4 lds_piece(const uint8_t *in, uint64_t block, uint64_t n_leaves, uint64_t seg,
                                            uint64_t off) {
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (seg < n_leaves) __builtin_memcpy(&v, in + seg * block + off, 16);
+    const uint64_t s = seg < n_leaves ? seg : n_leaves - 1;
+    uint4 v;
+    __builtin_memcpy(&v, in + s * block + off, 16);
     return v;
+}
+
+template <int KIND>
+__device__ __forceinline__ void lds_pair(const uint4 *tile, int lane, uint32_t st[5]) {
+    uint32_t X[32];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint4 v = tile[lane * LDS_ROW + i];
+        X[4 * i] = v.x;
+        X[4 * i + 1] = v.y;
+        X[4 * i + 2] = v.z;
+        X[4 * i + 3] = v.w;
+    }
+    Hash<KIND>::block(st, X);
+    Hash<KIND>::block(st, X + 16);
 }
 
 template <int KIND>
 __global__ __launch_bounds__(64) void leaf_lds_kernel(const uint8_t *__restrict__ in, uint64_t len, uint64_t block,
                                                       uint64_t n_leaves, uint8_t *__restrict__ out) {
-    __shared__ uint4 tile[64 * LDS_ROW];
+    __shared__ uint4 tile[2][64 * LDS_ROW];
     const int lane = threadIdx.x;
-    const uint64_t k0 = (uint64_t)blockIdx.x * 64, k = k0 + lane;
-    const bool active = k < n_leaves;
-    const uint64_t n = active ? (len - k * block < block ? len - k * block : block) : 0;
+    const uint64_t k0 = (uint64_t)blockIdx.x * 128, ka = k0 + lane, kb = k0 + 64 + lane;
+    const bool act_a = ka < n_leaves, act_b = kb < n_leaves;
+    const uint64_t na = act_a ? (len - ka * block < block ? len - ka * block : block) : 0;
+    const uint64_t nb = act_b ? (len - kb * block < block ? len - kb * block : block) : 0;
     // Pairs of blocks that every active segment of the wave has.
-    uint64_t m = active ? n >> 7 : ~0ull;
+    uint64_t m = act_a ? na >> 7 : ~0ull;
+    if (act_b && (nb >> 7) < m) m = nb >> 7;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const uint64_t o = __shfl_xor(m, off, 64);
         m = o < m ? o : m;
     }
+    const uint64_t P = m / 2;  // group B runs pair i - P in step i
     const int piece = lane & 7, row0 = lane >> 3;
-    uint4 R[8];
-    uint32_t st[5];
-    Hash<KIND>::init(st);
+    uint4 RA[8], RB[8];
+    uint32_t sa[5], sb[5];
+    Hash<KIND>::init(sa);
+    Hash<KIND>::init(sb);
     if (m > 0) {
 #pragma unroll
-        for (int j = 0; j < 8; j++) R[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, piece * 16);
+        for (int j = 0; j < 8; j++) RA[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, piece * 16);
 #pragma unroll
-        for (int j = 0; j < 8; j++) tile[(8 * j + row0) * LDS_ROW + piece] = R[j];
+        for (int j = 0; j < 8; j++) tile[0][(8 * j + row0) * LDS_ROW + piece] = RA[j];
+        if (P == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) RB[j] = lds_piece(in, block, n_leaves, k0 + 64 + 8 * j + row0, piece * 16);
+#pragma unroll
+            for (int j = 0; j < 8; j++) tile[1][(8 * j + row0) * LDS_ROW + piece] = RB[j];
+        }
         __syncthreads();
     }
-    for (uint64_t q = 0; q < m; q++) {
-        uint32_t X[32];
+    for (uint64_t i = 0; i < m + P; i++) {
+        const bool a_now = i < m, b_now = i >= P;
+        const bool a_next = i + 1 < m, b_next = i + 1 >= P && i + 1 < m + P;
+        // Next lines of both groups in flight while the current ones are
+        // compressed.
+        if (a_next) {
+            const uint64_t off = (i + 1) * 128 + piece * 16;
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const uint4 v = tile[lane * LDS_ROW + i];
-            X[4 * i] = v.x;
-            X[4 * i + 1] = v.y;
-            X[4 * i + 2] = v.z;
-            X[4 * i + 3] = v.w;
+            for (int j = 0; j < 8; j++) RA[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, off);
         }
-        __syncthreads();  // every row read before the tile is refilled
-        const bool more = q + 1 < m;
-        if (more) {
-            const uint64_t off = (q + 1) * 128 + piece * 16;
+        if (b_next) {
+            const uint64_t off = (i + 1 - P) * 128 + piece * 16;
 #pragma unroll
-            for (int j = 0; j < 8; j++) R[j] = lds_piece(in, block, n_leaves, k0 + 8 * j + row0, off);
+            for (int j = 0; j < 8; j++) RB[j] = lds_piece(in, block, n_leaves, k0 + 64 + 8 * j + row0, off);
         }
         __builtin_amdgcn_sched_barrier(0);
-        Hash<KIND>::block(st, X);
-        Hash<KIND>::block(st, X + 16);
+        if (a_now) lds_pair<KIND>(tile[0], lane, sa);
+        if (b_now) lds_pair<KIND>(tile[1], lane, sb);
         // The tile writes wait for the loads: keep them after the rounds
-        // (the compiler would otherwise merge them into the load branch).
-        asm volatile("" : "+v"(st[0]), "+v"(st[1]), "+v"(st[2]), "+v"(st[3]) : : "memory");
-        if (more) {
+        // (the compiler would otherwise merge them into the load branches).
+        asm volatile("" : "+v"(sa[0]), "+v"(sa[1]), "+v"(sa[2]), "+v"(sa[3]), "+v"(sb[0]), "+v"(sb[1]),
+                     "+v"(sb[2]), "+v"(sb[3]) : : "memory");
+        __syncthreads();  // every row read before the tiles are refilled
+        if (a_next) {
 #pragma unroll
-            for (int j = 0; j < 8; j++) tile[(8 * j + row0) * LDS_ROW + piece] = R[j];
+            for (int j = 0; j < 8; j++) tile[0][(8 * j + row0) * LDS_ROW + piece] = RA[j];
+        }
+        if (b_next) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) tile[1][(8 * j + row0) * LDS_ROW + piece] = RB[j];
         }
         __syncthreads();
     }
-    if (!active) return;
     const uint64_t done = m * 128;
-    hash_rest<KIND>(in + k * block + done, n - done, n, in + len, st);
-    store_digest<KIND>(out + k * (uint64_t)Hash<KIND>::DIGEST, st);
+    if (act_a) {
+        hash_rest<KIND>(in + ka * block + done, na - done, na, in + len, sa);
+        store_digest<KIND>(out + ka * (uint64_t)Hash<KIND>::DIGEST, sa);
+    }
+    if (act_b) {
+        hash_rest<KIND>(in + kb * block + done, nb - done, nb, in + len, sb);
+        store_digest<KIND>(out + kb * (uint64_t)Hash<KIND>::DIGEST, sb);
+    }
 }
 
 // Both digests of every segment in one pass over the input.
@@ -162,7 +207,7 @@ hipError_t launch_leaves(int kind, const uint8_t *in, uint64_t len, uint64_t blo
     if (kind == KIND_MD5 && block >= 256 && n_leaves >= 64 * 1024) {
         // MD5 needs more bytes per op than HBM delivers with one line per
         // lane per load: read whole lines per instruction through LDS.
-        const uint64_t grid = (n_leaves + 63) / 64;
+        const uint64_t grid = (n_leaves + 127) / 128;  // 128 segments per wave
         leaf_lds_kernel<KIND_MD5><<<dim3((unsigned)grid), dim3(64), 0, s>>>(in, len, block, n_leaves, out);
         return hipGetLastError();
     }
