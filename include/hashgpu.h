@@ -24,7 +24,8 @@
  *   - Synchrony: without HG_ASYNC the call returns when its results are in
  *     the caller's memory.  HG_ASYNC (valid only with HG_IN_DEVICE and
  *     HG_OUT_DEVICE, and only for hg_block_hash, hg_window_scan,
- *     hg_similarity and hg_chunk) returns after enqueueing; results are valid
+ *     hg_similarity, hg_chunk and the chunking stages below) returns after
+ *     enqueueing; results are valid
  *     once the stream has completed, and truncation can then only be seen by
  *     comparing the written count with the capacity (hg_chunk still waits
  *     for its counts, see there).
@@ -258,6 +259,53 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
 int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b,
                   const uint64_t *len_b, uint64_t n_b, int digest, uint64_t *matched,
                   uint64_t *matched_bytes, uint32_t flags, void *stream);
+
+/* --------------------------------------------- the chunking stages alone -- */
+/* The stages of hg_chunk as separate calls (Sec. 3.2.2: window digests, then
+ * the boundary decision, then a direct hash of each chunk; Fig. 3).  Counts
+ * produced on the device feed the next stage on the device, so a pipeline
+ * of hg_window_scan (HG_ASYNC), hg_chunk_select, hg_chunk_digests and
+ * hg_similarity_n runs without waiting on the host, and its stages can be
+ * placed on different streams with events between them. */
+
+/* Boundary decision from candidate window starts, by the rule of hg_chunk
+ * (minimum, and maximum when max_chunk > 0), for a block of len bytes.
+ *   starts     ascending window start offsets, as hg_window_scan writes them;
+ *              max_starts entries of room.
+ *   n_starts   one uint64: the number of candidates.  When *n_starts exceeds
+ *              max_starts (the scan found more than it could store), the
+ *              list is incomplete: *n_chunks is set to UINT64_MAX, and a
+ *              call that waits returns HG_ETRUNC.
+ *   ends       capacity entries; capacity must be at least max_starts + 1
+ *              (+ len / max_chunk + 1 with a maximum), else HG_EINVAL.
+ *   n_chunks   one uint64: the number of chunks.
+ * starts and n_starts are device pointers with HG_IN_DEVICE; ends and
+ * n_chunks with HG_OUT_DEVICE.  With HG_ASYNC (both flags) nothing waits on
+ * the host.  Starts that do not ascend give meaningless cuts, never writes
+ * outside `ends`. */
+int hg_chunk_select(hg_ctx *ctx, const uint64_t *starts, const uint64_t *n_starts, uint64_t max_starts,
+                    uint64_t len, uint32_t window, uint64_t min_chunk, uint64_t max_chunk, uint64_t *ends,
+                    uint64_t capacity, uint64_t *n_chunks, uint32_t flags, void *stream);
+
+/* Chunk digests (Fig. 3 legend, Sec. 3.2.4) of in[0, len): chunk j is
+ * [ends[j-1], ends[j]) with ends[-1] = 0, for min(*n_chunks, max_chunks)
+ * chunks; `digests` has room for max_chunks digests.  chunk_segment as in
+ * hg_chunk_params (0: standard digest; S > 0: two-level with S-byte
+ * segments).  Ends past len are read as len and a decreasing end as an empty
+ * chunk, so no input leads outside the buffers.  in, ends and n_chunks are
+ * device pointers with HG_IN_DEVICE, digests with HG_OUT_DEVICE; HG_ASYNC
+ * (both flags) returns after enqueueing. */
+int hg_chunk_digests(hg_ctx *ctx, const void *in, uint64_t len, const uint64_t *ends, const uint64_t *n_chunks,
+                     uint64_t max_chunks, int digest, uint64_t chunk_segment, void *digests, uint32_t flags,
+                     void *stream);
+
+/* hg_similarity with B's count read when the work runs: B has
+ * min(*n_b, max_b) chunks; dig_b and len_b have room for max_b entries.
+ * n_b is a device pointer with HG_IN_DEVICE (as hg_chunk_select writes it),
+ * a host pointer otherwise.  Other arguments and flags as hg_similarity. */
+int hg_similarity_n(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b, const uint64_t *len_b,
+                    const uint64_t *n_b, uint64_t max_b, int digest, uint64_t *matched, uint64_t *matched_bytes,
+                    uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------ block map -- */
 

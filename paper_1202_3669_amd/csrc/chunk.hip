@@ -101,8 +101,9 @@ __device__ __forceinline__ unsigned long long block_walk(const SelScratch &sc, u
     }
 }
 
-__global__ __launch_bounds__(256) void cs_spec(const uint64_t *__restrict__ starts, uint64_t n, uint32_t w,
-                                               uint64_t len, uint64_t step, SelScratch sc) {
+__global__ __launch_bounds__(256) void cs_spec(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ n_dev,
+                                               uint32_t w, uint64_t len, uint64_t step, SelScratch sc) {
+    const uint64_t n = *n_dev;
     const uint64_t nu = usable_count(starts, n, w, len);
     const int lane = threadIdx.x & 63;
     const uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -136,9 +137,10 @@ __global__ __launch_bounds__(256) void cs_spec(const uint64_t *__restrict__ star
     }
 }
 
-__global__ __launch_bounds__(256) void cs_super(const uint64_t *__restrict__ starts, uint64_t n, uint32_t w,
-                                                uint64_t len, SelScratch sc) {
-    const uint64_t nu = usable_count(starts, n, w, len);
+__global__ __launch_bounds__(256) void cs_super(const uint64_t *__restrict__ starts,
+                                                const uint64_t *__restrict__ n_dev, uint32_t w, uint64_t len,
+                                                SelScratch sc) {
+    const uint64_t nu = usable_count(starts, *n_dev, w, len);
     const int lane = threadIdx.x & 63;
     const uint64_t S = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nb = (nu + 63) / 64;
@@ -268,6 +270,7 @@ size_t chunk_select_scratch_bytes(uint64_t n_starts) {
 hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_dev, uint64_t n_starts,
                                uint32_t w, uint64_t len, uint64_t min_chunk, void *scratch, uint64_t *ends,
                                uint64_t cap, uint64_t *n_chunks_dev, hipStream_t s) {
+    // n_starts bounds *n_starts_dev (grids and scratch are sized by it).
     const uint64_t nb = (n_starts + 63) / 64 + 1;
     uint8_t *q = (uint8_t *)scratch;
     SelScratch sc;
@@ -281,9 +284,9 @@ hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_
     hipError_t e;
     if (n_starts) {
         const uint64_t nbl = (n_starts + 63) / 64;
-        cs_spec<<<(unsigned)((nbl + 3) / 4), 256, 0, s>>>(starts, n_starts, w, len, step, sc);
+        cs_spec<<<(unsigned)((nbl + 3) / 4), 256, 0, s>>>(starts, n_starts_dev, w, len, step, sc);
         const uint64_t nsb = (nbl + 63) / 64;
-        cs_super<<<(unsigned)((nsb + 3) / 4), 256, 0, s>>>(starts, n_starts, w, len, sc);
+        cs_super<<<(unsigned)((nsb + 3) / 4), 256, 0, s>>>(starts, n_starts_dev, w, len, sc);
         cs_fix<<<1, 64, 0, s>>>(starts, n_starts_dev, w, len, step, sc);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -312,22 +315,39 @@ __device__ __forceinline__ uint32_t len_class(uint64_t n) {
     return (uint32_t)(msb * 4 + ((n >> (msb - 2)) & 3));
 }
 
-// Segment j is [starts[j], ends[j]), or [ends[j-1], ends[j]) without starts.
-__device__ __forceinline__ uint64_t seg_start(const uint64_t *starts, const uint64_t *ends, uint64_t j) {
-    return starts ? starts[j] : (j ? ends[j - 1] : 0);
+// Segment j is [starts[j], ends[j]) (segments the library laid out), or
+// without starts [ends[j-1], ends[j]) of a buffer of len bytes, each end
+// clamped to len and a decreasing end read as an empty segment, so that ends
+// from the caller never lead outside the buffer.
+struct Seg {
+    uint64_t s, e;
+};
+__device__ __forceinline__ Seg seg_of(const uint64_t *starts, const uint64_t *ends, uint64_t len, uint64_t j) {
+    if (starts) return {starts[j], ends[j]};
+    const uint64_t a = j ? (ends[j - 1] < len ? ends[j - 1] : len) : 0;
+    const uint64_t b = ends[j] < len ? ends[j] : len;
+    return {a, b > a ? b : a};
 }
-__device__ __forceinline__ uint64_t seg_len(const uint64_t *starts, const uint64_t *ends, uint64_t j) {
-    return ends[j] - seg_start(starts, ends, j);
+__device__ __forceinline__ uint64_t seg_len(const uint64_t *starts, const uint64_t *ends, uint64_t len, uint64_t j) {
+    const Seg g = seg_of(starts, ends, len, j);
+    return g.e - g.s;
+}
+// The number of segments: *n_dev, at most max_n (the bound grids and
+// scratch were sized for).
+__device__ __forceinline__ uint64_t seg_count(const uint64_t *n_dev, uint64_t max_n) {
+    const uint64_t n = *n_dev;
+    return n < max_n ? n : max_n;
 }
 
 __global__ __launch_bounds__(256) void seg_hist(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ ends,
-                                                const uint64_t *__restrict__ n_dev, uint32_t *__restrict__ hist) {
+                                                uint64_t len, const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[SEG_CLASSES];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t n = *n_dev;
+    const uint64_t n = seg_count(n_dev, max_n);
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[len_class(seg_len(starts, ends, t))], 1u);
+        atomicAdd(&h[len_class(seg_len(starts, ends, len, t))], 1u);
     __syncthreads();
     if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
@@ -355,22 +375,22 @@ __global__ __launch_bounds__(SEG_CLASSES) void seg_offsets(uint32_t *__restrict_
 constexpr uint32_t SCATTER_PER_WG = 2048;
 
 __global__ __launch_bounds__(256) void seg_scatter(const uint64_t *__restrict__ starts, const uint64_t *__restrict__ ends,
-                                                   const uint64_t *__restrict__ n_dev, uint32_t *__restrict__ cursor,
-                                                   uint32_t *__restrict__ order) {
+                                                   uint64_t len, const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                   uint32_t *__restrict__ cursor, uint32_t *__restrict__ order) {
     __shared__ uint32_t cnt[SEG_CLASSES], base[SEG_CLASSES];
     const uint32_t t = threadIdx.x;
-    const uint64_t n = *n_dev;
+    const uint64_t n = seg_count(n_dev, max_n);
     const uint64_t lo = (uint64_t)blockIdx.x * SCATTER_PER_WG;
     const uint64_t hi = lo + SCATTER_PER_WG < n ? lo + SCATTER_PER_WG : n;
     cnt[t] = 0;
     __syncthreads();
-    for (uint64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[len_class(seg_len(starts, ends, i))], 1u);
+    for (uint64_t i = lo + t; i < hi; i += 256) atomicAdd(&cnt[len_class(seg_len(starts, ends, len, i))], 1u);
     __syncthreads();
     base[t] = cnt[t] ? atomicAdd(&cursor[t], cnt[t]) : 0;
     cnt[t] = 0;
     __syncthreads();
     for (uint64_t i = lo + t; i < hi; i += 256) {
-        const uint32_t c = len_class(seg_len(starts, ends, i));
+        const uint32_t c = len_class(seg_len(starts, ends, len, i));
         order[base[c] + atomicAdd(&cnt[c], 1u)] = (uint32_t)i;
     }
 }
@@ -379,19 +399,19 @@ template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void segment_digest_kernel(const uint8_t *__restrict__ in, uint64_t len,
                                                              const uint64_t *__restrict__ starts,
                                                              const uint64_t *__restrict__ ends,
-                                                             const uint64_t *__restrict__ n_dev,
+                                                             const uint64_t *__restrict__ n_dev, uint64_t max_n,
                                                              const uint32_t *__restrict__ order,
                                                              uint8_t *__restrict__ out) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *n_dev) return;
+    if (t >= seg_count(n_dev, max_n)) return;
     const uint64_t j = order[t];
-    const uint64_t s0 = seg_start(starts, ends, j);
+    const Seg g = seg_of(starts, ends, len, j);
     // Without explicit starts the segments tile [0, len) of one buffer and a
     // tail may be loaded as a whole block below in + len; with explicit
     // starts (files of an arena) only the segment's own bytes are read.
-    const uint8_t *buf_end = starts ? in + ends[j] : in + len;
+    const uint8_t *buf_end = starts ? in + g.e : in + len;
     uint32_t st[5];
-    hash_range<KIND>(in + s0, ends[j] - s0, buf_end, st);
+    hash_range<KIND>(in + g.s, g.e - g.s, buf_end, st);
     store_digest<KIND>(out + j * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 
@@ -408,15 +428,15 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
     hipError_t e = launch_fill_u32(hist, SEG_CLASSES, 0, s);
     if (e != hipSuccess) return e;
     const unsigned sgrid = (unsigned)std::min<uint64_t>((max_n + 255) / 256, 1024);
-    seg_hist<<<sgrid, 256, 0, s>>>(starts, ends, n_dev, hist);
+    seg_hist<<<sgrid, 256, 0, s>>>(starts, ends, len, n_dev, max_n, hist);
     seg_offsets<<<1, SEG_CLASSES, 0, s>>>(hist);
-    seg_scatter<<<(unsigned)((max_n + SCATTER_PER_WG - 1) / SCATTER_PER_WG), 256, 0, s>>>(starts, ends, n_dev, hist,
-                                                                                           order);
+    seg_scatter<<<(unsigned)((max_n + SCATTER_PER_WG - 1) / SCATTER_PER_WG), 256, 0, s>>>(starts, ends, len, n_dev,
+                                                                                           max_n, hist, order);
     const unsigned grid = (unsigned)((max_n + 255) / 256);
     if (kind == KIND_MD5)
-        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, order, out);
+        segment_digest_kernel<KIND_MD5><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, max_n, order, out);
     else
-        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, order, out);
+        segment_digest_kernel<KIND_SHA1><<<grid, 256, 0, s>>>(in, len, starts, ends, n_dev, max_n, order, out);
     return hipGetLastError();
 }
 
@@ -432,8 +452,8 @@ hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, con
 // so consecutive chunks never share a slot, and the slot count is at most
 // floor(len / S) + n + 1.
 
-__device__ __forceinline__ uint64_t tl_first(const uint64_t *ends, uint64_t j, uint64_t S) {
-    return (j ? ends[j - 1] : 0) / S + j;
+__device__ __forceinline__ uint64_t tl_first(const uint64_t *ends, uint64_t len, uint64_t j, uint64_t S) {
+    return seg_of(nullptr, ends, len, j).s / S + j;
 }
 
 // One lane per slot p: the chunk whose range of slots holds p (the largest j
@@ -441,18 +461,19 @@ __device__ __forceinline__ uint64_t tl_first(const uint64_t *ends, uint64_t j, u
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void tl_leaf_kernel(
     const uint8_t *__restrict__ in, uint64_t len, const uint64_t *__restrict__ ends,
-    const uint64_t *__restrict__ n_dev, uint64_t S, uint64_t n_slots, uint8_t *__restrict__ leaves) {
+    const uint64_t *__restrict__ n_dev, uint64_t max_n, uint64_t S, uint64_t n_slots, uint8_t *__restrict__ leaves) {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t n = *n_dev;
+    const uint64_t n = seg_count(n_dev, max_n);
     if (p >= n_slots || n == 0) return;
     uint64_t lo = 0, hi = n - 1;
     while (lo < hi) {
         const uint64_t mid = hi - ((hi - lo) >> 1);
-        if (tl_first(ends, mid, S) <= p) lo = mid;
+        if (tl_first(ends, len, mid, S) <= p) lo = mid;
         else hi = mid - 1;
     }
-    const uint64_t start = lo ? ends[lo - 1] : 0, clen = ends[lo] - start;
-    const uint64_t k = p - tl_first(ends, lo, S);
+    const Seg g = seg_of(nullptr, ends, len, lo);
+    const uint64_t start = g.s, clen = g.e - g.s;
+    const uint64_t k = p - tl_first(ends, len, lo, S);
     if (k >= (clen + S - 1) / S) return;  // a slot between two chunks' ranges
     const uint64_t s0 = start + k * S;
     const uint64_t sl = clen - k * S < S ? clen - k * S : S;
@@ -464,14 +485,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void t
 // One lane per chunk: the digest of its ceil(len_j / S) segment digests.
 template <int KIND>
 __global__ __launch_bounds__(256) void tl_root_kernel(const uint8_t *__restrict__ leaves, uint64_t n_slots,
-                                                      const uint64_t *__restrict__ ends,
-                                                      const uint64_t *__restrict__ n_dev, uint64_t S,
+                                                      uint64_t len, const uint64_t *__restrict__ ends,
+                                                      const uint64_t *__restrict__ n_dev, uint64_t max_n, uint64_t S,
                                                       uint8_t *__restrict__ out) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= *n_dev) return;
+    if (j >= seg_count(n_dev, max_n)) return;
     constexpr uint64_t D = Hash<KIND>::DIGEST;
-    const uint64_t start = j ? ends[j - 1] : 0, clen = ends[j] - start;
-    const uint8_t *p = leaves + tl_first(ends, j, S) * D;
+    const Seg g = seg_of(nullptr, ends, len, j);
+    const uint64_t clen = g.e - g.s;
+    // first + ceil(clen / S) <= floor(e / S) + 1 + j < n_slots for clamped
+    // ends: the digests read lie inside the slots.
+    const uint8_t *p = leaves + tl_first(ends, len, j, S) * D;
     uint32_t st[5];
     hash_range<KIND>(p, (clen + S - 1) / S * D, leaves + n_slots * D, st);
     store_digest<KIND>(out + j * D, st);
@@ -486,11 +510,11 @@ hipError_t launch_chunk_digests_two_level(int kind, const uint8_t *in, uint64_t 
     const uint64_t slots = two_level_slots(len, max_n, S);
     const unsigned lgrid = (unsigned)((slots + 255) / 256), rgrid = (unsigned)((max_n + 255) / 256);
     if (kind == KIND_MD5) {
-        tl_leaf_kernel<KIND_MD5><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, S, slots, leaves);
-        tl_root_kernel<KIND_MD5><<<rgrid, 256, 0, s>>>(leaves, slots, ends, n_dev, S, out);
+        tl_leaf_kernel<KIND_MD5><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, max_n, S, slots, leaves);
+        tl_root_kernel<KIND_MD5><<<rgrid, 256, 0, s>>>(leaves, slots, len, ends, n_dev, max_n, S, out);
     } else {
-        tl_leaf_kernel<KIND_SHA1><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, S, slots, leaves);
-        tl_root_kernel<KIND_SHA1><<<rgrid, 256, 0, s>>>(leaves, slots, ends, n_dev, S, out);
+        tl_leaf_kernel<KIND_SHA1><<<lgrid, 256, 0, s>>>(in, len, ends, n_dev, max_n, S, slots, leaves);
+        tl_root_kernel<KIND_SHA1><<<rgrid, 256, 0, s>>>(leaves, slots, len, ends, n_dev, max_n, S, out);
     }
     return hipGetLastError();
 }
@@ -518,12 +542,15 @@ template <int D>
 __global__ __launch_bounds__(256) void set_probe(const uint8_t *__restrict__ dig_a,
                                                  const uint8_t *__restrict__ dig_b,
                                                  const uint64_t *__restrict__ len_b, int len_is_ends,
-                                                 uint64_t n_b, const uint32_t *__restrict__ table,
+                                                 uint64_t n_b, const uint64_t *__restrict__ n_b_dev,
+                                                 const uint32_t *__restrict__ table,
                                                  uint64_t slot_mask, unsigned long long *__restrict__ counters) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // With a device count, n_b is its bound.
+    const uint64_t nb = n_b_dev && *n_b_dev < n_b ? *n_b_dev : n_b;
     bool hit = false;
     uint64_t bytes = 0;
-    if (i < n_b) {
+    if (i < nb) {
         const uint8_t *d = dig_b + i * D;
         uint64_t slot = dig_hash<D>(d) & slot_mask;
         for (uint64_t probe = 0; probe <= slot_mask; probe++) {
@@ -546,6 +573,29 @@ __global__ __launch_bounds__(256) void set_probe(const uint8_t *__restrict__ dig
         atomicAdd(&counters[0], hits);
         atomicAdd(&counters[1], b);
     }
+}
+
+// out[0] = min(*n, max), out[1] = (*n > max).
+__global__ void count_clamp_kernel(const uint64_t *__restrict__ n, uint64_t max, uint64_t *__restrict__ out) {
+    if (threadIdx.x == 0) {
+        const uint64_t v = *n;
+        out[0] = v < max ? v : max;
+        out[1] = v > max ? 1 : 0;
+    }
+}
+
+hipError_t launch_count_clamp(const uint64_t *n, uint64_t max, uint64_t *out, hipStream_t s) {
+    count_clamp_kernel<<<1, 64, 0, s>>>(n, max, out);
+    return hipGetLastError();
+}
+
+__global__ void count_invalidate_kernel(const uint64_t *__restrict__ flag, uint64_t *__restrict__ n) {
+    if (threadIdx.x == 0 && *flag) *n = ~0ull;
+}
+
+hipError_t launch_count_invalidate(const uint64_t *flag, uint64_t *n, hipStream_t s) {
+    count_invalidate_kernel<<<1, 64, 0, s>>>(flag, n);
+    return hipGetLastError();
 }
 
 __global__ void fill_u32_kernel(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
@@ -579,8 +629,8 @@ hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_
 }
 
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
-                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
-                             int log2_slots, unsigned long long *counters, hipStream_t s) {
+                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, const uint64_t *n_b_dev,
+                             uint32_t *table, int log2_slots, unsigned long long *counters, hipStream_t s) {
     const uint64_t slots = 1ull << log2_slots;
     hipError_t e = launch_fill_u32(table, slots, 0, s);
     if (e != hipSuccess) return e;
@@ -596,9 +646,9 @@ hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const
     if (n_b) {
         const unsigned g = (unsigned)((n_b + 255) / 256);
         if (kind == KIND_MD5)
-            set_probe<16><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, table, mask, counters);
+            set_probe<16><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, n_b_dev, table, mask, counters);
         else
-            set_probe<20><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, table, mask, counters);
+            set_probe<20><<<g, 256, 0, s>>>(dig_a, dig_b, len_b, len_is_ends, n_b, n_b_dev, table, mask, counters);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

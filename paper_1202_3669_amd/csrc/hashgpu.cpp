@@ -798,9 +798,11 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
                          : HG_OK;
 }
 
-int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b, const uint64_t *len_b,
-                  uint64_t n_b, int digest, uint64_t *matched, uint64_t *matched_bytes, uint32_t flags,
-                  void *stream) {
+// B has n_b digests, or with n_b_dev (device or host per HG_IN_DEVICE)
+// min(*n_b_dev, n_b) of them, read when the work runs.
+static int similarity_impl(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b, const uint64_t *len_b,
+                           uint64_t n_b, const uint64_t *n_b_dev, int digest, uint64_t *matched,
+                           uint64_t *matched_bytes, uint32_t flags, void *stream) {
     HG_TRY(enter(ctx));
     const bool len_ends = flags & HG_LEN_ENDS;
     flags &= ~(uint32_t)HG_LEN_ENDS;
@@ -813,6 +815,13 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
         return fail(ctx, HG_EINVAL, "n_a and n_b must be below 2^31");
     hipStream_t st = (hipStream_t)stream;
     const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    if (n_b_dev && !in_dev) {
+        // A host count: B is simply that long.
+        n_b = std::min(*n_b_dev, n_b);
+        n_b_dev = nullptr;
+    }
     const uint8_t *da, *db, *dl = nullptr;
     HG_TRY(device_input(ctx, SLOT_IN, dig_a, n_a * (uint64_t)d, in_dev, st, &da));
     HG_TRY(device_input(ctx, SLOT_IN2, dig_b, n_b * (uint64_t)d, in_dev, st, &db));
@@ -821,15 +830,140 @@ int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_
     while ((1ull << log2_slots) < 2 * n_a) log2_slots++;
     void *table;
     HG_TRY(ensure(ctx, SLOT_TABLE, (1ull << log2_slots) * 4, st, &table));
-    uint64_t *small;
-    HG_TRY(small_words(ctx, st, &small));
     unsigned long long *counters = (unsigned long long *)&small[4];
     HG_LAUNCH(ctx, HG_K_SIMILARITY, st,
-              hg::launch_similarity(digest, da, n_a, db, (const uint64_t *)dl, len_ends ? 1 : 0, n_b,
+              hg::launch_similarity(digest, da, n_a, db, (const uint64_t *)dl, len_ends ? 1 : 0, n_b, n_b_dev,
                                     (uint32_t *)table, log2_slots, counters, st));
     HG_TRY(copy_out(ctx, matched, &counters[0], 8, out_dev, st));
     if (matched_bytes) HG_TRY(copy_out(ctx, matched_bytes, &counters[1], 8, out_dev, st));
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
+    return HG_OK;
+}
+
+int hg_similarity(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b, const uint64_t *len_b,
+                  uint64_t n_b, int digest, uint64_t *matched, uint64_t *matched_bytes, uint32_t flags,
+                  void *stream) {
+    return similarity_impl(ctx, dig_a, n_a, dig_b, len_b, n_b, nullptr, digest, matched, matched_bytes, flags,
+                           stream);
+}
+
+int hg_similarity_n(hg_ctx *ctx, const void *dig_a, uint64_t n_a, const void *dig_b, const uint64_t *len_b,
+                    const uint64_t *n_b, uint64_t max_b, int digest, uint64_t *matched, uint64_t *matched_bytes,
+                    uint32_t flags, void *stream) {
+    if (ctx && !n_b) return fail(ctx, HG_EINVAL, "n_b is NULL");
+    return similarity_impl(ctx, dig_a, n_a, dig_b, len_b, max_b, n_b, digest, matched, matched_bytes, flags,
+                           stream);
+}
+
+int hg_chunk_select(hg_ctx *ctx, const uint64_t *starts, const uint64_t *n_starts, uint64_t max_starts,
+                    uint64_t len, uint32_t window, uint64_t min_chunk, uint64_t max_chunk, uint64_t *ends,
+                    uint64_t capacity, uint64_t *n_chunks, uint32_t flags, void *stream) {
+    HG_TRY(enter(ctx));
+    HG_TRY(check_flags(ctx, flags, true));
+    if (window == 0 || window > HG_MAX_WINDOW)
+        return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
+    const uint64_t step = min_chunk ? min_chunk : 1;
+    if (max_chunk != 0 && max_chunk < step)
+        return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
+    if (!n_starts || !n_chunks || !ends) return fail(ctx, HG_EINVAL, "n_starts, n_chunks or ends is NULL");
+    if (max_starts && !starts) return fail(ctx, HG_EINVAL, "starts is NULL with max_starts > 0");
+    const uint64_t bound = max_starts + 1 + (max_chunk ? 1 + len / max_chunk : 0);
+    if (bound >= hg::MAX_LANES)
+        return fail(ctx, HG_EINVAL, "max_starts %llu above the limit of 2^31 per call", (unsigned long long)max_starts);
+    if (capacity < bound)
+        return fail(ctx, HG_EINVAL, "capacity %llu below the bound %llu (max_starts + 1, plus len / max_chunk + 1)",
+                    (unsigned long long)capacity, (unsigned long long)bound);
+    hipStream_t st = (hipStream_t)stream;
+    const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    // small[8]: candidates used, small[9]: the list was incomplete,
+    // small[10]: chunk count when the output is host memory.
+    const uint64_t *dstarts = starts;
+    if (in_dev) {
+        HG_HIP(ctx, hg::launch_count_clamp(n_starts, max_starts, &small[8], st));
+    } else {
+        const uint64_t k = std::min(*n_starts, max_starts);
+        ctx->host_small[0] = k;
+        ctx->host_small[1] = *n_starts > max_starts ? 1 : 0;
+        HG_HIP(ctx, hipMemcpyAsync(&small[8], ctx->host_small, 16, hipMemcpyHostToDevice, st));
+        const uint8_t *p;
+        HG_TRY(device_input(ctx, SLOT_CAND, starts, k * 8, false, st, &p));
+        dstarts = (const uint64_t *)p;
+        HG_HIP(ctx, hipStreamSynchronize(st));  // host_small is reused below
+    }
+    void *dends = ends;
+    if (!out_dev) HG_TRY(ensure(ctx, SLOT_ENDS, bound * 8, st, &dends));
+    uint64_t *dn = out_dev ? n_chunks : &small[10];
+    if (max_chunk) {
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_chunk_select_max(dstarts, &small[8], window, len, min_chunk, max_chunk,
+                                              (uint64_t *)dends, bound, dn, st));
+    } else {
+        void *sel;
+        HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(max_starts), st, &sel));
+        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
+                  hg::launch_chunk_select(dstarts, &small[8], max_starts, window, len, min_chunk, sel,
+                                          (uint64_t *)dends, bound, dn, st));
+    }
+    HG_HIP(ctx, hg::launch_count_invalidate(&small[9], dn, st));
+    if (out_dev) {
+        if (flags & HG_ASYNC) return HG_OK;
+        uint64_t nc;
+        HG_TRY(read_u64(ctx, dn, st, &nc));
+        return nc == ~0ull ? fail(ctx, HG_ETRUNC, "the candidate list is incomplete (*n_starts > max_starts)")
+                           : HG_OK;
+    }
+    uint64_t nc;
+    HG_TRY(read_u64(ctx, dn, st, &nc));
+    *n_chunks = nc;
+    if (nc == ~0ull) return fail(ctx, HG_ETRUNC, "the candidate list is incomplete (*n_starts > max_starts)");
+    HG_TRY(copy_out(ctx, ends, dends, nc * 8, false, st));
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    return HG_OK;
+}
+
+int hg_chunk_digests(hg_ctx *ctx, const void *in, uint64_t len, const uint64_t *ends, const uint64_t *n_chunks,
+                     uint64_t max_chunks, int digest, uint64_t chunk_segment, void *digests, uint32_t flags,
+                     void *stream) {
+    HG_TRY(enter(ctx));
+    HG_TRY(check_flags(ctx, flags, true));
+    const int d = digest_bytes(digest);
+    if (d < 0) return fail(ctx, HG_EINVAL, "unknown digest %d", digest);
+    if (!n_chunks || !digests) return fail(ctx, HG_EINVAL, "n_chunks or digests is NULL");
+    if (max_chunks && !ends) return fail(ctx, HG_EINVAL, "ends is NULL with max_chunks > 0");
+    if (len && !in) return fail(ctx, HG_EINVAL, "in is NULL");
+    if (max_chunks >= hg::MAX_LANES) return fail(ctx, HG_EINVAL, "max_chunks must be below 2^31");
+    hipStream_t st = (hipStream_t)stream;
+    const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
+    uint64_t *small;
+    HG_TRY(small_words(ctx, st, &small));
+    const uint8_t *din = (const uint8_t *)in;
+    const uint64_t *dends = ends, *dn = n_chunks;
+    uint64_t k = max_chunks;
+    if (!in_dev) {
+        k = std::min(*n_chunks, max_chunks);
+        const uint8_t *p;
+        HG_TRY(device_input(ctx, SLOT_IN, in, len, false, st, &din));
+        HG_TRY(device_input(ctx, SLOT_CAND, ends, k * 8, false, st, &p));
+        dends = (const uint64_t *)p;
+        ctx->host_small[0] = k;
+        HG_HIP(ctx, hipMemcpyAsync(&small[11], ctx->host_small, 8, hipMemcpyHostToDevice, st));
+        HG_HIP(ctx, hipStreamSynchronize(st));
+        dn = &small[11];
+    }
+    void *dout = digests;
+    if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, std::max<uint64_t>(k, 1) * d, st, &dout));
+    hg_chunk_params p{};
+    p.chunk_digest = digest;
+    p.chunk_segment = chunk_segment;
+    HG_TRY(chunk_digests_of(ctx, p, din, len, dends, dn, k, (uint8_t *)dout, st));
+    if (!out_dev) {
+        HG_TRY(copy_out(ctx, digests, dout, k * (uint64_t)d, false, st));
+        HG_HIP(ctx, hipStreamSynchronize(st));
+    } else if (!(flags & HG_ASYNC)) {
+        HG_HIP(ctx, hipStreamSynchronize(st));
+    }
     return HG_OK;
 }
 

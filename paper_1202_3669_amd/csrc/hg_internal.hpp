@@ -201,10 +201,11 @@ hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *p
 // Open-addressing set of A's digests (table of 2^log2_slots uint32 slots),
 // then a probe of every B digest; matched count and matched byte sum land in
 // counters[0], counters[1] (cleared by the launcher).
-// len_b holds lengths, or chunk end offsets when len_is_ends is set.
+// len_b holds lengths, or chunk end offsets when len_is_ends is set.  With
+// n_b_dev, B has min(*n_b_dev, n_b) digests (read when the kernel runs).
 hipError_t launch_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const uint8_t *dig_b,
-                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, uint32_t *table,
-                             int log2_slots, unsigned long long *counters, hipStream_t s);
+                             const uint64_t *len_b, int len_is_ends, uint64_t n_b, const uint64_t *n_b_dev,
+                             uint32_t *table, int log2_slots, unsigned long long *counters, hipStream_t s);
 
 // ---------------------------------------------------------------- probes --
 // int32 VALU issue-rate and HBM read-rate microbenchmarks (out: a 4-byte
@@ -235,6 +236,11 @@ hipError_t launch_blockmap_write(int kind, const BlockMapView &m, const uint8_t 
 // dst[i] = src[i] + add for i < *n_dev (<= max_n, which sizes the grid).
 hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_dev, uint64_t max_n, uint64_t add,
                           hipStream_t s);
+
+// out[0] = min(*n, max) and out[1] = 1 if *n > max, else 0 (one kernel);
+// then *n_out = ~0 where *flag is set.
+hipError_t launch_count_clamp(const uint64_t *n, uint64_t max, uint64_t *out, hipStream_t s);
+hipError_t launch_count_invalidate(const uint64_t *flag, uint64_t *n_out, hipStream_t s);
 
 // Fill n 32-bit words with v (a kernel, so that captured graphs hold no
 // memset nodes).

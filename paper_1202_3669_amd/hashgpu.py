@@ -101,6 +101,12 @@ hg_chunk = _declare("hg_chunk", _int,
                     [_vp, _vp, _u64, ctypes.POINTER(hg_chunk_params), _vp, _u64, _vp, _vp, _u32, _vp])
 hg_similarity = _declare("hg_similarity", _int,
                          [_vp, _vp, _u64, _vp, _vp, _u64, _int, _vp, _vp, _u32, _vp])
+hg_chunk_select = _declare("hg_chunk_select", _int,
+                           [_vp, _vp, _vp, _u64, _u64, _u32, _u64, _u64, _vp, _u64, _vp, _u32, _vp])
+hg_chunk_digests = _declare("hg_chunk_digests", _int,
+                            [_vp, _vp, _u64, _vp, _vp, _u64, _int, _u64, _vp, _u32, _vp])
+hg_similarity_n = _declare("hg_similarity_n", _int,
+                           [_vp, _vp, _u64, _vp, _vp, _vp, _u64, _int, _vp, _vp, _u32, _vp])
 hg_leaves_batch = _declare("hg_leaves_batch", _int, [_vp, _vp, _u32, _u32, _vp])
 hg_roots_batch = _declare("hg_roots_batch", _int, [_vp, _vp, _u32, _u32, _vp])
 hg_block_hash_batch = _declare("hg_block_hash_batch", _int, [_vp, _vp, _u32, _u32, _vp])
@@ -155,7 +161,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_timing_origin", "hg_timing_intervals", "hg_probe_alu", "hg_probe_read",
             "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
             "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset", "hg_blockmap_create",
-            "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write"]
+            "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write", "hg_chunk_select",
+            "hg_chunk_digests", "hg_similarity_n"]
 
 
 class HashGpuError(RuntimeError):
@@ -266,11 +273,21 @@ class Context:
 
     # ----------------------------------------------------- sliding window --
     def window_scan(self, data, window: int, stride: int, mask: int, target: int,
-                    digest: int = HG_MD5, capacity: int | None = None, stream=None):
-        """Ascending candidate start offsets (int64 CUDA tensor)."""
+                    digest: int = HG_MD5, capacity: int | None = None, stream=None, out=None):
+        """Ascending candidate start offsets (int64 CUDA tensor).  With
+        out = (starts, count) preallocated CUDA int64 tensors the scan is
+        only enqueued (HG_ASYNC): count[0] gets the total found, starts the
+        first len(starts) of them; returns out."""
         torch = _torch()
         dev = torch.device("cuda", self.device)
         n = data.numel()
+        if out is not None:
+            starts, cnt = out
+            st = hg_window_scan(self.handle, data.data_ptr() if n else None, n, window, stride, mask, target,
+                                digest, starts.data_ptr(), starts.numel(), cnt.data_ptr(),
+                                HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC, _stream_handle(stream))
+            self._check(st)
+            return out
         nwin = (n - window) // stride + 1 if n >= window else 0
         if capacity is None:
             capacity = min(nwin, 4096 + nwin // 1024)
@@ -338,6 +355,68 @@ class Context:
                 return ends[:k], (dig[:k] if dig is not None else None)
             capacity = k
         raise HashGpuError(HG_ETRUNC, "chunk count changed between calls")
+
+    # ------------------------------------------------- chunking stages --
+    def chunk_select(self, starts, n_starts, length: int, window: int, min_chunk: int, max_chunk: int = 0,
+                     out=None, asynchronous: bool = False, stream=None):
+        """hg_chunk_select on CUDA tensors: starts (int64, room for
+        len(starts) candidates) and n_starts (int64, one count).  Returns
+        (ends, n) CUDA tensors; without asynchronous, ends[:n]."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        m = starts.numel()
+        bound = m + 1 + (length // max_chunk + 1 if max_chunk else 0)
+        if out is None:
+            out = (torch.empty(bound, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+        ends, n = out
+        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
+        self._check(hg_chunk_select(self.handle, starts.data_ptr() if m else None, n_starts.data_ptr(), m, length,
+                                    window, min_chunk, max_chunk, ends.data_ptr(), ends.numel(), n.data_ptr(),
+                                    flags, _stream_handle(stream)))
+        if asynchronous:
+            return ends, n
+        return ends[:int(n.item())], n
+
+    def chunk_digests(self, data, ends, n_chunks, digest: int = HG_SHA1, chunk_segment: int = 0, out=None,
+                      asynchronous: bool = False, stream=None):
+        """hg_chunk_digests on CUDA tensors: ends (int64, room for len(ends)
+        chunks), n_chunks (int64, one count).  Returns the (len(ends), d)
+        digest tensor (the first n_chunks rows are the digests)."""
+        torch = _torch()
+        m = ends.numel()
+        d = DIGEST_SIZE[digest]
+        if out is None:
+            out = torch.empty((max(m, 1), d), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
+        n = data.numel()
+        self._check(hg_chunk_digests(self.handle, data.data_ptr() if n else None, n, ends.data_ptr() if m else None,
+                                     n_chunks.data_ptr(), m, digest, chunk_segment, out.data_ptr(), flags,
+                                     _stream_handle(stream)))
+        return out
+
+    def similarity_n(self, dig_a, dig_b, n_b, ends_b=None, len_b=None, digest: int = HG_SHA1, out=None,
+                     asynchronous: bool = False, stream=None):
+        """hg_similarity_n: B's count n_b is a CUDA int64 tensor read when
+        the work runs.  Returns (matched, matched_bytes), or with
+        asynchronous=True leaves them in `out` (int64 CUDA tensor of 2)."""
+        torch = _torch()
+        d = DIGEST_SIZE[digest]
+        a = dig_a.reshape(-1, d)
+        b = dig_b.reshape(-1, d)
+        res = torch.zeros(2, dtype=torch.int64, device=torch.device("cuda", self.device)) if out is None else out
+        lens = ends_b if ends_b is not None else len_b
+        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_LEN_ENDS if ends_b is not None else 0)
+        if asynchronous:
+            flags |= HG_ASYNC
+        self._check(hg_similarity_n(self.handle, a.data_ptr() if a.numel() else None, a.shape[0],
+                                    b.data_ptr() if b.numel() else None,
+                                    lens.data_ptr() if lens is not None and lens.numel() else None,
+                                    n_b.data_ptr(), b.shape[0], digest, res.data_ptr(), res[1:].data_ptr(), flags,
+                                    _stream_handle(stream)))
+        if asynchronous:
+            return None
+        r = res.cpu()
+        return int(r[0]), int(r[1])
 
     # ------------------------------------------------------------- timing --
     def timing(self, enable: bool = True):
