@@ -54,6 +54,8 @@ WINDOW_OPS = 19 * 5 + 42 * 4
 BLOCK_OPS = {0: 324, 1: 613}
 # Chunking streams (steps round-robin), each driven by its own host thread.
 CHUNK_STREAMS = 3
+CHUNK_CALLS = "single"
+AHEAD = 8  # stages mode: steps queued ahead of the last finished chunking
 
 
 def padded_blocks(n):
@@ -76,6 +78,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=12)
     ap.add_argument("--group", type=int, default=24, help="steps per long-chain batch")
+    ap.add_argument("--chunk-calls", choices=["single", "stages"], default=CHUNK_CALLS,
+                    help="one hg_chunk per step (host threads wait on its counts), or the chunking "
+                         "stages with device counts (window scans back to back on one stream)")
     ap.add_argument("--chunk-streams", type=int, default=CHUNK_STREAMS,
                     help="chunking streams (steps go round-robin over them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -108,6 +113,7 @@ class Pipeline:
         # steps' window scans; the short segment batch has a stream of its
         # own so that it overlaps the window scans as well.
         self.NA = CHUNK_STREAMS
+        self.staged = CHUNK_CALLS == "stages"
         self.sa = [torch.cuda.Stream() for _ in range(self.NA)]
         self.sb = torch.cuda.Stream()
         self.s1 = torch.cuda.Stream()
@@ -125,6 +131,22 @@ class Pipeline:
         # Chunk outputs per chunking stream (capacity: every chunk but the last is
         # >= 2 KiB).
         self.cap = n // (2 * KiB) + 1
+        if self.staged:
+            # Stages: the window scans of consecutive steps back to back on
+            # one stream (each has the whole machine but for what overlaps
+            # it), the boundary decision, chunk digests and similarity of
+            # step i on chunking stream i % NA, every count on the device.
+            # Candidate room: twice the expectation of a 12-bit mask plus
+            # slack; a larger count would mark the step's result invalid,
+            # which run() checks.
+            self.sw = torch.cuda.Stream()
+            self.ctxw = hg.Context(0)
+            self.cand_cap = n // 2048 + 4096
+            self.cap = self.cand_cap + 1
+            self.starts = [torch.empty(self.cand_cap, dtype=torch.int64, device=dev) for _ in range(self.NA)]
+            self.cnt = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(self.NA)]
+            self.nch = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(self.NA)]
+            self.sel_done = [None] * self.NA
         self.ends = [torch.empty(self.cap, dtype=torch.int64, device=dev) for _ in range(self.NA)]
         self.digs = [torch.empty((self.cap, 20), dtype=torch.uint8, device=dev) for _ in range(self.NA)]
         self.nchunks = 0
@@ -150,6 +172,7 @@ class Pipeline:
         self.group_done = {}
         self.issue_ev = {}
         self.issue_ev_a = {}
+        self.chunk_done = {}
         # One host thread per chunking stream: hg_chunk waits on the host for
         # its candidate and chunk counts, and those waits must not hold up
         # the other stream or the rest of the step.
@@ -172,7 +195,10 @@ class Pipeline:
         ev.record(self.sb)
         self.issue_ev[i] = ev
         self.ctx0.run_batch(self.short_tables[slot], len(SHORT), "leaves", stream=self.sb)
-        self.futures.append(self.pool[i % self.NA].submit(self._chunk, i, slot))
+        if self.staged:
+            self._chunk_stages(i, slot)
+        else:
+            self.futures.append(self.pool[i % self.NA].submit(self._chunk, i, slot))
         if i % self.G == self.G - 1:
             self.close_group(g)
 
@@ -186,7 +212,39 @@ class Pipeline:
         ends, digs = ca.chunk(self.data, 20, 1, 0xFFF, 0, 2 * KiB, stream=sa,
                               out=(self.ends[p], self.digs[p]), asynchronous=True)
         ca.similarity(self.prev, digs, stream=sa, ends_b=ends, out=self.sim[slot], asynchronous=True)
+        done = self.torch.cuda.Event(enable_timing=True)
+        done.record(sa)
+        self.chunk_done[i] = done
         return ends.numel()
+
+    def _chunk_stages(self, i, slot):
+        """Chunking and similarity of step i as separate stages, nothing
+        waiting on the host."""
+        torch = self.torch
+        p = i % self.NA
+        sa, ca = self.sa[p], self.ctxa[p]
+        if self.sel_done[p] is not None:
+            # The candidate buffer is free once the previous step that used
+            # it has taken its cuts.
+            self.sw.wait_event(self.sel_done[p])
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.sw)
+        self.issue_ev_a[i] = ev
+        self.ctxw.window_scan(self.data, 20, 1, 0xFFF, 0, out=(self.starts[p], self.cnt[p]), stream=self.sw)
+        scanned = torch.cuda.Event()
+        scanned.record(self.sw)
+        sa.wait_event(scanned)
+        ca.chunk_select(self.starts[p], self.cnt[p], self.data.numel(), 20, 2 * KiB,
+                        out=(self.ends[p], self.nch[p]), asynchronous=True, stream=sa)
+        sel = torch.cuda.Event()
+        sel.record(sa)
+        self.sel_done[p] = sel
+        ca.chunk_digests(self.data, self.ends[p], self.nch[p], out=self.digs[p], asynchronous=True, stream=sa)
+        ca.similarity_n(self.prev, self.digs[p], self.nch[p], ends_b=self.ends[p], out=self.sim[slot],
+                        asynchronous=True, stream=sa)
+        done = torch.cuda.Event(enable_timing=True)
+        done.record(sa)
+        self.chunk_done[i] = done
 
     def close_group(self, g):
         """Queue the long chains of group g: the 1 MiB segments on S1, then
@@ -214,6 +272,11 @@ class Pipeline:
 
     def run(self, first, count):
         for i in range(first, first + count):
+            if self.staged and i - AHEAD in self.chunk_done:
+                # Bounded run-ahead: nothing here waits on the host otherwise,
+                # and a step queued far behind the GPU would count its queueing
+                # as latency.
+                self.chunk_done[i - AHEAD].synchronize()
             self.step(i)
         last = first + count - 1
         if last % self.G != self.G - 1:
@@ -221,13 +284,22 @@ class Pipeline:
         for f in self.futures:
             self.nchunks = f.result()
         self.futures.clear()
+        if self.staged:
+            self.torch.cuda.synchronize()
+            counts = [int(c.item()) for c in self.nch]
+            if any(c < 0 or c > self.cap for c in counts):
+                raise RuntimeError(f"a step's candidate list exceeded its room: chunk counts {counts}")
+            self.nchunks = counts[last % self.NA]
 
     def latencies_ms(self, first, count):
         out = []
         for i in range(first, first + count):
-            done = self.group_done[i // self.G]
-            # From the first of the step's launches to its group's last root.
-            out.append(max(self.issue_ev[i].elapsed_time(done), self.issue_ev_a[i].elapsed_time(done)))
+            # From the first of the step's launches to the later of its
+            # similarity and its group's last root.
+            t0 = self.issue_ev[i]
+            start = min(0.0, t0.elapsed_time(self.issue_ev_a[i]))
+            end = max(t0.elapsed_time(self.group_done[i // self.G]), t0.elapsed_time(self.chunk_done[i]))
+            out.append(end - start)
         return out
 
 
@@ -619,7 +691,7 @@ def main():
         sys.exit(2)
     # Three concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
-    queues = max(8, args.chunk_streams + 5)  # chunking streams + SB, S1, two S2, default
+    queues = max(8, args.chunk_streams + 6)  # chunking streams + window, SB, S1, two S2, default
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import numpy as np
@@ -659,8 +731,9 @@ def main():
     del prev
     torch.cuda.synchronize()
 
-    global CHUNK_STREAMS
+    global CHUNK_STREAMS, CHUNK_CALLS
     CHUNK_STREAMS = args.chunk_streams
+    CHUNK_CALLS = args.chunk_calls
     pipe = Pipeline(torch, hg, data, prev_dig, args.group)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     pipe.run(0, args.warmup)
@@ -668,7 +741,8 @@ def main():
     origin = torch.cuda.Event(enable_timing=True)
     origin.record()
     torch.cuda.synchronize()
-    for c in pipe.ctxa:
+    tctx = [pipe.ctxw] if pipe.staged else pipe.ctxa  # contexts that launch the window kernel
+    for c in tctx:
         c.timing(True)
         c.timing_reset()
         c.timing_origin(origin)
@@ -683,7 +757,7 @@ def main():
     lat = pipe.latencies_ms(first, args.steps)
     nwt, mswt = 0, 0.0
     starts, finishes = [], []
-    for c in pipe.ctxa:
+    for c in tctx:
         a, b = c.timing_read("window_tiles")
         nwt, mswt = nwt + a, mswt + b
         st_, en_ = c.timing_intervals("window_tiles")
