@@ -76,6 +76,21 @@ def test_null_context_is_rejected():
     assert hg.hg_window_scan(None, None, 0, 20, 1, 0, 0, hg.HG_MD5, None, 0,
                              ctypes.addressof(cnt), 0, None) == hg.HG_EINVAL
     assert hg.hg_last_error(None, None, 0) == hg.HG_EINVAL
+    p = hg.hg_chunk_params(20, 1, 0xFFF, 0, 2048, 0, hg.HG_MD5, hg.HG_SHA1, 0)
+    assert hg.hg_chunk(None, None, 0, ctypes.byref(p), None, 0, ctypes.addressof(cnt), None, 0,
+                       None) == hg.HG_EINVAL
+    assert hg.hg_similarity(None, None, 0, None, None, 0, hg.HG_SHA1, ctypes.addressof(cnt), None, 0,
+                            None) == hg.HG_EINVAL
+    assert hg.hg_similarity_n(None, None, 0, None, None, ctypes.addressof(cnt), 0, hg.HG_SHA1,
+                              ctypes.addressof(cnt), None, 0, None) == hg.HG_EINVAL
+    assert hg.hg_chunk_select(None, None, ctypes.addressof(cnt), 0, 0, 20, 0, 0, None, 1,
+                              ctypes.addressof(cnt), 0, None) == hg.HG_EINVAL
+    assert hg.hg_chunk_digests(None, None, 0, None, ctypes.addressof(cnt), 0, hg.HG_SHA1, 0, None, 0,
+                               None) == hg.HG_EINVAL
+    assert hg.hg_block_hash_dual(None, None, 0, 64, None, None, None, None, 0, None) == hg.HG_EINVAL
+    h = ctypes.c_void_p()
+    assert hg.hg_chunker_create(None, ctypes.byref(p), ctypes.byref(h)) == hg.HG_EINVAL
+    assert hg.hg_blockmap_create(None, hg.HG_SHA1, 16, ctypes.byref(h)) == hg.HG_EINVAL
     hg.hg_destroy(None)  # no-op
 
 
