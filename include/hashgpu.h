@@ -214,8 +214,7 @@ typedef struct {
                              * of S bytes from its start (the last one shorter),
                              * digest = H(H(seg_0) || ... || H(seg_m-1)), m =
                              * ceil(len / S) -- what hg_block_hash gives as the
-                             * root of the chunk's bytes at block size S.  Not
-                             * available in file batches (HG_EINVAL). */
+                             * root of the chunk's bytes at block size S. */
 } hg_chunk_params;
 
 /* Content-based chunking of one block: window scan, boundary decision and

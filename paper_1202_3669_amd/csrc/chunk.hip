@@ -519,6 +519,155 @@ hipError_t launch_chunk_digests_two_level(int kind, const uint8_t *in, uint64_t 
     return hipGetLastError();
 }
 
+// Two-level digests of chunks given as (start, end) pairs of an arena (file
+// batches: chunks of different files need not be in arena order).  Chunk j's
+// segment digests occupy slots first[j] .. first[j+1] - 1, first being the
+// exclusive prefix sum of ceil(len_j / S), computed in three passes: local
+// scans of 1024 chunks per workgroup with their sums, one workgroup scanning
+// the sums, and the sums added back.
+constexpr int TLS_TPB = 256, TLS_PER = 4, TLS_BLOCK = TLS_TPB * TLS_PER;
+
+__device__ __forceinline__ uint64_t tl_nseg(const uint64_t *starts, const uint64_t *ends, uint64_t j, uint64_t S) {
+    const uint64_t len = ends[j] - starts[j];
+    return (len + S - 1) / S;
+}
+
+// Exclusive scan of v over the workgroup (TLS_TPB lanes); *total gets the sum.
+__device__ __forceinline__ unsigned long long wg_exclusive(unsigned long long v, unsigned long long *total) {
+    __shared__ unsigned long long wsum[TLS_TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned long long x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    unsigned long long base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < TLS_TPB / 64; i++) {
+        base += i < wid ? wsum[i] : 0;
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(TLS_TPB) void tl_scan_local(const uint64_t *__restrict__ starts,
+                                                         const uint64_t *__restrict__ ends,
+                                                         const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                         uint64_t S, uint64_t *__restrict__ first,
+                                                         uint64_t *__restrict__ bsum) {
+    const uint64_t n = seg_count(n_dev, max_n);
+    const uint64_t i0 = (uint64_t)blockIdx.x * TLS_BLOCK + (uint64_t)threadIdx.x * TLS_PER;
+    uint64_t c[TLS_PER], t = 0;
+#pragma unroll
+    for (int q = 0; q < TLS_PER; q++) {
+        c[q] = i0 + q < n ? tl_nseg(starts, ends, i0 + q, S) : 0;
+        t += c[q];
+    }
+    unsigned long long total;
+    uint64_t run = wg_exclusive(t, &total);
+#pragma unroll
+    for (int q = 0; q < TLS_PER; q++) {
+        if (i0 + q < n) first[i0 + q] = run;
+        run += c[q];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the nb block sums in place; bsum[nb] gets
+// the total.
+__global__ __launch_bounds__(TLS_TPB) void tl_scan_sums(uint64_t *__restrict__ bsum, uint64_t nb) {
+    unsigned long long carry = 0;
+    for (uint64_t c0 = 0; c0 < nb; c0 += TLS_TPB) {
+        const uint64_t i = c0 + threadIdx.x;
+        const unsigned long long v = i < nb ? bsum[i] : 0;
+        unsigned long long total;
+        const unsigned long long ex = wg_exclusive(v, &total);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(TLS_TPB) void tl_scan_add(const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                       uint64_t *__restrict__ first,
+                                                       const uint64_t *__restrict__ bsum, uint64_t nb) {
+    const uint64_t n = seg_count(n_dev, max_n);
+    const uint64_t i0 = (uint64_t)blockIdx.x * TLS_BLOCK + (uint64_t)threadIdx.x * TLS_PER;
+    const uint64_t add = bsum[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < TLS_PER; q++)
+        if (i0 + q < n) first[i0 + q] += add;
+    if (blockIdx.x == 0 && threadIdx.x == 0) first[n] = bsum[nb];
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void tl_leaf_arena(
+    const uint8_t *__restrict__ in, const uint64_t *__restrict__ starts, const uint64_t *__restrict__ ends,
+    const uint64_t *__restrict__ n_dev, uint64_t max_n, uint64_t S, const uint64_t *__restrict__ first,
+    uint64_t n_slots, uint8_t *__restrict__ leaves) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = seg_count(n_dev, max_n);
+    if (n == 0 || p >= n_slots || p >= first[n]) return;
+    uint64_t lo = 0, hi = n - 1;  // the last chunk whose range starts at or before p
+    while (lo < hi) {
+        const uint64_t mid = hi - ((hi - lo) >> 1);
+        if (first[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    const uint64_t k = p - first[lo], clen = ends[lo] - starts[lo];
+    const uint64_t s0 = starts[lo] + k * S, sl = clen - k * S < S ? clen - k * S : S;
+    uint32_t st[5];
+    hash_range<KIND>(in + s0, sl, in + ends[lo], st);
+    store_digest<KIND>(leaves + p * (uint64_t)Hash<KIND>::DIGEST, st);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void tl_root_arena(const uint8_t *__restrict__ leaves, uint64_t n_slots,
+                                                     const uint64_t *__restrict__ first,
+                                                     const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                     uint8_t *__restrict__ out) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= seg_count(n_dev, max_n)) return;
+    constexpr uint64_t D = Hash<KIND>::DIGEST;
+    const uint64_t a = first[j] < n_slots ? first[j] : n_slots;
+    const uint64_t b = first[j + 1] < n_slots ? first[j + 1] : n_slots;
+    uint32_t st[5];
+    hash_range<KIND>(leaves + a * D, (b > a ? b - a : 0) * D, leaves + n_slots * D, st);
+    store_digest<KIND>(out + j * D, st);
+}
+
+size_t two_level_arena_scratch_bytes(uint64_t max_n) {
+    const uint64_t nb = (max_n + TLS_BLOCK - 1) / TLS_BLOCK;
+    return ((max_n + 1) * 8 + 255) / 256 * 256 + (nb + 1) * 8;
+}
+
+hipError_t launch_chunk_digests_two_level_arena(int kind, const uint8_t *arena, const uint64_t *starts,
+                                                const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n,
+                                                uint64_t S, void *scratch, uint8_t *leaves, uint64_t n_slots,
+                                                uint8_t *out, hipStream_t s) {
+    if (max_n == 0) return hipSuccess;
+    const uint64_t nb = (max_n + TLS_BLOCK - 1) / TLS_BLOCK;
+    uint64_t *first = (uint64_t *)scratch;
+    uint64_t *bsum = (uint64_t *)((uint8_t *)scratch + ((max_n + 1) * 8 + 255) / 256 * 256);
+    tl_scan_local<<<(unsigned)nb, TLS_TPB, 0, s>>>(starts, ends, n_dev, max_n, S, first, bsum);
+    tl_scan_sums<<<1, TLS_TPB, 0, s>>>(bsum, nb);
+    tl_scan_add<<<(unsigned)nb, TLS_TPB, 0, s>>>(n_dev, max_n, first, bsum, nb);
+    const unsigned lgrid = (unsigned)((n_slots + 255) / 256), rgrid = (unsigned)((max_n + 255) / 256);
+    if (kind == KIND_MD5) {
+        tl_leaf_arena<KIND_MD5><<<lgrid, 256, 0, s>>>(arena, starts, ends, n_dev, max_n, S, first, n_slots, leaves);
+        tl_root_arena<KIND_MD5><<<rgrid, 256, 0, s>>>(leaves, n_slots, first, n_dev, max_n, out);
+    } else {
+        tl_leaf_arena<KIND_SHA1><<<lgrid, 256, 0, s>>>(arena, starts, ends, n_dev, max_n, S, first, n_slots, leaves);
+        tl_root_arena<KIND_SHA1><<<rgrid, 256, 0, s>>>(leaves, n_slots, first, n_dev, max_n, out);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ similarity --
 // Digest keys and comparison: dig_hash / dig_equal (hg_device.hpp).
 

@@ -48,6 +48,11 @@ enum Slot {
 };
 
 constexpr size_t STAGE_PIECE = 64ull << 20;  // bytes per pinned staging buffer
+// Host-to-device pieces for window scans: small enough that the tiles of a
+// piece hash while the next piece is copied.  (Segment digests keep whole
+// staging buffers: each piece's launch lasts as long as a segment's chain,
+// so fewer, larger pieces are faster there.)
+constexpr size_t SCAN_PIECE = 16ull << 20;
 
 struct DevBuf {
     void *p = nullptr;
@@ -234,12 +239,11 @@ int ensure_stage(hg_ctx *ctx) {
 // the caller's unit (e.g. the segment size).
 template <class F>
 int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_t align,
-              hipStream_t st, F on_piece) {
+              hipStream_t st, F on_piece, uint64_t piece = STAGE_PIECE) {
     if (n == 0) return HG_OK;
     HG_TRY(ensure_copy_stream(ctx));
     const bool pinned = is_pinned_host(src);
     if (!pinned) HG_TRY(ensure_stage(ctx));
-    uint64_t piece = STAGE_PIECE;
     if (align > 1) piece = std::max<uint64_t>(align, piece - piece % align);
     // Pieces larger than a staging buffer cannot go through it: copy those
     // in one synchronous step.
@@ -319,7 +323,8 @@ int scan_tiles_from(hg_ctx *ctx, const void *in, uint64_t len, bool in_dev, uint
                                  t_done = t_end;
                              }
                              return HG_OK;
-                         }));
+                         },
+                         SCAN_PIECE));
     }
     *din_out = din;
     *plan_out = plan;
@@ -1103,6 +1108,10 @@ struct hg_batch {
     void *d_plan = nullptr, *d_ws = nullptr, *d_seg = nullptr;
     uint64_t *d_cand = nullptr, *d_slots = nullptr, *d_seg_start = nullptr, *d_seg_end = nullptr;
     uint32_t *d_cnt = nullptr;
+    // two-level chunk digests: prefix scratch and segment-digest slots
+    void *d_tl = nullptr;
+    uint8_t *d_tl_leaves = nullptr;
+    uint64_t tl_slots = 0;
     // schedule (set by hg_batch_tune)
     uint32_t grid = 8192;
     bool longest_first = true;
@@ -1173,7 +1182,11 @@ int batch_chunk(hg_batch *b, const uint8_t *arena, const hg_batch_out *out, hipS
                       b->d_seg_end, b->n, c.max_chunk, b->d_extra};
     HG_HIP(b->ctx, hg::launch_files_select(fc, c.window, c.min_chunk, out->status, st));
     HG_HIP(b->ctx, hg::launch_files_compact(fc, out->chunk_off, out->chunk_ends, b->max_chunks, out->status, st));
-    if (out->chunk_digests)
+    if (out->chunk_digests && c.chunk_segment)
+        HG_HIP(b->ctx, hg::launch_chunk_digests_two_level_arena(
+                           c.chunk_digest, arena, b->d_seg_start, b->d_seg_end, &out->status[1], b->max_chunks,
+                           c.chunk_segment, b->d_tl, b->d_tl_leaves, b->tl_slots, (uint8_t *)out->chunk_digests, st));
+    else if (out->chunk_digests)
         HG_HIP(b->ctx, hg::launch_segment_digests(c.chunk_digest, arena, 0, b->d_seg_start, b->d_seg_end,
                                                   &out->status[1], b->max_chunks, (uint8_t *)out->chunk_digests,
                                                   b->d_seg, st));
@@ -1228,8 +1241,6 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
         if (p.chunk.stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
         if (p.chunk.max_chunk != 0 && p.chunk.max_chunk < std::max<uint64_t>(p.chunk.min_chunk, 1))
             return fail(ctx, HG_EINVAL, "max_chunk must be 0 or at least max(min_chunk, 1)");
-        if (p.chunk.chunk_segment != 0)
-            return fail(ctx, HG_EINVAL, "two-level chunk digests (chunk_segment) are not available in file batches");
     }
     hg_batch *b = new hg_batch();
     b->ctx = ctx;
@@ -1315,6 +1326,22 @@ int hg_batch_create(hg_ctx *ctx, const uint64_t *file_off, const uint64_t *file_
             if ((st = batch_alloc(b, (size_t)std::max<uint32_t>(n_files, 1) * 4, &q)) != HG_OK) break;
             b->d_cnt = (uint32_t *)q;
             if ((st = batch_alloc(b, hg::segment_digest_scratch_bytes(b->max_chunks), &b->d_seg)) != HG_OK) break;
+            if (p.chunk.chunk_segment) {
+                // Segment digests: at most sum(len / S) + one partial segment
+                // per chunk.
+                uint64_t slots = b->max_chunks + 1;
+                for (uint32_t f = 0; f < n_files; f++) slots += b->len[f] / p.chunk.chunk_segment;
+                if (slots >= hg::MAX_LANES) {
+                    st = fail(ctx, HG_EINVAL, "%llu chunk segments (limit 2^31): use a larger chunk_segment",
+                              (unsigned long long)slots);
+                    break;
+                }
+                b->tl_slots = slots;
+                if ((st = batch_alloc(b, hg::two_level_arena_scratch_bytes(b->max_chunks), &b->d_tl)) != HG_OK)
+                    break;
+                if ((st = batch_alloc(b, slots * (uint64_t)b->d_chunk, &q)) != HG_OK) break;
+                b->d_tl_leaves = (uint8_t *)q;
+            }
         }
         hipError_t e;
         if ((e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking)) != hipSuccess ||
@@ -1564,7 +1591,8 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                                      t_done = t_end;
                                  }
                                  return HG_OK;
-                             }));
+                             },
+                             SCAN_PIECE));
         } else {
             HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
                       hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));

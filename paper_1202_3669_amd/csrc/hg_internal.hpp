@@ -134,6 +134,16 @@ hipError_t launch_chunk_digests_two_level(int kind, const uint8_t *in, uint64_t 
                                           const uint64_t *n_dev, uint64_t max_n, uint64_t S, uint8_t *leaves,
                                           uint8_t *out, hipStream_t s);
 
+// Two-level chunk digests of chunks [starts[j], ends[j]) of an arena
+// (*n_dev <= max_n of them, in any arena order): scratch of
+// two_level_arena_scratch_bytes(max_n), n_slots >= sum of ceil(len / S)
+// segment-digest slots in `leaves`.
+size_t two_level_arena_scratch_bytes(uint64_t max_n);
+hipError_t launch_chunk_digests_two_level_arena(int kind, const uint8_t *arena, const uint64_t *starts,
+                                                const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n,
+                                                uint64_t S, void *scratch, uint8_t *leaves, uint64_t n_slots,
+                                                uint8_t *out, hipStream_t s);
+
 // Streaming boundary decision over a carried buffer of len bytes whose
 // first chunk starts at last0: candidate starts cand[i] + add (ascending,
 // *n_dev of them).  Writes the cuts it can decide (relative to last0) to

@@ -241,7 +241,8 @@ class Context:
         self._check(st)
         return lv, rt
 
-    def block_hash_dual(self, data, block_size: int, leaves: bool = True, root: bool = True, stream=None):
+    def block_hash_dual(self, data, block_size: int, leaves: bool = True, root: bool = True, stream=None,
+                        flags_extra: int = 0):
         """(md5 leaves, md5 root, sha1 leaves, sha1 root) of a uint8 tensor in
         one pass (CUDA tensors; None where not asked for)."""
         torch = _torch()
@@ -251,7 +252,7 @@ class Context:
         ls = torch.empty((n, 20), dtype=torch.uint8, device=dev) if leaves else None
         rm = torch.empty(16, dtype=torch.uint8, device=dev) if root else None
         rs = torch.empty(20, dtype=torch.uint8, device=dev) if root else None
-        flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0)
+        flags = HG_OUT_DEVICE | (HG_IN_DEVICE if data.is_cuda else 0) | flags_extra
         ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None
         self._check(hg_block_hash_dual(self.handle, data.data_ptr() if data.numel() else None, data.numel(),
                                        block_size, ptr(lm), ptr(rm), ptr(ls), ptr(rs), flags,
@@ -539,7 +540,7 @@ class Batch:
                  block_digest: int = HG_SHA1, roots: bool = True, window: int = 20, stride: int = 1,
                  mask: int = 0xFFF, target: int = 0, min_chunk: int = 2048,
                  window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1,
-                 max_candidates: int = 0, max_chunk: int = 0):
+                 max_candidates: int = 0, max_chunk: int = 0, chunk_segment: int = 0):
         torch = _torch()
         import numpy as np
         self.ctx = ctx
@@ -548,7 +549,7 @@ class Batch:
         self.n = int(off.size)
         p = hg_batch_params(block_size, block_digest, 1 if roots else 0,
                             hg_chunk_params(window, stride, mask, target, min_chunk, max_chunk, window_digest,
-                                            chunk_digest), max_candidates)
+                                            chunk_digest, chunk_segment), max_candidates)
         h = _vp()
         ctx._check(hg_batch_create(ctx.handle, off.ctypes.data if self.n else None,
                                    ln.ctypes.data if self.n else None, self.n, ctypes.byref(p),

@@ -151,16 +151,36 @@ def test_batch_with_max_chunk(ctx, hg):
     b.close()
 
 
-def test_batch_rejects_two_level_chunk_digests(ctx, hg):
-    arena, off, ln = small_batch(907, 4)
-    note("batch rejects two-level chunk digests")
-    p = hg.hg_batch_params(64 * 1024, hg.HG_SHA1, 1,
-                           hg.hg_chunk_params(20, 1, 0xFFF, 0, 2048, 0, hg.HG_MD5, hg.HG_SHA1, 4096), 0)
-    h = ctypes.c_void_p()
-    o = np.ascontiguousarray(off, dtype=np.uint64)
-    n = np.ascontiguousarray(ln, dtype=np.uint64)
-    st = hg.hg_batch_create(ctx.handle, o.ctypes.data, n.ctypes.data, len(off), ctypes.byref(p), ctypes.byref(h))
-    assert st == hg.HG_EINVAL and not h.value
+@pytest.mark.parametrize("seg", [1000, 4096])
+def test_batch_two_level_chunk_digests(ctx, hg, seg):
+    arena, off, ln = small_batch(907, 40)
+    d = torch.from_numpy(arena).cuda()
+    note(f"batch with two-level chunk digests, segment {seg}")
+    b = hg.Batch(ctx, off, ln, chunk_segment=seg, max_chunk=3000 if seg == 1000 else 0)
+    mx = 3000 if seg == 1000 else 0
+    b.run(d)
+    fetch(b)
+    assert b._st[2] == 0
+    ref = b._cd.copy()
+    for j in range(len(off)):
+        data = arena[int(off[j]):int(off[j]) + int(ln[j])]
+        starts = oracle.window_scan(oracle.MD5, data, 20, 1, 0xFFF, 0)
+        ends = oracle.chunk_select(starts, 20, data.size, 2048, mx)
+        c0, c1 = int(b._co[j]), int(b._co[j + 1])
+        assert np.array_equal(b._ce[c0:c1].astype(np.uint64), ends), f"file {j} chunk ends"
+        assert np.array_equal(b._cd[c0:c1], oracle.chunk_digests(oracle.SHA1, data, ends, seg)), f"file {j}"
+    # captured into a graph: every replay rewrites the same digests
+    s = torch.cuda.Stream()
+    b.capture(d, s)
+    for r in range(3):
+        b.chunk_digests.zero_()
+        torch.cuda.synchronize()
+        b.replay(s)
+        s.synchronize()
+        fetch(b)
+        n = int(b._co[-1])
+        assert np.array_equal(b._cd[:n], ref[:n]), f"replay {r}"
+    b.close()
 
 
 def test_batch_reports_candidate_overflow(ctx, hg):

@@ -83,14 +83,17 @@ def test_streaming(ctx, hg, case, device_input):
     assert np.array_equal(np.concatenate(out_d).reshape(-1, 20), dig)
 
 
-def test_file_batch(ctx, hg, case):
+@pytest.mark.parametrize("seg", [0, 4096])
+def test_file_batch(ctx, hg, case, seg):
     data, ends, dig = case
+    if seg:
+        dig = oracle.chunk_digests(oracle.SHA1, data, ends, seg)
     # three files: the whole input, its first 5 MiB + 3 bytes, its last 9 MiB
     off = np.array([0, data.size, data.size + 5 * MiB + 3], dtype=np.uint64)
     ln = np.array([data.size, 5 * MiB + 3, 9 * MiB], dtype=np.uint64)
     arena = np.concatenate([data, data[:5 * MiB + 3], data[-9 * MiB:]])
-    note("system parameters, file batch of 3")
-    b = hg.Batch(ctx, off, ln, mask=MASK, min_chunk=MIN, max_chunk=MAX)
+    note(f"system parameters, file batch of 3, chunk segment {seg}")
+    b = hg.Batch(ctx, off, ln, mask=MASK, min_chunk=MIN, max_chunk=MAX, chunk_segment=seg)
     d = torch.from_numpy(arena).cuda()
     b.run(d)
     torch.cuda.synchronize()
@@ -106,7 +109,7 @@ def test_file_batch(ctx, hg, case):
         else:
             s_ = oracle.window_scan_sharded(oracle.MD5, f, W, S, MASK, TARGET, THREADS)
             exp_e = oracle.chunk_select(s_, W, f.size, MIN, MAX)
-            exp_d = oracle.chunk_digests(oracle.SHA1, f, exp_e)
+            exp_d = oracle.chunk_digests(oracle.SHA1, f, exp_e, seg)
         assert np.array_equal(ce[co[j]:co[j + 1]], exp_e), f"file {j} ends"
         assert np.array_equal(cd[co[j]:co[j + 1]], exp_d), f"file {j} digests"
     b.close()
