@@ -457,7 +457,11 @@ def breakdown(torch, hg, data, host_pinned):
         dt = time.perf_counter() - t0
         res[f"chunk_stream_64MiB_{where}"] = {"GBps": round(n / dt / 1e9, 1), "ms": round(dt * 1e3, 2)}
     ch.close()
-    # Host-to-device included: pinned host input streamed through the library.
+    # Host-to-device included: pinned host input streamed through the library
+    # (content-based chunking: window tiles hash while later pieces copy).
+    ts = timed(lambda: ctx.chunk(host_pinned, 20, 1, 0xFFF, 0, 2 * KiB), reps=3)
+    res["chunk_s1_with_h2d"] = {"GBps": round(n / statistics.median(ts) / 1e6, 1),
+                                "ms_p50": round(pct(ts, 50), 2)}
     for k in (0, 1):
         ts = timed(lambda: ctx.block_hash(host_pinned, 64 * KiB, k, root=False), reps=5)
         res[f"{'sha1' if k else 'md5'}_64k_with_h2d"] = {

@@ -497,7 +497,8 @@ typedef struct {
     uint64_t groups;                       /* groups run */
     uint64_t queued;                       /* waiting now */
     uint32_t in_flight, max_in_flight;     /* requests admitted and not completed */
-    double p50_ms, p99_ms, mean_ms, max_ms; /* latency submit -> completion, completed requests */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency submit -> completion over the last 2^20
+                                             * completed requests (since the last reset) */
 } hg_server_stats;
 
 /* Starts the workers on `device`; allocates every group and the staging

@@ -110,6 +110,7 @@ class Ranges {
 };
 
 constexpr uint64_t STAGE_ALIGN = 256;
+constexpr size_t LAT_WINDOW = 1u << 20;  // completions the latency statistics cover
 
 int dbytes(int d) { return d == HG_MD5 ? 16 : (d == HG_SHA1 ? 20 : -1); }
 uint64_t up256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -208,7 +209,10 @@ struct hg_server {
     // statistics
     uint64_t submitted = 0, completed = 0, failed = 0, bytes = 0, n_groups = 0;
     uint32_t in_flight = 0, max_in_flight = 0;
+    // Latencies of the last LAT_WINDOW completions (a ring), so that a
+    // long-running server's statistics use bounded memory.
     std::vector<double> lat_ms;
+    uint64_t lat_next = 0;
 };
 
 namespace {
@@ -617,7 +621,9 @@ Completion finish_locked(hg_server *s, Req *q, Clock::time_point now, bool admit
     if (q->status != HG_OK && q->status != HG_ETRUNC) s->failed++;
     s->bytes += q->r.len;
     const double ms = std::chrono::duration<double, std::milli>(now - q->t_arrival).count();
-    s->lat_ms.push_back(ms);
+    if (s->lat_ms.size() < LAT_WINDOW) s->lat_ms.push_back(ms);
+    else s->lat_ms[s->lat_next % LAT_WINDOW] = ms;
+    s->lat_next++;
     if (q->lat_out) *q->lat_out = ms;
     if (q->st_out) *q->st_out = q->status;
     Completion c{q->cb, q->user, q->id, q->status, q->remaining, q->waitable ? nullptr : q};
@@ -846,6 +852,7 @@ int hg_server_stats_reset(hg_server *s) {
     s->submitted = s->completed = s->failed = s->bytes = s->n_groups = 0;
     s->max_in_flight = s->in_flight;
     s->lat_ms.clear();
+    s->lat_next = 0;
     return HG_OK;
 }
 
