@@ -34,6 +34,7 @@ hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
 """
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -335,8 +336,10 @@ def recorded_traffic():
 
 
 def pct(xs, p):
+    """Nearest-rank percentile (as the server's statistics)."""
     xs = sorted(xs)
-    return xs[min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))]
+    rank = math.ceil(p / 100.0 * len(xs))
+    return xs[min(max(rank, 1), len(xs)) - 1]
 
 
 def cpu_baseline(data_np, prev_np, mib):
