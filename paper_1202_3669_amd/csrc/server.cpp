@@ -111,6 +111,10 @@ class Ranges {
 
 constexpr uint64_t STAGE_ALIGN = 256;
 constexpr size_t LAT_WINDOW = 1u << 20;  // completions the latency statistics cover
+// Two-level chunk digests are grouped for segments of at least this many
+// bytes (a group's segment-digest slots are sized for it); smaller segments
+// run alone.
+constexpr uint64_t TL_MIN_SEGMENT = 4096;
 
 int dbytes(int d) { return d == HG_MD5 ? 16 : (d == HG_SHA1 ? 20 : -1); }
 uint64_t up256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -169,6 +173,9 @@ struct Group {
     uint64_t *d_cand = nullptr, *d_slots = nullptr, *d_seg_start = nullptr, *d_seg_end = nullptr;
     uint64_t *d_ends = nullptr, *d_chunk_off = nullptr, *d_status = nullptr;
     uint32_t *d_cnt = nullptr;
+    void *d_tl = nullptr;              // two-level digests: prefix scratch
+    uint8_t *d_tl_leaves = nullptr;    // and segment-digest slots
+    uint64_t tl_cap = 0;
     // pinned host (one allocation, carved)
     uint8_t *h = nullptr;
     hg_block_job *h_jobs = nullptr;
@@ -307,6 +314,9 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
     GA(d_cdig, uint8_t *, g.max_chunks * 20);
     GA(d_cnt, uint32_t *, (size_t)g.R * 4);
     GA(d_seg, void *, hg::segment_digest_scratch_bytes(g.max_chunks));
+    g.tl_cap = M / TL_MIN_SEGMENT + g.max_chunks + 1;
+    GA(d_tl, void *, hg::two_level_arena_scratch_bytes(g.max_chunks));
+    GA(d_tl_leaves, uint8_t *, g.tl_cap * 20);
     GA(d_chunk_off, uint64_t *, (size_t)(g.R + 1) * 8);
     GA(d_status, uint64_t *, 64);
 #undef GA
@@ -359,8 +369,10 @@ bool fits(const Group &g, const hg_server_cfg &cfg, const Req *q) {
     const Need n = need_of(r);
     if (r.kind == HG_REQ_BLOCK) return g.leaf_used + n.leaf_bytes <= g.leaf_cap;
     // A maximum chunk size needs per-file room for forced cuts, and two-level
-    // chunk digests a per-file segment layout: such requests are served alone.
-    if (r.chunk.max_chunk != 0 || r.chunk.chunk_segment != 0) return false;
+    // chunk digests with short segments more slots than a group holds: such
+    // requests are served alone.
+    if (r.chunk.max_chunk != 0 || (r.chunk.chunk_segment != 0 && r.chunk.chunk_segment < TL_MIN_SEGMENT))
+        return false;
     if (!g.chunks.empty() && !same_chunk_params(g.cp, r.chunk)) return false;
     return g.tiles + n.tiles <= g.tile_cap && g.cand + n.cand <= g.cand_cap;
 }
@@ -505,9 +517,17 @@ int enqueue_chunks(Group &g, const uint8_t *arena, bool want_dig) {
                       0, nullptr};
     SV_HIP(hg::launch_files_select(fc, c.window, c.min_chunk, g.d_status, st));
     SV_HIP(hg::launch_files_compact(fc, g.d_chunk_off, g.d_ends, g.max_chunks, g.d_status, st));
-    if (want_dig)
+    if (want_dig && c.chunk_segment) {
+        // Segment digests of the group's chunks: at most bytes / S plus one
+        // partial segment per chunk.
+        const uint64_t slots = std::min(g.tl_cap, g.bytes / c.chunk_segment + g.max_chunks + 1);
+        SV_HIP(hg::launch_chunk_digests_two_level_arena(c.chunk_digest, arena, g.d_seg_start, g.d_seg_end,
+                                                        &g.d_status[1], g.max_chunks, c.chunk_segment, g.d_tl,
+                                                        g.d_tl_leaves, slots, g.d_cdig, st));
+    } else if (want_dig) {
         SV_HIP(hg::launch_segment_digests(c.chunk_digest, arena, 0, g.d_seg_start, g.d_seg_end, &g.d_status[1],
                                           g.max_chunks, g.d_cdig, g.d_seg, st));
+    }
     SV_HIP(hipMemcpyAsync(g.h_chunk_off, g.d_chunk_off, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, st));
     SV_HIP(hipMemcpyAsync(g.h_status, g.d_status, 32, hipMemcpyDeviceToHost, st));
     return HG_OK;

@@ -1,10 +1,9 @@
-// Thread-sanitizer stress of the serving loop's host code (admission, group
-// formation, completion, waiters, callbacks, statistics): four submitter
-// threads, callbacks and waiters mixed, injected failures, a statistics
-// reader running concurrently, then a stop with requests still queued.
-// Every served result must equal the single call on its own context.  Built
-// with the host code instrumented (-fsanitize=thread on the host side only)
-// by tests/test_gpu_tsan.py; exit status 0 on success.
+// Stress of the serving loop through the C ABI (admission, group formation,
+// completion, waiters, callbacks, statistics): four submitter threads,
+// callbacks and waiters mixed, injected failures, a statistics reader
+// running concurrently, then a stop with requests still queued.  Every
+// served result must equal the single call on its own context.  Built and
+// run by tests/test_gpu_server_stress.py; exit status 0 on success.
 #include "hashgpu.h"
 
 #include <atomic>

@@ -201,6 +201,27 @@ def test_chunk_requests_with_two_level_digests(ctx, hg, pool):
             assert np.array_equal(got[2], oracle.chunk_digests(oracle.SHA1, data, ends, 1024))
 
 
+def test_grouped_chunk_requests_with_two_level_digests(ctx, hg, pool):
+    host, dev = pool
+    specs = [(2, 1000 * i + 3, 300 * KiB + 777 * i) for i in range(12)] + [(0, 5, 300 * KiB)]
+    rs = hg.RequestSet(dev.data_ptr(), True, specs, chunk_segment=4096)
+    note("grouped chunk requests with two-level chunk digests (4 KiB segments)")
+    with hg.Server(0, slots=1, max_requests=16, device_budget=8 * MiB, max_group_bytes=8 * MiB) as srv:
+        _, sts = srv.play(rs, np.zeros(len(specs)))
+        st = srv.stats()
+    assert np.all(sts == hg.HG_OK)
+    assert st["groups"] < 12  # served together, not one by one
+    for i, (k, o, n) in enumerate(specs):
+        if k != 2:
+            continue
+        got = rs.result(i)
+        data = host[o:o + n]
+        starts = oracle.window_scan(oracle.MD5, data, 20, 1, 0xFFF, 0)
+        ends = oracle.chunk_select(starts, 20, n, 2048)
+        assert np.array_equal(got[1], ends)
+        assert np.array_equal(got[2], oracle.chunk_digests(oracle.SHA1, data, ends, 4096))
+
+
 def test_truncation_and_injected_failure(ctx, hg, pool):
     host, dev = pool
     specs = [(2, 0, 1 * MiB), (0, 5, 300 * KiB), (2, 50, 2 * MiB), (1, 9, 1 * MiB)]
