@@ -380,7 +380,34 @@ def cpu_baseline(data_np, prev_np, mib):
                       f"{threads} threads",
             "single_thread_value": round(7 * n1 / dt1 / 1e9, 4),
             "single_thread_sample": f"first {n1 // MiB} MiB, {dt1:.2f} s",
-            "cpu_model": model, "host_cpus": os.cpu_count()}
+            "cpu_model": model, "host_cpus": os.cpu_count(),
+            "context_hashlib": hashlib_context(data_np[:n], threads)}
+
+
+def hashlib_context(sample, threads):
+    """Context only, not the oracle: Python's hashlib (OpenSSL, vectorised
+    code) over the sample's 64 KiB segments, MD5 and SHA-1, on the same
+    threads (hashlib releases the GIL for large buffers)."""
+    import hashlib
+    from concurrent.futures import ThreadPoolExecutor
+    mv = memoryview(sample)
+    seg = 64 * KiB
+    out = {}
+    for name in ("md5", "sha1"):
+        fn = getattr(hashlib, name)
+
+        def run(lo, hi):
+            for a in range(lo, hi, seg):
+                fn(mv[a:min(a + seg, hi)]).digest()
+        parts = [(a, min(a + len(sample) // threads + seg, len(sample))) for a in
+                 range(0, len(sample), len(sample) // threads + seg)]
+        parts = [(a - a % seg, b - b % seg if b < len(sample) else b) for a, b in parts]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as pool:
+            list(pool.map(lambda ab: run(*ab), parts))
+        out[f"{name}_64k_GBps"] = round(len(sample) / (time.perf_counter() - t0) / 1e9, 2)
+    out["threads"] = threads
+    return out
 
 
 def breakdown(torch, hg, data, host_pinned):
