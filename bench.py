@@ -91,6 +91,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-sweep", action="store_true", help="skip the similarity workload and block-size sweep")
+    ap.add_argument("--no-dedup", action="store_true", help="skip the block-map write path over versions")
     ap.add_argument("--leaf-probe", action="store_true",
                     help="only hash the 1 GiB input with one lane per segment (MD5/SHA-1, 4 KiB and "
                          "64 KiB segments, 3 launches each, no second level), for counter runs")
@@ -621,6 +622,49 @@ def similarity_sweep(torch, hg, inputs):
     return res
 
 
+def dedup_write_path(torch, hg, inputs, n_versions=8):
+    """The block-map write path (Sec. 3.2.1) over a series of versions of a
+    256 MiB file (seed 7; each next version 256 seeded 1-4 KiB edits of the
+    previous one, seeds 8...): per version, content-based chunking (MD5 w=20,
+    low 12 bits, min 2 KiB, SHA-1 digests) and the block-map write that marks
+    the chunks already stored.  Beside it the CA-Infinite bound of Sec. 4.4:
+    the same writes with hashing taking no time (block-map time only)."""
+    ctx = hg.Context(0)
+    bm = hg.BlockMap(ctx, hg.HG_SHA1, capacity=1 << 24)
+    v = inputs.uniform_bytes(7, 256 * MiB)
+    total = stored = 0
+    t_hash = t_map = 0.0
+    per = []
+    for k in range(n_versions):
+        d = torch.from_numpy(v).cuda()
+        ctx.chunk(d, 20, 1, 0xFFF, 0, 2 * KiB)  # warm the context's buffers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ends, dig = ctx.chunk(d, 20, 1, 0xFFF, 0, 2 * KiB)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, dup_chunks, dup_bytes = bm.write(dig, ends=ends)
+        t2 = time.perf_counter()
+        total += v.size
+        stored += v.size - dup_bytes
+        t_hash += t1 - t0
+        t_map += t2 - t1
+        per.append({"version": k, "chunks": int(ends.numel()), "duplicate_chunks": dup_chunks,
+                    "stored_fraction": round(1 - dup_bytes / v.size, 4),
+                    "hash_ms": round(1e3 * (t1 - t0), 3), "blockmap_ms": round(1e3 * (t2 - t1), 3)})
+        del d
+        if k + 1 < n_versions:
+            v, _ = inputs.edited_version(v, 8 + k, 256)
+    res = {"versions": n_versions, "bytes": total, "stored_bytes": stored,
+           "write_path_GBps": round(total / (t_hash + t_map) / 1e9, 1),
+           "ca_infinite_GBps": round(total / t_map / 1e9, 1),
+           "fraction_of_ca_infinite": round(t_map / (t_hash + t_map), 3),
+           "blockmap_entries": bm.size(), "per_version": per}
+    bm.close()
+    ctx.close()
+    return res
+
+
 def serving(torch, hg, inputs, data, host_pinned, n_req):
     """The serving loop under the request stream (seed 6): log-normal sizes
     4 KiB-256 MiB (median 1 MiB, sigma 1.85), mix 50% block SHA-1 / 30% block
@@ -873,6 +917,9 @@ def main():
     if not args.no_sweep:
         print("[bench] similarity workload and block-size sweep", file=sys.stderr, flush=True)
         line["similarity_sweep"] = similarity_sweep(torch, hg, inputs)
+    if not args.no_dedup:
+        print("[bench] block-map write path over 8 versions", file=sys.stderr, flush=True)
+        line["dedup_write_path"] = dedup_write_path(torch, hg, inputs)
     if not args.no_serving:
         print(f"[bench] serving loop ({args.serve_requests} requests per point)", file=sys.stderr, flush=True)
         line["serving"] = serving(torch, hg, inputs, data, host_pinned, args.serve_requests)
