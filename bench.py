@@ -473,20 +473,29 @@ def breakdown(torch, hg, data, host_pinned):
         res[f"chunk_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1)}
     # Streaming chunker: the 1 GiB fed in 64 MiB pieces (device-resident,
     # and from pinned host memory: host-to-device copy included).
+    # Synchronous feeds return host arrays; asynchronous ones (HG_ASYNC)
+    # leave device outputs and the digests running into the next feed.
     ch = hg.Chunker(ctx)
-    for where, src in (("device", data), ("pinned_host", host_pinned)):
-        def stream_all():
-            ch.reset()
-            for a in range(0, n, 64 * MiB):
-                ch.feed(src[a:a + 64 * MiB] if where == "device" else src[a:a + 64 * MiB].numpy())
-            ch.finish()
-        stream_all()  # warm-up: scratch sized once
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        stream_all()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        res[f"chunk_stream_64MiB_{where}"] = {"GBps": round(n / dt / 1e9, 1), "ms": round(dt * 1e3, 2)}
+    for mode in ("", "_async"):
+        for where, src in (("device", data), ("pinned_host", host_pinned)):
+            def stream_all():
+                ch.reset()
+                outs = []
+                for a in range(0, n, 64 * MiB):
+                    piece = src[a:a + 64 * MiB] if where == "device" else src[a:a + 64 * MiB].numpy()
+                    outs.append(ch.feed(piece, asynchronous=bool(mode)))
+                outs.append(ch.finish(asynchronous=bool(mode)))
+                return outs
+            stream_all()  # warm-up: scratch sized once
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs = stream_all()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            chunks = sum(int(o[2].item()) if mode else o[0].size for o in outs)
+            res[f"chunk_stream_64MiB_{where}{mode}"] = {"GBps": round(n / dt / 1e9, 1), "ms": round(dt * 1e3, 2),
+                                                         "chunks": chunks}
+            del outs
     ch.close()
     # Host-to-device included: pinned host input streamed through the library
     # (content-based chunking: window tiles hash while later pieces copy).

@@ -72,7 +72,7 @@ enum {
 };
 
 /* Flags.  HG_LEN_ENDS applies to hg_similarity and hg_blockmap_write only; HG_BACKGROUND to the
- * batch calls only; HG_COUNT_HOST to hg_chunk only. */
+ * batch calls only; HG_COUNT_HOST to hg_chunk and the chunker's feed and finish only. */
 enum {
     HG_IN_DEVICE = 1u,
     HG_OUT_DEVICE = 2u,
@@ -357,7 +357,14 @@ int hg_chunker_bound(const hg_chunker *c, uint64_t len, uint64_t *bound);
  * previous one -- of this or an earlier call -- ended, the first at 0), and
  * their digests (NULL: not wanted).  Outputs are device pointers with
  * HG_OUT_DEVICE (then n_chunks too, unless HG_COUNT_HOST), host pointers
- * otherwise.  Synchronous.  HG_EINVAL when capacity < hg_chunker_bound. */
+ * otherwise.  Synchronous, unless HG_ASYNC (with HG_OUT_DEVICE; the input
+ * may be host memory): then the call returns once the input has been read
+ * and the cuts decided, and ends[], the digests and a device *n_chunks are
+ * written in stream order on `stream`, valid after it synchronizes.  The
+ * input may be reused when the call returns; the outputs may not be read
+ * or reused before the stream synchronizes.  The digests left running are
+ * then overlapped with the next feed's host-to-device copy.  HG_EINVAL when
+ * capacity < hg_chunker_bound, or HG_ASYNC without HG_OUT_DEVICE. */
 int hg_chunker_feed(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends,
                     uint64_t capacity, uint64_t *n_chunks, void *chunk_digests, void *stream);
 

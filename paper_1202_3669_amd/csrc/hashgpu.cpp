@@ -239,7 +239,7 @@ int ensure_stage(hg_ctx *ctx) {
 // the caller's unit (e.g. the segment size).
 template <class F>
 int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_t align,
-              hipStream_t st, F on_piece, uint64_t piece = STAGE_PIECE) {
+              hipStream_t st, F on_piece, uint64_t piece = STAGE_PIECE, bool after_stream = true) {
     if (n == 0) return HG_OK;
     HG_TRY(ensure_copy_stream(ctx));
     const bool pinned = is_pinned_host(src);
@@ -251,9 +251,12 @@ int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_
         HG_HIP(ctx, hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st));
         return on_piece(0, n);
     }
-    // The copy stream must not overwrite memory still read by earlier work.
-    HG_HIP(ctx, hipEventRecord(ctx->piece_ready, st));
-    HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->piece_ready, 0));
+    // The copy stream must not overwrite memory still read by earlier work
+    // (unless the caller knows that no pending work on st touches dst).
+    if (after_stream) {
+        HG_HIP(ctx, hipEventRecord(ctx->piece_ready, st));
+        HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->piece_ready, 0));
+    }
     int k = 0;
     for (uint64_t off = 0; off < n; off += piece, k ^= 1) {
         const uint64_t len = std::min(piece, n - off);
@@ -1536,8 +1539,10 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     hg_ctx *ctx = c->ctx;
     HG_TRY(enter(ctx));
     const bool count_host = flags & HG_COUNT_HOST;
-    flags &= ~(uint32_t)HG_COUNT_HOST;
+    const bool async = flags & HG_ASYNC;
+    flags &= ~(uint32_t)(HG_COUNT_HOST | HG_ASYNC);
     HG_TRY(check_flags(ctx, flags, false));
+    if (async && !(flags & HG_OUT_DEVICE)) return fail(ctx, HG_EINVAL, "HG_ASYNC requires HG_OUT_DEVICE");
     if (c->finished) return fail(ctx, HG_EINVAL, "the stream is finished (hg_chunker_reset starts a new one)");
     if (len && !data) return fail(ctx, HG_EINVAL, "data is NULL");
     if (!n_out) return fail(ctx, HG_EINVAL, "n_chunks is NULL");
@@ -1572,7 +1577,11 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
         if (host_in) {
             // Host bytes arrive in pieces; the tiles whose windows have
-            // landed run while later pieces are copied.
+            // landed run while later pieces are copied.  The copies land in
+            // this feed's buffer past the carry, which no pending work on
+            // st reads (the previous feed's digests, left running by
+            // HG_ASYNC, read the other buffer; everything before them ended
+            // at that feed's cut decision), so they need not wait for st.
             uint64_t t_done = 0;
             HG_TRY(stream_in(ctx, W + carry, (const uint8_t *)data, len, 1, st,
                              [&](uint64_t off, uint64_t plen) -> int {
@@ -1592,7 +1601,7 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                                  }
                                  return HG_OK;
                              },
-                             SCAN_PIECE));
+                             SCAN_PIECE, false));
         } else {
             HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
                       hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));
@@ -1662,7 +1671,7 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     }
     if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &small[2], 8, hipMemcpyDeviceToDevice, st));
     else *n_out = k;
-    HG_HIP(ctx, hipStreamSynchronize(st));
+    if (!async) HG_HIP(ctx, hipStreamSynchronize(st));
     if (!out_dev)
         for (uint64_t i = 0; i < k; i++) ends[i] += abs_add;
     // New carry: from w - 1 bytes before the last cut (windows straddling it).

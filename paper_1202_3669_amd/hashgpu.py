@@ -759,7 +759,10 @@ class Chunker:
 
     feed(piece) takes a uint8 CUDA tensor or numpy array and returns
     (ends, digests) numpy arrays of the chunks decided so far (absolute
-    stream offsets); finish() returns the rest.
+    stream offsets); finish() returns the rest.  With asynchronous=True
+    both return (ends, digests, count) CUDA tensors instead, written in
+    stream order (valid after the stream synchronizes; the first count[0]
+    rows hold the chunks), and the call returns once the cuts are decided.
     """
 
     def __init__(self, ctx: Context, window: int = 20, stride: int = 1, mask: int = 0xFFF, target: int = 0,
@@ -790,11 +793,13 @@ class Chunker:
         b = _u64(0)
         self.ctx._check(hg_chunker_bound(self.handle, n, ctypes.byref(b)))
         cap = int(b.value)
+        is_dev = hasattr(data, "is_cuda") and data.is_cuda
+        if fn == "feed" and n and not is_dev and not (data.flags["C_CONTIGUOUS"] and data.dtype == np.uint8):
+            raise ValueError("host input must be a contiguous uint8 array")
         ends = np.zeros(cap, dtype=np.uint64)
         dig = np.zeros((cap, self.d), dtype=np.uint8)
         cnt = _u64(0)
         if fn == "feed":
-            is_dev = hasattr(data, "is_cuda") and data.is_cuda
             ptr = (data.data_ptr() if is_dev else data.ctypes.data) if n else None
             st = hg_chunker_feed(self.handle, ptr, n, HG_IN_DEVICE if is_dev else 0, ends.ctypes.data, cap,
                                  ctypes.byref(cnt), dig.ctypes.data, _stream_handle(stream))
@@ -805,11 +810,35 @@ class Chunker:
         k = int(cnt.value)
         return ends[:k].copy(), dig[:k].copy()
 
-    def feed(self, data, stream=None):
-        return self._call("feed", data, stream)
+    def _call_async(self, fn, data, stream):
+        import torch
+        n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
+        b = _u64(0)
+        self.ctx._check(hg_chunker_bound(self.handle, n, ctypes.byref(b)))
+        cap = int(b.value)
+        dev = torch.device("cuda", self.ctx.device)
+        ends = torch.empty(cap, dtype=torch.int64, device=dev)
+        dig = torch.empty((cap, self.d), dtype=torch.uint8, device=dev)
+        cnt = torch.empty(1, dtype=torch.int64, device=dev)
+        flags = HG_OUT_DEVICE | HG_ASYNC
+        if fn == "feed":
+            is_dev = hasattr(data, "is_cuda") and data.is_cuda
+            if n and not is_dev and not (data.flags["C_CONTIGUOUS"] and data.dtype.itemsize == 1):
+                raise ValueError("host input must be a contiguous uint8 array")
+            ptr = (data.data_ptr() if is_dev else data.ctypes.data) if n else None
+            st = hg_chunker_feed(self.handle, ptr, n, flags | (HG_IN_DEVICE if is_dev else 0), ends.data_ptr(), cap,
+                                 cnt.data_ptr(), dig.data_ptr(), _stream_handle(stream))
+        else:
+            st = hg_chunker_finish(self.handle, flags, ends.data_ptr(), cap, cnt.data_ptr(), dig.data_ptr(),
+                                   _stream_handle(stream))
+        self.ctx._check(st)
+        return ends, dig, cnt
 
-    def finish(self, stream=None):
-        return self._call("finish", None, stream)
+    def feed(self, data, stream=None, asynchronous=False):
+        return self._call_async("feed", data, stream) if asynchronous else self._call("feed", data, stream)
+
+    def finish(self, stream=None, asynchronous=False):
+        return self._call_async("finish", None, stream) if asynchronous else self._call("finish", None, stream)
 
     def reset(self):
         self.ctx._check(hg_chunker_reset(self.handle))

@@ -160,3 +160,66 @@ def test_stream_rejects_small_capacity_and_use_after_finish(ctx, hg):
     with pytest.raises(hg.HashGpuError):
         ch.feed(data)
     ch.close()
+
+
+ASYNC_CASES = [  # (length, w, s, mask, target, min, max, segment)
+    (3 * MiB + 11, 20, 1, 0xFFF, 0, 2048, 0, 0),
+    (1 * MiB + 5, 20, 1, 0xFF, 0, 0, 0, 0),
+    (2 * MiB + 1, 20, 1, 0xFFF, 0, 2048, 8192, 0),
+    (2 * MiB + 3, 20, 1, 0xFFF, 0, 2048, 0, 4096),
+]
+
+
+@pytest.mark.parametrize("case", ASYNC_CASES)
+@pytest.mark.parametrize("where", ["device", "pinned", "pageable"])
+def test_stream_async_feeds(ctx, hg, case, where):
+    # HG_ASYNC: every feed returns once its cuts are decided, its digests
+    # still running; host input comes through ONE staging array that is
+    # overwritten with the next piece as soon as a feed returns.
+    length, w, s, mask, target, mn, mx, seg = case
+    data = inputs.uniform_bytes(530 + length % 71, length)
+    exp_ends, exp_dig = one_shot(data, w, s, mask, target, mn, mx, seg)
+    rng = np.random.default_rng(531 + length % 17)
+    cuts = exp_ends[:: max(1, exp_ends.size // 5)].tolist()
+    splits = pieces(rng, length, cuts + [c + 1 for c in cuts])
+    note(f"async stream case={case} input={where} pieces={len(splits)}")
+    big = max(b - a for a, b in splits)
+    if where == "pinned":
+        stage = torch.empty(max(big, 1), dtype=torch.uint8, pin_memory=True).numpy()
+    else:
+        stage = np.empty(max(big, 1), dtype=np.uint8)
+    dev = torch.from_numpy(data).cuda() if where == "device" else None
+    ch = hg.Chunker(ctx, w, s, mask, target, mn, mx, chunk_segment=seg)
+    outs = []
+    for a, b in splits:
+        if where == "device":
+            piece = dev[a:b]
+        else:
+            stage[:b - a] = data[a:b]
+            piece = stage[:b - a]
+        outs.append(ch.feed(piece, asynchronous=True))
+        if where != "device":
+            stage[:] = 0xA5  # the call has read its input
+    outs.append(ch.finish(asynchronous=True))
+    torch.cuda.synchronize()
+    got_e = [e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in outs]
+    got_d = [d[:int(c.item())].cpu().numpy() for _, d, c in outs]
+    ch.close()
+    assert np.array_equal(np.concatenate(got_e), exp_ends)
+    assert np.array_equal(np.concatenate(got_d).reshape(-1, 20), exp_dig)
+
+
+def test_stream_async_needs_device_outputs(ctx, hg):
+    import ctypes
+    ch = hg.Chunker(ctx)
+    data = inputs.uniform_bytes(540, 10_000)
+    ends = np.zeros(64, dtype=np.uint64)
+    n = ctypes.c_uint64(0)
+    note("async feed with host outputs")
+    assert hg.hg_chunker_feed(ch.handle, data.ctypes.data, data.size, hg.HG_ASYNC, ends.ctypes.data, 64,
+                              ctypes.byref(n), None, None) == hg.HG_EINVAL
+    e, d = ch.feed(data)  # the rejected call left the stream untouched
+    e2, d2 = ch.finish()
+    exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, 0)
+    assert np.array_equal(np.concatenate([e, e2]), exp_ends)
+    ch.close()
