@@ -12,6 +12,8 @@ other implementation to fall back to.
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 import os
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhashgpu.so")
@@ -186,6 +188,23 @@ def _stream_handle(stream=None):
     return s.cuda_stream
 
 
+def _on_stream(fn):
+    """Runs a method with its `stream` argument (a torch stream, if given)
+    as torch's current stream, so that the output tensors it allocates, and
+    the fills that zero them, are ordered on the stream the library writes
+    them on (and their memory is only reused after that stream's work)."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def run(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        with _torch().cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return run
+
+
 class Context:
     """One hg_ctx on one device, used from one stream at a time."""
 
@@ -222,6 +241,7 @@ class Context:
         raise HashGpuError(st, buf.value.decode(errors="replace"))
 
     # ------------------------------------------------------------ direct --
+    @_on_stream
     def block_hash(self, data, block_size: int, digest: int, leaves: bool = True,
                    root: bool = True, stream=None, flags_extra: int = 0):
         """Segment digests (n, d) uint8 and/or root (d,) uint8 of a uint8
@@ -241,6 +261,7 @@ class Context:
         self._check(st)
         return lv, rt
 
+    @_on_stream
     def block_hash_dual(self, data, block_size: int, leaves: bool = True, root: bool = True, stream=None,
                         flags_extra: int = 0):
         """(md5 leaves, md5 root, sha1 leaves, sha1 root) of a uint8 tensor in
@@ -265,6 +286,7 @@ class Context:
         self._check(hg_probe_alu(self.handle, ctypes.byref(v), _stream_handle(stream)))
         return v.value
 
+    @_on_stream
     def probe_read(self, data, stream=None) -> float:
         """Measured HBM read rate (GB/s) over a CUDA tensor."""
         v = ctypes.c_double(0.0)
@@ -273,6 +295,7 @@ class Context:
         return v.value
 
     # ----------------------------------------------------- sliding window --
+    @_on_stream
     def window_scan(self, data, window: int, stride: int, mask: int, target: int,
                     digest: int = HG_MD5, capacity: int | None = None, stream=None, out=None):
         """Ascending candidate start offsets (int64 CUDA tensor).  With
@@ -306,6 +329,7 @@ class Context:
             capacity = total
         raise HashGpuError(HG_ETRUNC, "candidate count changed between calls")
 
+    @_on_stream
     def chunk(self, data, window: int, stride: int, mask: int, target: int, min_chunk: int,
               window_digest: int = HG_MD5, chunk_digest: int = HG_SHA1, digests: bool = True,
               capacity: int | None = None, stream=None, out=None, asynchronous: bool = False,
@@ -358,6 +382,7 @@ class Context:
         raise HashGpuError(HG_ETRUNC, "chunk count changed between calls")
 
     # ------------------------------------------------- chunking stages --
+    @_on_stream
     def chunk_select(self, starts, n_starts, length: int, window: int, min_chunk: int, max_chunk: int = 0,
                      out=None, asynchronous: bool = False, stream=None):
         """hg_chunk_select on CUDA tensors: starts (int64, room for
@@ -378,6 +403,7 @@ class Context:
             return ends, n
         return ends[:int(n.item())], n
 
+    @_on_stream
     def chunk_digests(self, data, ends, n_chunks, digest: int = HG_SHA1, chunk_segment: int = 0, out=None,
                       asynchronous: bool = False, stream=None):
         """hg_chunk_digests on CUDA tensors: ends (int64, room for len(ends)
@@ -395,6 +421,7 @@ class Context:
                                      _stream_handle(stream)))
         return out
 
+    @_on_stream
     def similarity_n(self, dig_a, dig_b, n_b, ends_b=None, len_b=None, digest: int = HG_SHA1, out=None,
                      asynchronous: bool = False, stream=None):
         """hg_similarity_n: B's count n_b is a CUDA int64 tensor read when
@@ -478,6 +505,7 @@ class Context:
         raw = bytes(memoryview(recs).cast("B"))
         return torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
 
+    @_on_stream
     def block_hash_batch(self, specs, roots: bool = True, stream=None):
         """Direct hash of many jobs: specs = [(data, block_size, digest)].
         Returns (leaf tensors, root tensors) in spec order."""
@@ -488,6 +516,7 @@ class Context:
         self._check(st)
         return leaves, rts
 
+    @_on_stream
     def run_batch(self, table, n_jobs: int, which: str = "both", asynchronous: bool = True,
                   stream=None, background: bool = False):
         """Run a device job table (from device_job_table): which in
@@ -499,6 +528,7 @@ class Context:
             flags |= HG_BACKGROUND
         self._check(fn(self.handle, table.data_ptr(), n_jobs, flags, _stream_handle(stream)))
 
+    @_on_stream
     def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None,
                    ends_b=None, out=None, asynchronous: bool = False):
         """(matched, matched_bytes) of B's chunk digests against A's.  Chunk
@@ -568,6 +598,8 @@ class Batch:
         self.chunk_digests = torch.zeros((max(self.max_chunks, 1), d2), dtype=torch.uint8, device=dev)
         self.chunk_off = torch.zeros(self.n + 1, dtype=torch.int64, device=dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
+        # the batch may run on another stream: the zero fills end first
+        torch.cuda.current_stream(dev).synchronize()
         self._out = hg_batch_out(self.leaves.data_ptr(), self.roots.data_ptr() if roots else None,
                                  self.chunk_ends.data_ptr(), self.chunk_digests.data_ptr(),
                                  self.chunk_off.data_ptr(), self.status.data_ptr())
@@ -834,9 +866,11 @@ class Chunker:
         self.ctx._check(st)
         return ends, dig, cnt
 
+    @_on_stream
     def feed(self, data, stream=None, asynchronous=False):
         return self._call_async("feed", data, stream) if asynchronous else self._call("feed", data, stream)
 
+    @_on_stream
     def finish(self, stream=None, asynchronous=False):
         return self._call_async("finish", None, stream) if asynchronous else self._call("finish", None, stream)
 
@@ -869,6 +903,7 @@ class BlockMap:
         self.ctx._check(hg_blockmap_size(self.handle, ctypes.byref(n)))
         return int(n.value)
 
+    @_on_stream
     def write(self, digests, ends=None, lengths=None, stream=None):
         """Writes a version's chunk digests ((n, d) uint8 CUDA tensor or
         numpy array); ends (chunk end offsets) or lengths, same placement.

@@ -191,3 +191,59 @@ def test_argument_errors(ctx, hg):
     m = ctypes.c_uint64(0)
     assert hg.hg_similarity_n(ctx.handle, dig.ctypes.data, 4, dig.ctypes.data, None, None, 4, hg.HG_SHA1,
                               ctypes.byref(m), None, 0, None) == hg.HG_EINVAL
+
+
+def test_side_stream_argument(ctx, hg):
+    # Calls given a side stream while torch's current stream is busy: the
+    # outputs they allocate and the fills that zero them are ordered on the
+    # side stream, so nothing lands after the library's writes.
+    data = inputs.uniform_bytes(640, 2 * MiB + 3)
+    exp_starts = oracle.window_scan_sharded(oracle.MD5, data, 20, 1, 0xFFF, 0, THREADS)
+    exp_ends = oracle.chunk_select(exp_starts, 20, data.size, 2048)
+    exp_dig = oracle.chunk_digests(oracle.SHA1, data, exp_ends)
+    lens = np.diff(exp_ends, prepend=np.uint64(0))
+    exp_sim = oracle.similarity(oracle.SHA1, exp_dig, exp_dig[::2], lens[::2])
+    d = torch.from_numpy(data).cuda()
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    note("stage calls on a side stream, current stream busy")
+    a = torch.randn(2048, 2048, device="cuda")
+    for _ in range(200):  # fp32 products: tens of ms on torch's current stream
+        a = a @ a
+        a = a / a.norm()
+    starts = ctx.window_scan(d, 20, 1, 0xFFF, 0, stream=st)
+    with torch.cuda.stream(st):
+        cnt = torch.full((1,), starts.numel(), dtype=torch.int64, device="cuda")
+    ends, n = ctx.chunk_select(starts, cnt, data.size, 20, 2048, asynchronous=True, stream=st)
+    dig = ctx.chunk_digests(d, ends, n, asynchronous=True, stream=st)
+    st.synchronize()
+    k = int(n.item())
+    assert np.array_equal(starts.cpu().numpy().astype(np.uint64), exp_starts)
+    assert k == exp_ends.size
+    assert np.array_equal(ends[:k].cpu().numpy().astype(np.uint64), exp_ends)
+    assert np.array_equal(dig[:k].cpu().numpy(), exp_dig)
+    for _ in range(100):
+        a = a @ a
+        a = a / a.norm()
+    dd = torch.from_numpy(exp_dig).cuda()
+    torch.cuda.synchronize()
+    for _ in range(100):
+        a = a @ a
+        a = a / a.norm()
+    with torch.cuda.stream(st):
+        nb = torch.full((1,), exp_dig[::2].shape[0], dtype=torch.int64, device="cuda")
+        db = dd[::2].contiguous()
+        lb = torch.from_numpy(lens[::2].astype(np.int64)).cuda()
+    got = ctx.similarity_n(dd, db, nb, len_b=lb, stream=st)
+    assert tuple(got) == exp_sim
+    # an asynchronous streaming chunker on the side stream
+    ch = hg.Chunker(ctx)
+    outs = [ch.feed(d[x:x + 700_000], stream=st, asynchronous=True) for x in range(0, data.size, 700_000)]
+    outs.append(ch.finish(stream=st, asynchronous=True))
+    st.synchronize()
+    ch.close()
+    got_e = np.concatenate([e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in outs])
+    got_d = np.concatenate([g[:int(c.item())].cpu().numpy() for _, g, c in outs])
+    assert np.array_equal(got_e, exp_ends)
+    assert np.array_equal(got_d, exp_dig)
+    torch.cuda.synchronize()
