@@ -293,6 +293,13 @@ class Pipeline:
                 raise RuntimeError(f"a step's candidate list exceeded its room: chunk counts {counts}")
             self.nchunks = counts[last % self.NA]
 
+    def close(self):
+        for p in self.pool:
+            p.shutdown()
+        ctxs = self.ctxa + [self.ctx0, self.ctx1, self.ctx3] + self.ctx2 + ([self.ctxw] if self.staged else [])
+        for c in ctxs:
+            c.close()
+
     def latencies_ms(self, first, count):
         out = []
         for i in range(first, first + count):
