@@ -789,7 +789,7 @@ class RequestSet:
 class Chunker:
     """A streaming content-based chunker (hg_chunker) on a Context.
 
-    feed(piece) takes a uint8 CUDA tensor or numpy array and returns
+    feed(piece) takes a uint8 CUDA or CPU tensor or numpy array and returns
     (ends, digests) numpy arrays of the chunks decided so far (absolute
     stream offsets); finish() returns the rest.  With asynchronous=True
     both return (ends, digests, count) CUDA tensors instead, written in
@@ -819,8 +819,16 @@ class Chunker:
         except Exception:
             pass
 
+    @staticmethod
+    def _host_view(data):
+        # a CPU torch tensor is passed as the numpy array over its memory
+        if data is not None and hasattr(data, "is_cuda") and not data.is_cuda:
+            return data.contiguous().numpy()
+        return data
+
     def _call(self, fn, data, stream):
         import numpy as np
+        data = self._host_view(data)
         n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
         b = _u64(0)
         self.ctx._check(hg_chunker_bound(self.handle, n, ctypes.byref(b)))
@@ -844,6 +852,7 @@ class Chunker:
 
     def _call_async(self, fn, data, stream):
         import torch
+        data = self._host_view(data)
         n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
         b = _u64(0)
         self.ctx._check(hg_chunker_bound(self.handle, n, ctypes.byref(b)))

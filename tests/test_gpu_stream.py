@@ -171,7 +171,7 @@ ASYNC_CASES = [  # (length, w, s, mask, target, min, max, segment)
 
 
 @pytest.mark.parametrize("case", ASYNC_CASES)
-@pytest.mark.parametrize("where", ["device", "pinned", "pageable"])
+@pytest.mark.parametrize("where", ["device", "pinned", "pageable", "torch_pinned"])
 def test_stream_async_feeds(ctx, hg, case, where):
     # HG_ASYNC: every feed returns once its cuts are decided, its digests
     # still running; host input comes through ONE staging array that is
@@ -184,8 +184,9 @@ def test_stream_async_feeds(ctx, hg, case, where):
     splits = pieces(rng, length, cuts + [c + 1 for c in cuts])
     note(f"async stream case={case} input={where} pieces={len(splits)}")
     big = max(b - a for a, b in splits)
-    if where == "pinned":
-        stage = torch.empty(max(big, 1), dtype=torch.uint8, pin_memory=True).numpy()
+    if where in ("pinned", "torch_pinned"):
+        stage_t = torch.empty(max(big, 1), dtype=torch.uint8, pin_memory=True)
+        stage = stage_t.numpy()
     else:
         stage = np.empty(max(big, 1), dtype=np.uint8)
     dev = torch.from_numpy(data).cuda() if where == "device" else None
@@ -196,7 +197,7 @@ def test_stream_async_feeds(ctx, hg, case, where):
             piece = dev[a:b]
         else:
             stage[:b - a] = data[a:b]
-            piece = stage[:b - a]
+            piece = stage_t[:b - a] if where == "torch_pinned" else stage[:b - a]  # CPU tensor or array
         outs.append(ch.feed(piece, asynchronous=True))
         if where != "device":
             stage[:] = 0xA5  # the call has read its input
