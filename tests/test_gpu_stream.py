@@ -224,3 +224,40 @@ def test_stream_async_needs_device_outputs(ctx, hg):
     exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, 0)
     assert np.array_equal(np.concatenate([e, e2]), exp_ends)
     ch.close()
+
+
+def test_stream_async_reset_with_digests_pending(ctx, hg):
+    # Two streams through one chunker, the second started by reset() while
+    # the first one's last digests may still run, with host-count feeds
+    # (HG_COUNT_HOST) in the second: both outputs equal the one-shot result.
+    import ctypes
+    data = inputs.uniform_bytes(550, 3 * MiB + 17)
+    exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, 0)
+    note("async feeds across a reset")
+    ch = hg.Chunker(ctx)
+    first = [ch.feed(data[a:a + MiB], asynchronous=True) for a in range(0, data.size, MiB)]
+    first.append(ch.finish(asynchronous=True))
+    ch.reset()
+    outs = []
+    for a in range(0, data.size + 1, 777_777):
+        piece = data[a:a + 777_777]
+        b = ctypes.c_uint64(0)
+        assert hg.hg_chunker_bound(ch.handle, piece.size, ctypes.byref(b)) == hg.HG_OK
+        ends = torch.empty(int(b.value), dtype=torch.int64, device="cuda")
+        dig = torch.empty((int(b.value), 20), dtype=torch.uint8, device="cuda")
+        n = ctypes.c_uint64(0)
+        st = hg.hg_chunker_feed(ch.handle, piece.ctypes.data if piece.size else None, piece.size,
+                                hg.HG_OUT_DEVICE | hg.HG_ASYNC | hg.HG_COUNT_HOST, ends.data_ptr(), int(b.value),
+                                ctypes.byref(n), dig.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        assert st == hg.HG_OK
+        outs.append((ends, dig, int(n.value)))  # the host count is final when the call returns
+    e, d, c = ch.finish(asynchronous=True)
+    torch.cuda.synchronize()
+    outs.append((e, d, int(c.item())))
+    ch.close()
+    got1_e = np.concatenate([e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in first])
+    got1_d = np.concatenate([d[:int(c.item())].cpu().numpy() for _, d, c in first])
+    assert np.array_equal(got1_e, exp_ends) and np.array_equal(got1_d, exp_dig)
+    got2_e = np.concatenate([e[:k].cpu().numpy().astype(np.uint64) for e, _, k in outs])
+    got2_d = np.concatenate([d[:k].cpu().numpy() for _, d, k in outs])
+    assert np.array_equal(got2_e, exp_ends) and np.array_equal(got2_d, exp_dig)
