@@ -22,13 +22,14 @@
  *   - Stream: `stream` is a hipStream_t (NULL = the default stream).  All
  *     GPU work of the call is ordered on it.
  *   - Synchrony: without HG_ASYNC the call returns when its results are in
- *     the caller's memory.  HG_ASYNC (valid only with HG_IN_DEVICE and
- *     HG_OUT_DEVICE, and only for hg_block_hash, hg_window_scan,
- *     hg_similarity, hg_chunk and the chunking stages below) returns after
- *     enqueueing; results are valid
- *     once the stream has completed, and truncation can then only be seen by
- *     comparing the written count with the capacity (hg_chunk still waits
- *     for its counts, see there).
+ *     the caller's memory.  HG_ASYNC (valid with HG_IN_DEVICE and
+ *     HG_OUT_DEVICE for hg_block_hash, hg_block_hash_dual, hg_window_scan,
+ *     hg_similarity, hg_chunk and the chunking stages below; with a device
+ *     job table for the batch calls; with HG_OUT_DEVICE for the streaming
+ *     chunker's feeds) returns after enqueueing; results are valid once the
+ *     stream has completed, and truncation can then only be seen by
+ *     comparing the written count with the capacity (hg_chunk and the
+ *     chunker still wait for the counts they need, see there).
  *   - Sizes: lengths and offsets are 64-bit; inputs may exceed 4 GiB.  Work
  *     that needs 2^31 or more candidates, chunks, two-level chunk segments
  *     or similarity digests in one call is refused with HG_EINVAL (split the
