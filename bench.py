@@ -810,7 +810,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+              "(the path runs on one GPU; sharding across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
     # Three concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
