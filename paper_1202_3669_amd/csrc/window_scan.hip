@@ -39,10 +39,14 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t &total)
     __shared__ uint32_t wave_sum[WS_TPB / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t x = v;
+    // Most waves of a window scan have no candidate: their inclusive scan
+    // is all zeros, so the shuffle steps run only where some lane has v > 0.
+    if (__ballot(v != 0)) {
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
     }
     if (lane == 63) wave_sum[wid] = x;
     __syncthreads();
@@ -139,15 +143,27 @@ __device__ __forceinline__ uint32_t ws_reg_bits(const TileView v, uint32_t mask,
         }
     }
     const uint32_t st[4] = {MD5_IV0, MD5_IV1, MD5_IV2, MD5_IV3};
-    uint32_t bits = 0;
+    // Candidates are rare (one window in 2^popcount(mask)): per window the
+    // test is one 3-input logic op, t = (word0 & mask) ^ target (zero for a
+    // candidate), and a running minimum; the lane bits are formed only in
+    // waves where some lane saw t = 0.  Windows at or past nwin (the lane's
+    // last group may run over) are cleared there.
+    uint32_t t[WS_G];
+    uint32_t z = 0xFFFFFFFFu;
 #pragma unroll
     for (int g = 0; g < WS_G; g++) {
         uint32_t X[16];
 #pragma unroll
         for (int j = 0; j < 16; j++) X[j] = win_word<W, ND>(dw, g * S, j);
-        uint32_t a0 = md5_compress_word0(st, X);
-        bool hit = ((a0 & mask) == target) && (k0 + g < v.nwin);
-        bits |= (uint32_t)hit << g;
+        t[g] = (md5_compress_word0(st, X) & mask) ^ target;
+        z = z < t[g] ? z : t[g];
+    }
+    uint32_t bits = 0;
+    if (__ballot(z == 0)) {
+#pragma unroll
+        for (int g = 0; g < WS_G; g++) bits |= (uint32_t)(t[g] == 0) << g;
+        const uint64_t left = v.nwin - k0;  // >= 1 here
+        if (left < WS_G) bits &= (1u << left) - 1u;
     }
     return bits;
 }
