@@ -440,9 +440,10 @@ def breakdown(torch, hg, data, host_pinned):
             ts.append(a.elapsed_time(b) / inner)
         return ts
 
-    def kernel_ms(fn, reps=20):
-        # Average duration of the segment-digest launches, from the HIP
-        # events the library records around each launch on its stream,
+    def kernel_ms(fn, reps=20, name="leaves"):
+        # Average duration of one kernel class's launches (segment digests
+        # by default), from the HIP events the library records around each
+        # launch on its stream,
         # after about 0.1 s of back-to-back warm-up launches: a kernel that
         # reads HBM at 4-5 TB/s runs up to 1.4x slower for its first tens of
         # launches after a pause, then settles (rocprofv3 per-launch trace).
@@ -458,7 +459,7 @@ def breakdown(torch, hg, data, host_pinned):
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
-        launches, ms = ctx.timing_read("leaves")
+        launches, ms = ctx.timing_read(name)
         ctx.timing(False)
         return ms / max(launches, 1)
 
@@ -497,8 +498,13 @@ def breakdown(torch, hg, data, host_pinned):
                                         "capped_frac": round(frac / cap, 4)}
     for st in (1, 4):
         t = statistics.median(timed(lambda: ctx.window_scan(data, 20, st, 0xFFF, 0), reps=3))
+        # the window kernel alone (its launches' own events), beside the whole call
+        tk = kernel_ms(lambda: ctx.window_scan(data, 20, st, 0xFFF, 0), reps=5, name="window_tiles")
+        nwin = (n - 20) // st + 1
         res[f"window_md5_w20_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1),
-                                        "Gwindows_per_s": round(((n - 20) // st + 1) / t / 1e6, 1)}
+                                        "Gwindows_per_s": round(nwin / t / 1e6, 1),
+                                        "kernel_ms": round(tk, 3), "kernel_Gwindows_per_s": round(nwin / tk / 1e6, 1),
+                                        "kernel_alu_frac": round(nwin * WINDOW_OPS / (tk / 1e3) / peak, 4)}
         t = statistics.median(timed(lambda: ctx.chunk(data, 20, st, 0xFFF, 0, 2 * KiB), reps=3))
         res[f"chunk_s{st}"] = {"ms": round(t, 3), "GBps": round(n / t / 1e6, 1)}
     # Streaming chunker: the 1 GiB fed in 64 MiB pieces (device-resident,
