@@ -18,16 +18,16 @@ Workload (one step = one pass of the whole path over one input):
 Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1): the
 second-level hash of a job is one sequential chain (for 4 KiB SHA-1 segments
 of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
-sequential chains per job.  Per step, chunking runs on stream SA[step % 3]
+sequential chains per job.  Per step, chunking runs on stream SA[step % 5]
 (the window scan is the throughput engine; while one stream waits for its
 counts or runs its chunk digests, the others' window scans run) and the
 4 KiB / 64 KiB segments on stream SB; for a group of G = 24 steps, the 1 MiB
 segments run as one batched launch on stream S1 and all second levels as one
 batched launch on stream S2[group % 2], while the other streams carry on
 with the next group.  A step's latency therefore ends when its group's roots
-are done.  Seven busy streams need as many hardware queues: HIP shares its
+are done.  Ten busy streams need as many hardware queues: HIP shares its
 default four queues among all streams of the process, so the benchmark asks
-for eight (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
+for eleven (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
 
 value = hashed bytes per second: each of the 7 primitive passes (6 direct
 hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
@@ -54,7 +54,7 @@ WINDOW_OPS = 19 * 5 + 42 * 4
 # swaps + 5 final additions.
 BLOCK_OPS = {0: 324, 1: 613}
 # Chunking streams (steps round-robin), each driven by its own host thread.
-CHUNK_STREAMS = 3
+CHUNK_STREAMS = 5
 CHUNK_CALLS = "single"
 AHEAD = 8  # stages mode: steps queued ahead of the last finished chunking
 
@@ -818,7 +818,7 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path runs on one GPU; sharding across GPUs is a design, not built)", file=sys.stderr)
         sys.exit(2)
-    # Three concurrently busy streams: give HIP enough hardware queues before
+    # Many concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
     queues = max(8, args.chunk_streams + 6)  # chunking streams + window, SB, S1, two S2, default
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:

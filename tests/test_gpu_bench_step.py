@@ -1,7 +1,7 @@
 """GPU parity of the timed step itself: bench.py's pipeline (the 1 GiB
 input, seed 2, resident in HBM; six direct hashes through the persistent
-job tables with the 1 MiB chains batched per group, chunking on three
-streams, similarity against the previous version's digests) run for more
+job tables with the 1 MiB chains batched per group, chunking round-robin
+over its chunking streams, similarity against the previous version's digests) run for more
 steps than its ring of output slots holds, in both chunking modes.  Every
 slot's segment digests and second levels, the chunk ends and digests of
 each chunking stream and every step's similarity equal the oracle's,
@@ -57,7 +57,6 @@ def workload():
 def test_pipeline_step_outputs(hg, workload, monkeypatch, mode, group, steps):
     data_np, prev_dig, ends, dig, sim, leaves, roots = workload
     monkeypatch.setattr(bench, "CHUNK_CALLS", mode)
-    monkeypatch.setattr(bench, "CHUNK_STREAMS", 3)
     note(f"bench pipeline mode={mode} group={group} steps={steps}")
     data = torch.from_numpy(data_np).cuda()
     pipe = bench.Pipeline(torch, hg, data, torch.from_numpy(prev_dig).cuda(), group)
