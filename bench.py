@@ -21,7 +21,7 @@ of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
 sequential chains per job.  Per step, chunking runs on stream SA[step % 5]
 (the window scan is the throughput engine; while one stream waits for its
 counts or runs its chunk digests, the others' window scans run) and the
-4 KiB / 64 KiB segments on stream SB; for a group of G = 24 steps, the 1 MiB
+4 KiB / 64 KiB segments on stream SB; for a group of G = 32 steps, the 1 MiB
 segments run as one batched launch on stream S1 and all second levels as one
 batched launch on stream S2[group % 2], while the other streams carry on
 with the next group.  A step's latency therefore ends when its group's roots
@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=12)
-    ap.add_argument("--group", type=int, default=24, help="steps per long-chain batch")
+    ap.add_argument("--group", type=int, default=32, help="steps per long-chain batch")
     ap.add_argument("--chunk-calls", choices=["single", "stages"], default=CHUNK_CALLS,
                     help="one hg_chunk per step (host threads wait on its counts), or the chunking "
                          "stages with device counts (window scans back to back on one stream)")

@@ -53,7 +53,7 @@ def workload():
     return data, prev_dig, ends, dig, sim, leaves, roots
 
 
-@pytest.mark.parametrize("mode,group,steps", [("single", 24, 51), ("stages", 4, 11)])
+@pytest.mark.parametrize("mode,group,steps", [("single", 32, 67), ("stages", 4, 11)])
 def test_pipeline_step_outputs(hg, workload, monkeypatch, mode, group, steps):
     data_np, prev_dig, ends, dig, sim, leaves, roots = workload
     monkeypatch.setattr(bench, "CHUNK_CALLS", mode)
