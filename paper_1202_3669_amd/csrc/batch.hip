@@ -290,12 +290,17 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
     }
 }
 
-__global__ __launch_bounds__(64) void leaves_batch_kernel(const hg_block_job *__restrict__ jobs,
+// Workgroups of one to four wavefronts; every wavefront works on its own
+// (ballots and shuffles only, no workgroup barrier), numbered w across the
+// grid.
+__global__ __launch_bounds__(256) void leaves_batch_kernel(const hg_block_job *__restrict__ jobs,
                                                            uint32_t n_jobs, Plan *plan, int boost) {
-    // Split the grid between the two digest kinds in proportion to their
-    // VALU work (an MD5 block costs about half a SHA-1 block).
+    // Split the grid's wavefronts between the two digest kinds in proportion
+    // to their VALU work (an MD5 block costs about half a SHA-1 block).
     const double w0 = (double)plan->blocks[0] * 328.0, w1 = (double)plan->blocks[1] * 618.0;
-    const uint32_t g = gridDim.x;
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t g = gridDim.x * wpg;
+    const uint32_t w = blockIdx.x * wpg + (threadIdx.x >> 6);
     uint32_t g0;
     if (plan->tasks[1] == 0) g0 = g;
     else if (plan->tasks[0] == 0) g0 = 0;
@@ -304,11 +309,10 @@ __global__ __launch_bounds__(64) void leaves_batch_kernel(const hg_block_job *__
         g0 = g0 < 1 ? 1 : (g0 > g - 1 ? g - 1 : g0);
     }
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x < g0)
-        leaves_worker<KIND_MD5>(jobs, n_jobs, plan, boost != 0, (uint64_t)blockIdx.x * 64 + lane,
-                                (uint64_t)g0 * 64);
+    if (w < g0)
+        leaves_worker<KIND_MD5>(jobs, n_jobs, plan, boost != 0, (uint64_t)w * 64 + lane, (uint64_t)g0 * 64);
     else
-        leaves_worker<KIND_SHA1>(jobs, n_jobs, plan, boost != 0, (uint64_t)(blockIdx.x - g0) * 64 + lane,
+        leaves_worker<KIND_SHA1>(jobs, n_jobs, plan, boost != 0, (uint64_t)(w - g0) * 64 + lane,
                                  (uint64_t)(g - g0) * 64);
 }
 
@@ -339,9 +343,11 @@ hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *pl
     return hipGetLastError();
 }
 
-hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t grid,
-                               bool boost, hipStream_t s) {
-    leaves_batch_kernel<<<grid, 64, 0, s>>>(jobs, n_jobs, (Plan *)plan, boost ? 1 : 0);
+hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t waves,
+                               uint32_t wg_waves, bool boost, hipStream_t s) {
+    if (wg_waves != 1 && wg_waves != 2 && wg_waves != 4) return hipErrorInvalidValue;
+    const uint32_t grid = (waves + wg_waves - 1) / wg_waves;
+    leaves_batch_kernel<<<grid, 64 * wg_waves, 0, s>>>(jobs, n_jobs, (Plan *)plan, boost ? 1 : 0);
     return hipGetLastError();
 }
 

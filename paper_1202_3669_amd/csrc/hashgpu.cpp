@@ -651,7 +651,7 @@ int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t 
         // per CU); fewer when the host knows there are fewer segments.
         uint32_t grid = 8192;
         if (host_table) grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(grid, (total_leaves + 63) / 64 + 1));
-        HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, boost, st));
+        HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, 1, boost, st));
     }
     if (roots) HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, boost, st));
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
@@ -1115,8 +1115,10 @@ struct hg_batch {
     void *d_tl = nullptr;
     uint8_t *d_tl_leaves = nullptr;
     uint64_t tl_slots = 0;
-    // schedule (set by hg_batch_tune)
+    // schedule (set by hg_batch_tune): wavefronts of the persistent grid,
+    // wavefronts per workgroup, file order
     uint32_t grid = 8192;
+    uint32_t wg_waves = 1;
     bool longest_first = true;
     // concurrency and graph
     hipStream_t aux = nullptr;
@@ -1166,7 +1168,7 @@ int batch_hash(hg_batch *b, const uint8_t *arena, const hg_batch_out *out, hipSt
                                          b->p.block_size, b->p.block_digest, (uint8_t *)out->leaf_digests,
                                          b->p.roots ? (uint8_t *)out->roots : nullptr, b->d_jobs, st));
     HG_HIP(b->ctx, hg::launch_batch_plan(b->d_jobs, b->n, b->d_plan, st));
-    HG_HIP(b->ctx, hg::launch_leaves_batch(b->d_jobs, b->n, b->d_plan, b->grid, true, st));
+    HG_HIP(b->ctx, hg::launch_leaves_batch(b->d_jobs, b->n, b->d_plan, b->grid, b->wg_waves, true, st));
     if (b->p.roots) HG_HIP(b->ctx, hg::launch_roots_batch(b->d_jobs, b->n, b->d_plan, true, st));
     return HG_OK;
 }
@@ -1432,14 +1434,17 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
         HG_HIP(b->ctx, hipEventCreate(&e0));
         HG_HIP(b->ctx, hipEventCreate(&e1));
         float best = 1e30f;
-        uint32_t best_grid = b->grid;
+        uint32_t best_grid = b->grid, best_wg = b->wg_waves;
         bool best_order = b->longest_first;
         const uint32_t grids[] = {1024, 2048, 4096, 8192};
+        const uint32_t wgs[] = {1, 4};
         for (int lf = 1; lf >= 0; lf--) {
             const std::vector<uint32_t> &ord = lf ? b->order_desc : b->order_given;
             HG_HIP(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
+            for (uint32_t wg : wgs)
             for (uint32_t g : grids) {
                 b->grid = g;
+                b->wg_waves = wg;
                 float t = 1e30f;
                 for (int rep_i = 0; rep_i < 3; rep_i++) {
                     HG_HIP(b->ctx, hipEventRecord(e0, st));
@@ -1451,11 +1456,12 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
                     if (rep_i > 0) t = std::min(t, ms);  // first run warms up
                 }
                 char buf[96];
-                snprintf(buf, sizeof buf, "%s/%u:%.3fms ", lf ? "longest" : "given", g, t);
+                snprintf(buf, sizeof buf, "%s/%ux%u:%.3fms ", lf ? "longest" : "given", g, 64 * wg, t);
                 rep += buf;
                 if (t < best) {
                     best = t;
                     best_grid = g;
+                    best_wg = wg;
                     best_order = lf;
                 }
             }
@@ -1463,11 +1469,13 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         b->grid = best_grid;
+        b->wg_waves = best_wg;
         b->longest_first = best_order;
         const std::vector<uint32_t> &ord = best_order ? b->order_desc : b->order_given;
         HG_HIP(b->ctx, hipMemcpy(b->d_order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice));
         char buf[128];
-        snprintf(buf, sizeof buf, "-> %s order, %u workgroups", best_order ? "longest-first" : "given", best_grid);
+        snprintf(buf, sizeof buf, "-> %s order, %u wavefronts in workgroups of %u lanes",
+                 best_order ? "longest-first" : "given", best_grid, 64 * best_wg);
         rep += buf;
         // A graph captured before holds the old schedule.
         if (b->exec) (void)hipGraphExecDestroy(b->exec);

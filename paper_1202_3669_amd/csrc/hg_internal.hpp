@@ -202,9 +202,11 @@ hipError_t launch_files_jobs(const uint8_t *arena, const uint64_t *off, const ui
 // two launchers that follow it on the same stream.
 size_t batch_plan_bytes(uint32_t n_jobs);
 hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s);
-// boost: waves on long chains raise their issue priority.
-hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t grid,
-                               bool boost, hipStream_t s);
+// A persistent grid of `waves` wavefronts (rounded up to whole workgroups)
+// in workgroups of wg_waves (1, 2 or 4) wavefronts.  boost: waves on long
+// chains raise their issue priority.
+hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t waves,
+                               uint32_t wg_waves, bool boost, hipStream_t s);
 hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, bool boost, hipStream_t s);
 
 // ----------------------------------------------------------- similarity --

@@ -202,8 +202,22 @@ def test_batch_tuner_keeps_results(ctx, hg):
     b.run(d)
     fetch(b)
     ref = (b._lv.copy(), b._rt.copy())
+    b.leaves.zero_()
+    b.roots.zero_()
+    torch.cuda.synchronize()
     report = b.tune(d)
     assert "->" in report, report
+    # every candidate was timed: both file orders, 64- and 256-lane
+    # workgroups, 1024-8192 wavefronts
+    for order in ("longest", "given"):
+        for g in (1024, 2048, 4096, 8192):
+            for lanes in (64, 256):
+                assert f"{order}/{g}x{lanes}:" in report, report
+    # the outputs of the last candidate timed (given order, 8192 wavefronts
+    # in 256-lane workgroups), then of the chosen schedule
+    torch.cuda.synchronize()
+    fetch(b)
+    assert np.array_equal(b._lv, ref[0]) and np.array_equal(b._rt, ref[1])
     b.run(d)
     fetch(b)
     assert np.array_equal(b._lv, ref[0]) and np.array_equal(b._rt, ref[1])
