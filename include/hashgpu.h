@@ -429,8 +429,8 @@ int hg_batch_replay(hg_batch *b, void *stream);
 
 /* Schedule autotuner: times the direct-hash part of the batch under each
  * candidate segment-to-lane schedule (file order: longest first or as
- * given; persistent grid: 1024-8192 wavefronts; lanes per workgroup: 64 or
- * 256) with HIP events, keeps the fastest for later runs (and captures),
+ * given; persistent grid: 1024-8192 wavefronts; lanes per workgroup: 64,
+ * 128 or 256) with HIP events, keeps the fastest for later runs (and captures),
  * and writes a one-line report of what it measured.  Synchronous. */
 int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void *stream, char *report,
                   size_t report_len);

@@ -476,7 +476,7 @@ int enqueue_blocks(Group &g, bool boost) {
     SV_HIP(hipMemcpyAsync(g.d_jobs, g.h_jobs, (size_t)n * sizeof(hg_block_job), hipMemcpyHostToDevice, st));
     SV_HIP(hg::launch_batch_plan(g.d_jobs, n, g.d_plan, st));
     const uint32_t grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(8192, (total_leaves + 63) / 64 + 1));
-    SV_HIP(hg::launch_leaves_batch(g.d_jobs, n, g.d_plan, grid, 1, boost, st));
+    SV_HIP(hg::launch_leaves_batch(g.d_jobs, n, g.d_plan, grid, 2, boost, st));
     SV_HIP(hg::launch_roots_batch(g.d_jobs, n, g.d_plan, boost, st));
     if (leaf_off) SV_HIP(hipMemcpyAsync(g.h_leaves, g.d_leaves, leaf_off, hipMemcpyDeviceToHost, st));
     SV_HIP(hipMemcpyAsync(g.h_roots, g.d_roots, (size_t)n * 20, hipMemcpyDeviceToHost, st));

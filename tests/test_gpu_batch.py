@@ -207,11 +207,11 @@ def test_batch_tuner_keeps_results(ctx, hg):
     torch.cuda.synchronize()
     report = b.tune(d)
     assert "->" in report, report
-    # every candidate was timed: both file orders, 64- and 256-lane
+    # every candidate was timed: both file orders, 64-, 128- and 256-lane
     # workgroups, 1024-8192 wavefronts
     for order in ("longest", "given"):
         for g in (1024, 2048, 4096, 8192):
-            for lanes in (64, 256):
+            for lanes in (64, 128, 256):
                 assert f"{order}/{g}x{lanes}:" in report, report
     # the outputs of the last candidate timed (given order, 8192 wavefronts
     # in 256-lane workgroups), then of the chosen schedule
