@@ -19,6 +19,9 @@ Every routine follows a passage of "GPUs as Storage System Accelerators":
                       standard digest of its bytes, or its two-level direct
                       hash (Sec. 3.2.2) with a segment size.
 * ``similarity``      block-map lookup of Sec. 3.2.1 (similarity % of Sec. 4.3).
+* ``BlockMap``        the block-map of a content-addressable store across
+                      writes (Sec. 3.2.1): per chunk of a write, whether its
+                      digest is already held, and the digests held after it.
 
 ``map_ranges`` shards independent units (segments, windows) over threads and
 concatenates the per-range results in order; the result is identical to the
@@ -91,6 +94,14 @@ def _bind(path: str):
     lib.oracle_chunk_digests.restype = _int
     lib.oracle_similarity.argtypes = [_int, _vp, _u64, _vp, _vp, _u64, _vp]
     lib.oracle_similarity.restype = _u64
+    lib.oracle_blockmap_create.argtypes = [_int, _u64]
+    lib.oracle_blockmap_create.restype = _vp
+    lib.oracle_blockmap_destroy.argtypes = [_vp]
+    lib.oracle_blockmap_destroy.restype = None
+    lib.oracle_blockmap_size.argtypes = [_vp]
+    lib.oracle_blockmap_size.restype = _u64
+    lib.oracle_blockmap_write.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _vp]
+    lib.oracle_blockmap_write.restype = _int
     lib.oracle_init()  # fill the constant tables once, before any threads
     return lib
 
@@ -254,7 +265,23 @@ def chunk(kind_window: int, kind_chunk: int, data, window: int, stride: int, mas
     buf = _bytes_view(data)
     starts = window_scan_sharded(kind_window, buf, window, stride, mask, target, threads)
     ends = chunk_select(starts, window, buf.size, min_chunk, max_chunk)
-    return starts, ends, chunk_digests(kind_chunk, buf, ends, segment)
+    return starts, ends, chunk_digests_sharded(kind_chunk, buf, ends, segment, threads)
+
+
+def chunk_digests_sharded(kind, data, ends, segment=0, threads=1):
+    """chunk_digests over contiguous ranges of chunks on several threads
+    (chunks are independent: range [j0, j1) is the same call on the bytes
+    from ends[j0-1] with its ends shifted by that offset)."""
+    buf = _bytes_view(data)
+    e = np.ascontiguousarray(ends, dtype=np.uint64)
+    if threads <= 1 or e.size < 64:
+        return chunk_digests(kind, buf, e, segment)
+
+    def part(j0, j1):
+        s0 = int(e[j0 - 1]) if j0 else 0
+        return chunk_digests(kind, buf[s0:int(e[j1 - 1])], e[j0:j1] - np.uint64(s0), segment)
+    parts = map_ranges(part, e.size, threads, 16)
+    return np.concatenate(parts)
 
 
 def map_ranges(fn, n: int, threads: int, min_per_range: int = 1):
@@ -284,3 +311,52 @@ def leaves_sharded(kind, data, block, threads=1):
     parts = map_ranges(lambda a, b: leaves(kind, buf, block, a, b), n, threads)
     d = DIGEST_SIZE[kind]
     return np.concatenate(parts) if parts else np.zeros((0, d), dtype=np.uint8)
+
+
+class BlockMap:
+    """The store's block-map across writes (Sec. 3.2.1).  ``write`` takes one
+    write's chunk digests in order and returns (is_dup, dup_chunks,
+    dup_bytes): a chunk is a duplicate iff its digest is held when its turn
+    comes (stored by an earlier write, or equal to an earlier chunk of this
+    write); the others are stored.  ``lengths`` (or ``ends``, chunk end
+    offsets) give the bytes.  A write that could exceed ``capacity`` raises
+    ``OverflowError`` and changes nothing."""
+
+    def __init__(self, kind: int, capacity: int = 1 << 62):
+        self._lib = _load()
+        self.kind, self.d = kind, DIGEST_SIZE[kind]
+        self._h = self._lib.oracle_blockmap_create(kind, capacity)
+        if not self._h:
+            raise MemoryError("oracle_blockmap_create failed")
+
+    def write(self, digests, lengths=None, ends=None):
+        dig = np.ascontiguousarray(digests, dtype=np.uint8).reshape(-1, self.d)
+        n = dig.shape[0]
+        if ends is not None:
+            lengths = np.diff(np.ascontiguousarray(ends, dtype=np.uint64), prepend=np.uint64(0))
+        ln = None if lengths is None else np.ascontiguousarray(lengths, dtype=np.uint64)
+        if ln is not None and ln.size != n:
+            raise ValueError("one length per digest")
+        dup = np.zeros(n, dtype=np.uint8)
+        c, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        r = self._lib.oracle_blockmap_write(self._h, _ptr(dig), None if ln is None else _ptr(ln), n,
+                                            _ptr(dup), ctypes.addressof(c), ctypes.addressof(b))
+        if r == -5:
+            raise OverflowError("block-map capacity")
+        if r != 0:
+            raise ValueError("oracle_blockmap_write failed")
+        return dup.astype(bool), int(c.value), int(b.value)
+
+    def size(self) -> int:
+        return int(self._lib.oracle_blockmap_size(self._h))
+
+    def close(self):
+        if self._h:
+            self._lib.oracle_blockmap_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -26,6 +26,9 @@
  *   - Similarity: fraction of the new version's chunks whose hash appears in
  *     the previous version's block-map (Sec. 3.2.1; similarity percentages
  *     of Sec. 4.3).
+ *   - The block-map write of a content-addressable store: which chunks of a
+ *     write are already held (and need not be stored) and the digests held
+ *     afterwards (Sec. 3.2.1).
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   - a short last segment is hashed as-is with standard padding;
@@ -386,4 +389,114 @@ uint64_t oracle_similarity(int kind, const uint8_t *dig_a, uint64_t n_a, const u
     free(sorted);
     if (matched_bytes) *matched_bytes = bytes;
     return matched;
+}
+
+/* ------------------------------------------------------------- block map -- */
+/* The block-map of a content-addressable store (Sec. 3.2.1): data written to
+ * the store is cut into chunks named by their digests, the block-map holds
+ * the digests of every chunk stored so far, and a chunk whose digest is
+ * already held is not stored again.  A write hands over n chunk digests in
+ * order; chunk i is a duplicate iff its digest is held when its turn comes,
+ * i.e. it was stored by an earlier write or it equals an earlier chunk j < i
+ * of the same write (chunk j's digest is held from then on, whether j was
+ * stored or was itself a duplicate).  Every other chunk is stored and its
+ * digest added.  The held digests are kept as a sorted array; membership is
+ * a binary search.  Capacity is a limit of the interface, not of the paper:
+ * a write that could exceed it (size + n > capacity) is refused and changes
+ * nothing. */
+typedef struct {
+    int kind, d;
+    uint64_t capacity, n;
+    uint8_t *dig; /* n sorted digests */
+} oracle_blockmap;
+
+typedef struct {
+    uint8_t dig[20];
+    uint64_t idx;
+} bm_rec;
+
+/* Records in digest order; equal digests in chunk order.  An MD5 digest
+ * fills the first 16 bytes and the rest are zero, so comparing all 20
+ * bytes orders both digest sizes. */
+static int bm_cmp_rec(const void *x, const void *y) {
+    const bm_rec *a = (const bm_rec *)x, *b = (const bm_rec *)y;
+    int c = memcmp(a->dig, b->dig, sizeof a->dig);
+    if (c) return c;
+    return a->idx < b->idx ? -1 : (a->idx > b->idx ? 1 : 0);
+}
+
+oracle_blockmap *oracle_blockmap_create(int kind, uint64_t capacity) {
+    int d = oracle_digest_size(kind);
+    if (d < 0) return NULL;
+    oracle_blockmap *m = (oracle_blockmap *)calloc(1, sizeof *m);
+    if (!m) return NULL;
+    m->kind = kind;
+    m->d = d;
+    m->capacity = capacity;
+    return m;
+}
+
+void oracle_blockmap_destroy(oracle_blockmap *m) {
+    if (!m) return;
+    free(m->dig);
+    free(m);
+}
+
+uint64_t oracle_blockmap_size(const oracle_blockmap *m) { return m ? m->n : 0; }
+
+/* One write: dig holds n digests (chunk order), len their lengths (or NULL).
+ * is_dup (n bytes, may be NULL) receives 1 for a duplicate, 0 for a stored
+ * chunk; *dup_chunks / *dup_bytes the number of duplicates and the sum of
+ * their lengths.  Returns 0, -1 for bad arguments, -5 when refused for
+ * capacity. */
+int oracle_blockmap_write(oracle_blockmap *m, const uint8_t *dig, const uint64_t *len, uint64_t n,
+                          uint8_t *is_dup, uint64_t *dup_chunks, uint64_t *dup_bytes) {
+    if (!m || (n && !dig)) return -1;
+    if (m->n + n > m->capacity) return -5;
+    const int d = m->d;
+    uint64_t count = 0, bytes = 0, added = 0;
+    bm_rec *r = NULL;
+    uint8_t *dup = NULL, *grown = NULL;
+    if (n) {
+        r = (bm_rec *)malloc((size_t)n * sizeof *r);
+        dup = (uint8_t *)malloc((size_t)n);
+        grown = (uint8_t *)realloc(m->dig, (size_t)((m->n + n) * (uint64_t)d));
+        if (!r || !dup || !grown) {
+            free(r);
+            free(dup);
+            if (grown) m->dig = grown;
+            return -1;
+        }
+        m->dig = grown;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        memset(r[i].dig, 0, sizeof r[i].dig);
+        memcpy(r[i].dig, dig + i * (uint64_t)d, (size_t)d);
+        r[i].idx = i;
+    }
+    if (n) qsort(r, (size_t)n, sizeof *r, bm_cmp_rec);
+    for (uint64_t k = 0; k < n; k++) {
+        const uint64_t i = r[k].idx;
+        const int repeat = k > 0 && memcmp(r[k - 1].dig, r[k].dig, (size_t)d) == 0;
+        const int held = m->n && bsearch(r[k].dig, m->dig, (size_t)m->n, (size_t)d,
+                                         d == 16 ? cmp_md5 : cmp_sha1) != NULL;
+        dup[i] = (uint8_t)(repeat || held);
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        if (dup[i]) {
+            count++;
+            if (len) bytes += len[i];
+        } else {
+            memcpy(m->dig + (m->n + added) * (uint64_t)d, dig + i * (uint64_t)d, (size_t)d);
+            added++;
+        }
+    }
+    m->n += added;
+    if (m->n) qsort(m->dig, (size_t)m->n, (size_t)d, d == 16 ? cmp_md5 : cmp_sha1);
+    if (is_dup && n) memcpy(is_dup, dup, (size_t)n);
+    if (dup_chunks) *dup_chunks = count;
+    if (dup_bytes) *dup_bytes = bytes;
+    free(r);
+    free(dup);
+    return 0;
 }

@@ -21,6 +21,12 @@ The oracle is checked against things other than itself:
   no maximum when no chunk can reach it.
 * Chunk digests against ``hashlib`` per chunk; similarity against constructed
   digest sets with a known overlap.
+* The block-map write (Sec. 3.2.1: a chunk whose digest the store already
+  holds is not stored again) against a Python ``set`` walked chunk by chunk
+  over successive writes with planted repeats within and across writes, and
+  against closed forms: one digest written k times, a write repeated, a
+  write of an old version's digests followed by a new version's (duplicates
+  = the similarity count), the capacity refusal that changes nothing.
 """
 import hashlib
 import math
@@ -354,3 +360,98 @@ def test_edited_versions_are_mostly_similar_at_stride_1():
     _, eb, db = oracle.chunk(oracle.MD5, oracle.SHA1, newv, 20, 1, 0xFF, 0, 2048, 8)
     m, _ = oracle.similarity(oracle.SHA1, da, db)
     assert m / len(db) > 0.8
+
+
+# ------------------------------------------------------------- block map --
+def _planted_writes(seed, d, plan):
+    """Digests of successive writes: random rows, with repeats planted inside
+    a write and copies of rows written before; lengths random."""
+    rng = np.random.default_rng(seed)
+    written, out = [], []
+    for n, inner, cross in plan:
+        dig = rng.integers(0, 256, size=(n, d), dtype=np.uint8)
+        for _ in range(inner if n > 1 else 0):
+            i, j = sorted(rng.choice(n, size=2, replace=False).tolist())
+            dig[j] = dig[i]
+        if written and n:
+            pool = np.concatenate(written)
+            for j in rng.choice(n, size=min(cross, n), replace=False).tolist():
+                dig[j] = pool[int(rng.integers(0, len(pool)))]
+        lens = rng.integers(1, 100_000, size=n).astype(np.uint64)
+        out.append((dig, lens))
+        if n:
+            written.append(dig)
+    return out
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_blockmap_writes_vs_python_set(kind):
+    d = oracle.digest_size(kind)
+    plan = [(3000, 40, 0), (5000, 300, 400), (1, 0, 1), (0, 0, 0), (2, 0, 2), (8000, 800, 2000)]
+    bm = oracle.BlockMap(kind)
+    held = set()
+    for w, (dig, lens) in enumerate(_planted_writes(31 + kind, d, plan)):
+        exp = np.zeros(len(dig), dtype=bool)
+        for i, row in enumerate(dig):  # the store, one chunk at a time
+            key = row.tobytes()
+            exp[i] = key in held
+            held.add(key)
+        dup, c, b = bm.write(dig, lengths=lens)
+        assert np.array_equal(dup, exp), f"write {w}"
+        assert c == int(exp.sum()) and b == int(lens[exp].sum()), f"write {w}"
+        assert bm.size() == len(held), f"write {w}"
+    bm.close()
+
+
+def test_blockmap_closed_forms():
+    rng = np.random.default_rng(32)
+    one = rng.integers(0, 256, size=(1, 20), dtype=np.uint8)
+    lens = np.arange(1, 8, dtype=np.uint64)
+    bm = oracle.BlockMap(oracle.SHA1)
+    # one digest written 7 times: the first is stored, the rest are duplicates
+    dup, c, b = bm.write(np.repeat(one, 7, axis=0), lengths=lens)
+    assert dup.tolist() == [False] + [True] * 6 and (c, b) == (6, 27) and bm.size() == 1
+    # a write repeated: every chunk a duplicate, nothing added
+    a = rng.integers(0, 256, size=(400, 20), dtype=np.uint8)
+    la = rng.integers(1, 5000, size=400).astype(np.uint64)
+    dup, c, b = bm.write(a, lengths=la)
+    assert not dup.any() and bm.size() == 401
+    dup, c, b = bm.write(a, lengths=la)
+    assert dup.all() and (c, b) == (400, int(la.sum())) and bm.size() == 401
+    # ends instead of lengths
+    ends = np.cumsum(la)
+    assert bm.write(a, ends=ends)[2] == int(la.sum())
+    # an empty write changes nothing
+    assert bm.write(a[:0])[1:] == (0, 0) and bm.size() == 401
+    bm.close()
+
+
+def test_blockmap_new_version_duplicates_equal_similarity():
+    # Old version's chunks (all distinct) stored, then a new version with no
+    # repeats of its own: its duplicates are exactly the chunks the
+    # similarity lookup finds, by count and by bytes.
+    rng = np.random.default_rng(33)
+    a = rng.integers(0, 256, size=(600, 16), dtype=np.uint8)
+    b = rng.integers(0, 256, size=(500, 16), dtype=np.uint8)
+    pick = rng.choice(500, size=220, replace=False)
+    b[pick] = a[rng.choice(600, size=220, replace=False)]
+    lb = rng.integers(1, 9000, size=500).astype(np.uint64)
+    bm = oracle.BlockMap(oracle.MD5)
+    bm.write(a)
+    dup, c, by = bm.write(b, lengths=lb)
+    assert (c, by) == oracle.similarity(oracle.MD5, a, b, lb) == (220, int(lb[pick].sum()))
+    assert bm.size() == 600 + 280
+    bm.close()
+
+
+def test_blockmap_capacity_refusal_changes_nothing():
+    rng = np.random.default_rng(34)
+    a = rng.integers(0, 256, size=(60, 20), dtype=np.uint8)
+    bm = oracle.BlockMap(oracle.SHA1, capacity=100)
+    bm.write(a)
+    with pytest.raises(OverflowError):
+        bm.write(rng.integers(0, 256, size=(41, 20), dtype=np.uint8))
+    assert bm.size() == 60
+    dup, c, _ = bm.write(a[:40])  # size + n == capacity is accepted
+    assert dup.all() and c == 40 and bm.size() == 60
+    bm.close()

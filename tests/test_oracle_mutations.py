@@ -48,6 +48,13 @@ MUTATIONS = {
                             "if (max_chunk != 0 && next - last >= max_chunk) {"),
     "similarity_bytes_wrong_index": ("if (len_b) bytes += len_b[j];",
                                      "if (len_b) bytes += len_b[0];"),
+    "blockmap_repeat_in_write_missed": (
+        "const int repeat = k > 0 && memcmp(r[k - 1].dig, r[k].dig, (size_t)d) == 0;",
+        "const int repeat = 0;"),
+    "blockmap_held_not_checked": ("const int held = m->n && bsearch(", "const int held = 0 && bsearch("),
+    "blockmap_first_copy_marked": ("return a->idx < b->idx ? -1 : (a->idx > b->idx ? 1 : 0);",
+                                   "return a->idx > b->idx ? -1 : (a->idx < b->idx ? 1 : 0);"),
+    "blockmap_bytes_of_sorted_position": ("if (len) bytes += len[i];", "if (len) bytes += len[r[i].idx];"),
 }
 
 
@@ -72,6 +79,11 @@ def _pin_suite():
         pins.test_chunk_select_max_properties(seed)
     pins.test_chunk_select_max_reductions()
     pins.test_similarity_multiplicity_and_identity()
+    for kind in pins.KINDS:
+        pins.test_blockmap_writes_vs_python_set(kind)
+    pins.test_blockmap_closed_forms()
+    pins.test_blockmap_new_version_duplicates_equal_similarity()
+    pins.test_blockmap_capacity_refusal_changes_nothing()
 
 
 def _build_variant(src_text, tmpdir, name):
