@@ -15,19 +15,20 @@ Workload (one step = one pass of the whole path over one input):
       counted by chunks and by bytes.
   Input bytes are resident in HBM when the timed region starts.
 
-Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1): the
-second-level hash of a job is one sequential chain (for 4 KiB SHA-1 segments
-of 1 GiB it hashes 5 MiB in one lane, ~90 ms), and 1 MiB segments are 1024
-sequential chains per job.  Per step, chunking runs on stream SA[step % 5]
-(the window scan is the throughput engine; while one stream waits for its
-counts or runs its chunk digests, the others' window scans run) and the
-4 KiB / 64 KiB segments on stream SB; for a group of G = 32 steps, the 1 MiB
-segments run as one batched launch on stream S1 and all second levels as one
-batched launch on stream S2[group % 2], while the other streams carry on
-with the next group.  A step's latency therefore ends when its group's roots
-are done.  Ten busy streams need as many hardware queues: HIP shares its
-default four queues among all streams of the process, so the benchmark asks
-for eleven (GPU_MAX_HW_QUEUES, read when the HIP runtime starts).
+Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1):
+per step, chunking runs on stream SA[step % 5] (the window scan is the
+throughput engine; while one stream waits for its counts or runs its chunk
+digests, the others' window scans run), the 4 KiB / 64 KiB segments on
+stream SB, and the 1 MiB segments -- 2048 sequential chains that each take
+longer than a step -- on stream S1[step % 3], as the step's first launch.
+The second levels run on the host's cores, where the paper computes them
+(Sec. 3.2.2): a root worker thread takes the 4 KiB / 64 KiB jobs' digests
+as soon as their segments are done (while the 1 MiB chains still run), then
+the 1 MiB jobs' digests.  A step's latency ends when its last second level
+and its similarity are done.  The busy streams need as many hardware
+queues: HIP shares its default four among all streams of the process, so
+the benchmark asks for one per stream (GPU_MAX_HW_QUEUES, read when the HIP
+runtime starts).
 
 value = hashed bytes per second: each of the 7 primitive passes (6 direct
 hashes + chunking) consumes the 1 GiB input once, so a step hashes 7 GiB.
@@ -57,6 +58,9 @@ BLOCK_OPS = {0: 324, 1: 613}
 CHUNK_STREAMS = 5
 CHUNK_CALLS = "single"
 AHEAD = 8  # stages mode: steps queued ahead of the last finished chunking
+LONG_STREAMS = 3  # streams for the per-step 1 MiB segment launches (round-robin)
+ROOT_WORKERS = 2  # host threads (each with a stream) computing the second levels
+SLOTS = 10        # ring of per-step output buffers
 
 
 def padded_blocks(n):
@@ -67,8 +71,8 @@ def padded_blocks(n):
 # (digest, segment size); within a launch, jobs with the longest sequential
 # chains come first.
 BLOCK_JOBS = [(1, 64 * KiB), (0, 64 * KiB), (1, 4 * KiB), (0, 4 * KiB), (1, MiB), (0, MiB)]
-SHORT = [0, 1, 2, 3]   # indices of BLOCK_JOBS whose segments go in the per-step launch
-LONG = [4, 5]          # 1 MiB segments: batched per group
+SHORT = [0, 1, 2, 3]   # indices of BLOCK_JOBS whose segments go in the short-segment launch
+LONG = [4, 5]          # 1 MiB segments: a launch of their own
 ROOT_EARLY = [2, 3, 0, 1]  # second levels that need no 1 MiB segments, longest chain first
 ROOT_LATE = [4, 5]         # second levels of the 1 MiB jobs
 
@@ -78,7 +82,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=12)
-    ap.add_argument("--group", type=int, default=32, help="steps per long-chain batch")
+    ap.add_argument("--slots", type=int, default=SLOTS, help="ring of per-step output buffers (steps in flight)")
     ap.add_argument("--chunk-calls", choices=["single", "stages"], default=CHUNK_CALLS,
                     help="one hg_chunk per step (host threads wait on its counts), or the chunking "
                          "stages with device counts (window scans back to back on one stream)")
@@ -104,12 +108,11 @@ def parse():
 class Pipeline:
     """Buffers, job tables and streams of the pipelined step."""
 
-    def __init__(self, torch, hg, data, prev_digests, group):
+    def __init__(self, torch, hg, data, prev_digests, slots=SLOTS):
         self.torch, self.hg = torch, hg
         self.data = data
         self.prev = prev_digests
-        self.G = group
-        self.slots = 2 * group
+        self.slots = slots
         # Chunking goes round-robin over CHUNK_STREAMS streams so that one
         # step's counts, boundary decision and chunk digests overlap other
         # steps' window scans; the short segment batch has a stream of its
@@ -118,16 +121,17 @@ class Pipeline:
         self.staged = CHUNK_CALLS == "stages"
         self.sa = [torch.cuda.Stream() for _ in range(self.NA)]
         self.sb = torch.cuda.Stream()
-        self.s1 = torch.cuda.Stream()
-        # Second levels: two streams, alternating by group, so that the
-        # single-lane chains of consecutive groups (about 0.1 s for the 4 KiB
-        # SHA-1 one) overlap instead of queueing.
-        self.s2s = [torch.cuda.Stream(), torch.cuda.Stream()]
+        # 1 MiB segments: one launch per step, each lasting a whole 1 MiB
+        # chain (longer than a step), so consecutive steps' launches go
+        # round-robin over LONG_STREAMS streams and overlap.
+        self.s1 = [torch.cuda.Stream() for _ in range(LONG_STREAMS)]
+        # Second levels on the host: one stream and host thread per root
+        # worker (the call waits on the host for its digests).
+        self.sr = [torch.cuda.Stream() for _ in range(ROOT_WORKERS)]
         self.ctxa = [hg.Context(0) for _ in range(self.NA)]
         self.ctx0 = hg.Context(0)
-        self.ctx1 = hg.Context(0)
-        self.ctx2 = [hg.Context(0), hg.Context(0)]
-        self.ctx3 = hg.Context(0)
+        self.ctx1 = [hg.Context(0) for _ in range(LONG_STREAMS)]
+        self.ctxr = [hg.Context(0) for _ in range(ROOT_WORKERS)]
         dev = data.device
         n = data.numel()
         # Chunk outputs per chunking stream (capacity: every chunk but the last is
@@ -153,56 +157,75 @@ class Pipeline:
         self.digs = [torch.empty((self.cap, 20), dtype=torch.uint8, device=dev) for _ in range(self.NA)]
         self.nchunks = 0
         self.sim = torch.zeros((self.slots, 2), dtype=torch.int64, device=dev)
-        # Ring of segment-digest buffers and root outputs, one per slot.
+        # Ring of segment-digest buffers and root outputs, one per slot; the
+        # device job tables of the short and the long segments, and the host
+        # records of the early and the late second levels.
         self.recs = []
+        self.short_tables, self.long_tables, self.early, self.late = [], [], [], []
+        Job = hg.hg_block_job
         for slot in range(self.slots):
             specs = [(data, b, k) for k, b in BLOCK_JOBS]
             recs, leaves, roots = self.ctx0.batch_outputs(specs)
             self.recs.append((recs, leaves, roots))
-        Job = hg.hg_block_job
-        self.short_tables = [self.ctx0.device_job_table(self._subset(slot, SHORT))
-                             for slot in range(self.slots)]
-        self.long_tables, self.early_tables, self.late_tables = [], [], []
-
-        def table(ctx, recs):
-            return ctx.device_job_table((Job * len(recs))(*recs)), len(recs)
-        for parity in range(2):
-            slots = range(parity * group, parity * group + group)
-            self.long_tables.append(table(self.ctx1, [self.recs[s][0][j] for s in slots for j in LONG]))
-            self.early_tables.append(table(self.ctx2[parity], [self.recs[s][0][j] for j in ROOT_EARLY for s in slots]))
-            self.late_tables.append(table(self.ctx3, [self.recs[s][0][j] for j in ROOT_LATE for s in slots]))
-        self.group_done = {}
+            sub = lambda idx: (Job * len(idx))(*[recs[j] for j in idx])  # noqa: E731
+            self.short_tables.append(self.ctx0.device_job_table(sub(SHORT)))
+            self.long_tables.append(self.ctx0.device_job_table(sub(LONG)))
+            self.early.append(sub(ROOT_EARLY))
+            self.late.append(sub(ROOT_LATE))
         self.issue_ev = {}
         self.issue_ev_a = {}
         self.chunk_done = {}
+        self.root_done = {}
+        self.root_futs = {}
         # One host thread per chunking stream: hg_chunk waits on the host for
         # its candidate and chunk counts, and those waits must not hold up
-        # the other stream or the rest of the step.
+        # the other stream or the rest of the step.  Likewise one per root
+        # worker.
         from concurrent.futures import ThreadPoolExecutor
         self.pool = [ThreadPoolExecutor(1) for _ in range(self.NA)]
+        self.rpool = [ThreadPoolExecutor(1) for _ in range(ROOT_WORKERS)]
         self.futures = []
-
-    def _subset(self, slot, idx):
-        recs = self.recs[slot][0]
-        return (self.hg.hg_block_job * len(idx))(*[recs[i] for i in idx])
 
     def step(self, i):
         torch = self.torch
         slot = i % self.slots
-        g = i // self.G
-        if i % self.G == 0 and (g - 2) in self.group_done:
-            # Slots of group g were last read by group g-2's roots.
-            self.sb.wait_event(self.group_done[g - 2])
+        s1 = self.s1[i % LONG_STREAMS]
+        old = i - self.slots
+        if old in self.root_futs:
+            # The slot's buffers are free once step i - slots has its roots
+            # (the last work that reads them).
+            self.root_futs.pop(old).result()
+            ev = self.root_done[old]
+            s1.wait_event(ev)
+            self.sb.wait_event(ev)
         ev = torch.cuda.Event(enable_timing=True)
-        ev.record(self.sb)
+        ev.record(s1)
         self.issue_ev[i] = ev
+        self.ctx1[i % LONG_STREAMS].run_batch(self.long_tables[slot], len(LONG), "leaves", stream=s1)
+        long_done = torch.cuda.Event()
+        long_done.record(s1)
         self.ctx0.run_batch(self.short_tables[slot], len(SHORT), "leaves", stream=self.sb)
+        short_done = torch.cuda.Event()
+        short_done.record(self.sb)
+        r = i % ROOT_WORKERS
+        self.root_futs[i] = self.rpool[r].submit(self._roots, i, slot, r, short_done, long_done)
         if self.staged:
             self._chunk_stages(i, slot)
         else:
             self.futures.append(self.pool[i % self.NA].submit(self._chunk, i, slot))
-        if i % self.G == self.G - 1:
-            self.close_group(g)
+
+    def _roots(self, i, slot, r, short_done, long_done):
+        """Second levels of step i on the host (on root worker r's thread):
+        those of the 4 KiB / 64 KiB jobs as soon as their segments are done,
+        while the 1 MiB chains still run, then those of the 1 MiB jobs."""
+        sr, cr = self.sr[r], self.ctxr[r]
+        sr.wait_event(short_done)
+        cr.run_batch(self.early[slot], len(ROOT_EARLY), "roots", stream=sr, host_roots=True)
+        sr.wait_event(long_done)
+        cr.run_batch(self.late[slot], len(ROOT_LATE), "roots", stream=sr, host_roots=True)
+        done = self.torch.cuda.Event(enable_timing=True)
+        done.record(sr)
+        self.root_done[i] = done
 
     def _chunk(self, i, slot):
         """Chunking and similarity of step i (on its stream's thread)."""
@@ -248,30 +271,6 @@ class Pipeline:
         done.record(sa)
         self.chunk_done[i] = done
 
-    def close_group(self, g):
-        """Queue the long chains of group g: the 1 MiB segments on S1, then
-        (after them) their second levels; the other second levels on S2 as
-        soon as the group's short work is done."""
-        torch = self.torch
-        parity = g % 2
-        short_done = torch.cuda.Event()
-        short_done.record(self.sb)
-        s2 = self.s2s[parity]
-        self.s1.wait_event(short_done)
-        s2.wait_event(short_done)
-        lt, ln = self.long_tables[parity]
-        et, en = self.early_tables[parity]
-        zt, zn = self.late_tables[parity]
-        self.ctx2[parity].run_batch(et, en, "roots", stream=s2)
-        self.ctx1.run_batch(lt, ln, "leaves", stream=self.s1, background=True)
-        self.ctx3.run_batch(zt, zn, "roots", stream=self.s1)
-        s1_done = torch.cuda.Event()
-        s1_done.record(self.s1)
-        s2.wait_event(s1_done)
-        done = torch.cuda.Event(enable_timing=True)
-        done.record(s2)
-        self.group_done[g] = done
-
     def run(self, first, count):
         for i in range(first, first + count):
             if self.staged and i - AHEAD in self.chunk_done:
@@ -280,23 +279,22 @@ class Pipeline:
                 # as latency.
                 self.chunk_done[i - AHEAD].synchronize()
             self.step(i)
-        last = first + count - 1
-        if last % self.G != self.G - 1:
-            self.close_group(last // self.G)
         for f in self.futures:
             self.nchunks = f.result()
         self.futures.clear()
+        for i in sorted(self.root_futs):
+            self.root_futs.pop(i).result()
         if self.staged:
             self.torch.cuda.synchronize()
             counts = [int(c.item()) for c in self.nch]
             if any(c < 0 or c > self.cap for c in counts):
                 raise RuntimeError(f"a step's candidate list exceeded its room: chunk counts {counts}")
-            self.nchunks = counts[last % self.NA]
+            self.nchunks = counts[(first + count - 1) % self.NA]
 
     def close(self):
-        for p in self.pool:
+        for p in self.pool + self.rpool:
             p.shutdown()
-        ctxs = self.ctxa + [self.ctx0, self.ctx1, self.ctx3] + self.ctx2 + ([self.ctxw] if self.staged else [])
+        ctxs = self.ctxa + [self.ctx0] + self.ctx1 + self.ctxr + ([self.ctxw] if self.staged else [])
         for c in ctxs:
             c.close()
 
@@ -304,10 +302,10 @@ class Pipeline:
         out = []
         for i in range(first, first + count):
             # From the first of the step's launches to the later of its
-            # similarity and its group's last root.
+            # similarity and its last second level.
             t0 = self.issue_ev[i]
             start = min(0.0, t0.elapsed_time(self.issue_ev_a[i]))
-            end = max(t0.elapsed_time(self.group_done[i // self.G]), t0.elapsed_time(self.chunk_done[i]))
+            end = max(t0.elapsed_time(self.root_done[i]), t0.elapsed_time(self.chunk_done[i]))
             out.append(end - start)
         return out
 
@@ -820,7 +818,8 @@ def main():
         sys.exit(2)
     # Many concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
-    queues = max(8, args.chunk_streams + 6)  # chunking streams + window, SB, S1, two S2, default
+    # chunking streams + window + SB + S1 streams + root streams + default
+    queues = max(8, args.chunk_streams + 3 + LONG_STREAMS + ROOT_WORKERS)
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import numpy as np
@@ -863,7 +862,7 @@ def main():
     global CHUNK_STREAMS, CHUNK_CALLS
     CHUNK_STREAMS = args.chunk_streams
     CHUNK_CALLS = args.chunk_calls
-    pipe = Pipeline(torch, hg, data, prev_dig, args.group)
+    pipe = Pipeline(torch, hg, data, prev_dig, args.slots)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     pipe.run(0, args.warmup)
     torch.cuda.synchronize()
@@ -878,7 +877,7 @@ def main():
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    first = ((args.warmup + args.group - 1) // args.group) * args.group
+    first = args.warmup
     pipe.run(first, args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -934,15 +933,11 @@ def main():
                         "at 4 KiB/64 KiB/1 MiB segments with second level, content-based chunking "
                         "(MD5 w=20 s=1 low-12-bit boundary, min 2 KiB, SHA-1 chunk digests), "
                         "similarity vs previous version (1024 seeded 1-4 KiB edits)",
-            "input_bytes": GiB, "hashed_bytes_per_step": 7 * GiB, "group": args.group,
+            "input_bytes": GiB, "hashed_bytes_per_step": 7 * GiB, "slots": args.slots,
             "chunks_per_step": nchunks,
             "similarity_chunks": [int(sims[-1][0]), nchunks],
         },
         "input_GBps": round(GiB * args.steps / wall / 1e9, 2),
-        "latency_ms": {"step_p50": round(pct(lat, 50), 2), "step_p99": round(pct(lat, 99), 2)},
-        "step_alu": {"ops_per_step": int(step_ops),
-                     "achieved_Tops": round(step_ops / (wall / args.steps) / 1e12, 2),
-                     "frac": round(step_ops / (wall / args.steps) / 1e12 / INT32_PEAK_TOPS, 4)},
         "roofline": {"kernel": "window hash + tile count (MD5 w=20 s=1)", "bound": "alu",
                      "achieved": round(achieved, 2), "peak": round(INT32_PEAK_TOPS, 2),
                      "unit": "Tops/s (int32)", "frac": round(achieved / INT32_PEAK_TOPS, 4),
@@ -972,6 +967,12 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(data_np, prev_np, args.cpu_sample_mib)
+    # Last, so that they stay in view where only the end of the line is kept.
+    line["step_alu"] = {"ops_per_step": int(step_ops),
+                        "achieved_Tops": round(step_ops / (wall / args.steps) / 1e12, 2),
+                        "frac": round(step_ops / (wall / args.steps) / 1e12 / INT32_PEAK_TOPS, 4)}
+    line["latency_ms"] = {"step_p50": round(pct(lat, 50), 2), "step_p99": round(pct(lat, 99), 2),
+                          "value_GBps": round(value, 2), "ms_per_step": round(1e3 * wall / args.steps, 3)}
     print(json.dumps(line), flush=True)
 
 

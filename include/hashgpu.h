@@ -73,14 +73,16 @@ enum {
 };
 
 /* Flags.  HG_LEN_ENDS applies to hg_similarity and hg_blockmap_write only; HG_BACKGROUND to the
- * batch calls only; HG_COUNT_HOST to hg_chunk and the chunker's feed and finish only. */
+ * batch calls only; HG_COUNT_HOST to hg_chunk and the chunker's feed and finish only;
+ * HG_HOST_ROOTS to hg_roots_batch and hg_block_hash_batch only. */
 enum {
     HG_IN_DEVICE = 1u,
     HG_OUT_DEVICE = 2u,
     HG_ASYNC = 4u,
     HG_LEN_ENDS = 8u,
     HG_BACKGROUND = 16u,
-    HG_COUNT_HOST = 32u
+    HG_COUNT_HOST = 32u,
+    HG_HOST_ROOTS = 64u
 };
 
 /* Limits of the sliding-window primitive. */
@@ -107,6 +109,17 @@ int hg_last_error(const hg_ctx *ctx, char *buf, size_t n);
 /* Digest size in bytes: 16 for HG_MD5, 20 for HG_SHA1, HG_EINVAL otherwise. */
 int hg_digest_size(int digest);
 
+/* The standard digest of a host buffer, computed on the calling thread by
+ * the library's own sequential MD5 / SHA-1 for the host: the routine with
+ * which the host computes the last step of direct hashing (Sec. 3.2.2: the
+ * CPU hashes the buffer of segment digests into the final value).  in: len
+ * bytes of host memory (may be NULL when len is 0); out: digest_size bytes.
+ * Needs no context and no GPU.  SHA-1 uses the processor's SHA extensions
+ * when it has them (HG_HOST_SHA1_PORTABLE set in the environment when the
+ * library loads selects the portable code).  HG_EINVAL for an unknown
+ * digest or a NULL pointer. */
+int hg_host_hash(int digest, const void *in, uint64_t len, void *out);
+
 /* Pinned (page-locked) host memory from the context, for one-copy transfers
  * (Sec. 3.1: data handed to the GPU should already sit in non-pageable
  * memory, and such buffers should be allocated once and reused).  Freed by
@@ -129,14 +142,21 @@ int hg_host_free(hg_ctx *ctx, void *p);
  *               digests (for len = 0, the digest of the empty string); may be
  *               NULL.  At least one of leaf_out, root_out is required.
  * With a host `in` the block is streamed to the GPU in pieces through pinned
- * staging buffers, overlapping copies with hashing. */
+ * staging buffers, overlapping copies with hashing.
+ * The second level is computed on the host, as the paper places it
+ * (Sec. 3.2.2: the CPU hashes the buffer of segment digests), when the
+ * digest buffer holds at least 16 KiB: the segment digests are copied back
+ * and the call waits for them on the host even with HG_ASYNC (which then
+ * only leaves the root's copy to a device root_out enqueued).  A smaller
+ * second level runs in one GPU lane and needs no host wait. */
 int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, int digest,
                   void *leaf_out, void *root_out, uint32_t flags, void *stream);
 
 /* Both digests in one pass over the input: the MD5 and the SHA-1 direct
  * hash of the block (the same segments; each byte is read once).  Equal to
  * hg_block_hash with HG_MD5 and with HG_SHA1.  Outputs as there; each may
- * be NULL, not all four. */
+ * be NULL, not all four.  Second levels as for hg_block_hash (the two host
+ * ones run at once). */
 int hg_block_hash_dual(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size, void *md5_leaf_out,
                        void *md5_root_out, void *sha1_leaf_out, void *sha1_root_out, uint32_t flags,
                        void *stream);
@@ -173,8 +193,14 @@ int hg_leaves_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint
 /* Second level of every job whose root_out is not NULL: root_out receives
  * the digest of the job's leaf_out buffer (ceil(len/B) digests), as
  * hg_block_hash does.  Reads leaf_out, so it must be ordered after the
- * hg_leaves_batch call that wrote it.  One lane per job.  Arguments as for
- * hg_leaves_batch. */
+ * hg_leaves_batch call that wrote it.  One GPU lane per job (many small
+ * second levels).  Arguments as for hg_leaves_batch.
+ * With HG_HOST_ROOTS (host job table only) the second levels run on the
+ * host's cores instead, where the paper computes them (Sec. 3.2.2; a few
+ * long second levels): the call copies every job's segment digests back,
+ * waits for them on the host, hashes them on the library's host threads
+ * (longest first), and copies the roots to their root_out pointers on
+ * `stream`; with HG_ASYNC it returns once those copies are enqueued. */
 int hg_roots_batch(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags,
                    void *stream);
 

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhashgpu.so")
 
-SOURCES = ["hashgpu.cpp", "server.cpp", "block_hash.hip", "window_scan.hip", "chunk.hip", "batch.hip", "files.hip", "probe.hip", "blockmap.hip"]
+SOURCES = ["hashgpu.cpp", "server.cpp", "block_hash.hip", "window_scan.hip", "chunk.hip", "batch.hip", "files.hip", "probe.hip", "blockmap.hip", "host_hash.cpp"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

@@ -338,6 +338,25 @@ __global__ __launch_bounds__(64) void roots_batch_kernel(const hg_block_job *__r
     else root_lane<KIND_SHA1>(j);
 }
 
+// Second levels computed elsewhere (on the host): root j of `roots` (20-byte
+// records by job index) goes to jobs[j].root_out, one lane per job.
+__global__ __launch_bounds__(256) void roots_scatter_kernel(const hg_block_job *__restrict__ jobs, uint32_t n_jobs,
+                                                            const uint8_t *__restrict__ roots) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_jobs) return;
+    const hg_block_job j = jobs[i];
+    if (!j.root_out) return;
+    const int d = j.digest == KIND_MD5 ? 16 : 20;
+    uint8_t *out = (uint8_t *)j.root_out;
+    for (int b = 0; b < d; b++) out[b] = roots[20ull * i + b];
+}
+
+hipError_t launch_roots_scatter(const hg_block_job *jobs, uint32_t n_jobs, const uint8_t *roots, hipStream_t s) {
+    if (n_jobs == 0) return hipSuccess;
+    roots_scatter_kernel<<<(n_jobs + 255) / 256, 256, 0, s>>>(jobs, n_jobs, roots);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *plan, hipStream_t s) {
     batch_plan_kernel<<<1, PLAN_TPB, 0, s>>>(jobs, n_jobs, (Plan *)plan);
     return hipGetLastError();

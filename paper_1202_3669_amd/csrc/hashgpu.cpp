@@ -22,6 +22,7 @@
 
 #include "hashgpu.h"
 #include "hg_internal.hpp"
+#include "host_hash.hpp"
 
 namespace {
 
@@ -44,6 +45,7 @@ enum Slot {
     SLOT_SMALL,    // counts and counters
     SLOT_AUX,      // shifted candidate starts (streaming chunker)
     SLOT_TLEAF,    // segment digests of two-level chunk digests
+    SLOT_ROOTS,    // second levels computed on the host, on their way to root_out
     N_SLOTS
 };
 
@@ -53,6 +55,11 @@ constexpr size_t STAGE_PIECE = 64ull << 20;  // bytes per pinned staging buffer
 // staging buffers: each piece's launch lasts as long as a segment's chain,
 // so fewer, larger pieces are faster there.)
 constexpr size_t SCAN_PIECE = 16ull << 20;
+// Segment-digest bytes from which the second level of hg_block_hash runs on
+// the host (Sec. 3.2.2 computes it there): one sequential chain, which a
+// CPU core runs 10-40x faster than one GPU lane.  Below this, a lane is
+// about as quick and the call needs no host wait for it.
+constexpr uint64_t HOST_ROOT_MIN = 16u << 10;
 
 struct DevBuf {
     void *p = nullptr;
@@ -77,6 +84,12 @@ struct hg_ctx {
     hipEvent_t piece_ready = nullptr;
     hipStream_t copy_stream = nullptr;
     std::unordered_set<void *> host_allocs;
+    // Second levels computed on the host: pinned memory for the segment
+    // digests copied back and for the roots sent to device outputs, and an
+    // event after the last copy out of it.
+    uint8_t *hstep = nullptr;
+    size_t hstep_bytes = 0;
+    hipEvent_t hstep_free = nullptr;
     // Kernel timing (hg_timing_*).
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -368,6 +381,66 @@ int copy_out(hg_ctx *ctx, void *dst, const void *src, size_t n, bool dst_device,
     return HG_OK;
 }
 
+// Pinned memory for the host's second levels: `roots` bytes for root
+// outputs followed by `digests` bytes of segment digests.  Waits until the
+// copies out of it that earlier calls enqueued have finished.
+int host_step_buffer(hg_ctx *ctx, size_t roots, size_t digests, uint8_t **r, uint8_t **dg) {
+    roots = (roots + 255) & ~(size_t)255;
+    const size_t want = roots + digests;
+    if (!ctx->hstep_free) HG_HIP(ctx, hipEventCreateWithFlags(&ctx->hstep_free, hipEventDisableTiming));
+    else HG_HIP(ctx, hipEventSynchronize(ctx->hstep_free));
+    if (ctx->hstep_bytes < want) {
+        if (ctx->hstep) HG_HIP(ctx, hipHostFree(ctx->hstep));
+        ctx->hstep = nullptr;
+        ctx->hstep_bytes = 0;
+        size_t sz = std::max(want, (size_t)1 << 20);
+        sz = (sz + ((1u << 20) - 1)) & ~(size_t)((1u << 20) - 1);
+        hipError_t e = hipHostMalloc((void **)&ctx->hstep, sz, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->hstep = nullptr;
+            return fail(ctx, HG_ENOMEM, "pinned allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
+        }
+        ctx->hstep_bytes = sz;
+    }
+    *r = ctx->hstep;
+    *dg = ctx->hstep + roots;
+    return HG_OK;
+}
+
+// One second level computed on the host.
+struct HostRoot {
+    int kind;
+    const uint8_t *digests;  // device pointer, or host pointer when on_host
+    uint64_t bytes;
+    bool on_host;
+    uint8_t *out;            // host: d bytes
+};
+
+// The second levels of `roots` on the host's cores (Sec. 3.2.2): device
+// digest buffers are copied back into `stage` (room for all of them) on st,
+// the stream is synchronized, and the pool hashes the buffers, longest first.
+int host_roots(hg_ctx *ctx, HostRoot *roots, size_t n, uint8_t *stage, hipStream_t st) {
+    uint64_t off = 0;
+    for (size_t i = 0; i < n; i++) {
+        if (roots[i].on_host || roots[i].bytes == 0) continue;
+        HG_HIP(ctx, hipMemcpyAsync(stage + off, roots[i].digests, roots[i].bytes, hipMemcpyDeviceToHost, st));
+        roots[i].digests = stage + off;
+        roots[i].on_host = true;
+        off += roots[i].bytes;
+    }
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    std::vector<size_t> order(n);
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return roots[a].bytes > roots[b].bytes; });
+    hg::host::parallel_for(n, [&](uint64_t k) {
+        const HostRoot &r = roots[order[k]];
+        hg::host::digest(r.kind, r.digests, r.bytes, r.out);
+    });
+    return HG_OK;
+}
+
 // Digests of the chunks [ends[j-1], ends[j]) of in[0, len) (*n_dev <= max_n
 // of them): the standard digest of each chunk's bytes, or with chunk_segment
 // the two-level direct hash of each chunk.
@@ -417,6 +490,12 @@ const char *hg_strerror(int status) {
         case HG_EBUSY: return "busy";
         default: return "unknown status";
     }
+}
+
+int hg_host_hash(int digest, const void *in, uint64_t len, void *out) {
+    if (digest_bytes(digest) < 0 || !out || (len && !in)) return HG_EINVAL;
+    hg::host::digest(digest, (const uint8_t *)in, len, (uint8_t *)out);
+    return HG_OK;
 }
 
 int hg_digest_size(int digest) {
@@ -475,6 +554,8 @@ void hg_destroy(hg_ctx *ctx) {
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+    if (ctx->hstep) (void)hipHostFree(ctx->hstep);
+    if (ctx->hstep_free) (void)hipEventDestroy(ctx->hstep_free);
     if (ctx->piece_ready) (void)hipEventDestroy(ctx->piece_ready);
     if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     delete ctx;
@@ -548,9 +629,23 @@ int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size
                              return HG_OK;
                          }));
     }
-    if (root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(digest, leaves, n * (uint64_t)d, root, st));
-    if (leaf_out && !out_dev) HG_TRY(copy_out(ctx, leaf_out, leaves, n * (uint64_t)d, false, st));
-    if (root_out && !out_dev) HG_TRY(copy_out(ctx, root_out, root, (size_t)d, false, st));
+    const uint64_t dbytes = n * (uint64_t)d;
+    if (leaf_out && !out_dev) HG_TRY(copy_out(ctx, leaf_out, leaves, dbytes, false, st));
+    if (root_out && dbytes >= HOST_ROOT_MIN) {
+        // The second level on the host: it waits for the segment digests.
+        uint8_t *hr, *hd;
+        HG_TRY(host_step_buffer(ctx, 64, leaf_out && !out_dev ? 0 : dbytes, &hr, &hd));
+        const bool have = leaf_out && !out_dev;
+        HostRoot r{digest, have ? (const uint8_t *)leaf_out : leaves, dbytes, have, out_dev ? hr : (uint8_t *)root_out};
+        HG_TRY(host_roots(ctx, &r, 1, hd, st));
+        if (out_dev) {
+            HG_HIP(ctx, hipMemcpyAsync(root_out, hr, (size_t)d, hipMemcpyHostToDevice, st));
+            HG_HIP(ctx, hipEventRecord(ctx->hstep_free, st));
+        }
+    } else if (root_out) {
+        HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(digest, leaves, dbytes, root, st));
+        if (!out_dev) HG_TRY(copy_out(ctx, root_out, root, (size_t)d, false, st));
+    }
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return HG_OK;
 }
@@ -600,12 +695,46 @@ int hg_block_hash_dual(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block
                              return HG_OK;
                          }));
     }
-    if (md5_root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(HG_MD5, lm, n * 16, rm, st));
-    if (sha1_root_out) HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(HG_SHA1, ls, n * 20, rs, st));
     if (md5_leaf_out && !out_dev) HG_TRY(copy_out(ctx, md5_leaf_out, lm, n * 16, false, st));
     if (sha1_leaf_out && !out_dev) HG_TRY(copy_out(ctx, sha1_leaf_out, ls, n * 20, false, st));
-    if (md5_root_out && !out_dev) HG_TRY(copy_out(ctx, md5_root_out, rm, 16, false, st));
-    if (sha1_root_out && !out_dev) HG_TRY(copy_out(ctx, sha1_root_out, rs, 20, false, st));
+    // Second levels: on the host (both at once on the pool) when the digest
+    // buffers are large, else one GPU lane each.
+    void *const rout[2] = {md5_root_out, sha1_root_out};
+    void *const lout[2] = {md5_leaf_out, sha1_leaf_out};
+    const uint8_t *const lv[2] = {lm, ls};
+    uint8_t *const rdev[2] = {rm, rs};
+    HostRoot hr_[2];
+    size_t nh = 0, stage_bytes = 0;
+    for (int k = 0; k < 2; k++) {
+        if (!rout[k]) continue;
+        const int dk = k ? 20 : 16;
+        const uint64_t db = n * (uint64_t)dk;
+        if (db >= HOST_ROOT_MIN) {
+            const bool have = lout[k] && !out_dev;
+            hr_[nh++] = HostRoot{k ? HG_SHA1 : HG_MD5, have ? (const uint8_t *)lout[k] : lv[k], db, have,
+                                 (uint8_t *)rout[k]};
+            if (!have) stage_bytes += db;
+        } else {
+            HG_LAUNCH(ctx, HG_K_ROOT, st, hg::launch_hash_one(k ? HG_SHA1 : HG_MD5, lv[k], db, rdev[k], st));
+            if (!out_dev) HG_TRY(copy_out(ctx, rout[k], rdev[k], (size_t)dk, false, st));
+        }
+    }
+    if (nh) {
+        uint8_t *hr, *hd;
+        HG_TRY(host_step_buffer(ctx, 64, stage_bytes, &hr, &hd));
+        uint8_t *dst[2];
+        for (size_t i = 0; i < nh; i++) {
+            dst[i] = hr_[i].out;
+            if (out_dev) hr_[i].out = hr + 32 * i;
+        }
+        HG_TRY(host_roots(ctx, hr_, nh, hd, st));
+        if (out_dev) {
+            for (size_t i = 0; i < nh; i++)
+                HG_HIP(ctx, hipMemcpyAsync(dst[i], hr + 32 * i, (size_t)digest_bytes(hr_[i].kind),
+                                           hipMemcpyHostToDevice, st));
+            HG_HIP(ctx, hipEventRecord(ctx->hstep_free, st));
+        }
+    }
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return HG_OK;
 }
@@ -618,11 +747,14 @@ namespace {
 int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t flags, void *stream,
                bool leaves, bool roots) {
     HG_TRY(enter(ctx));
-    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC | HG_BACKGROUND))
+    if (flags & ~(uint32_t)(HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC | HG_BACKGROUND | HG_HOST_ROOTS))
         return fail(ctx, HG_EINVAL, "unknown flag bits 0x%x", flags);
     const bool boost = !(flags & HG_BACKGROUND);
-    if ((flags & HG_ASYNC) && !(flags & HG_IN_DEVICE))
-        return fail(ctx, HG_EINVAL, "HG_ASYNC requires a device job table (HG_IN_DEVICE)");
+    const bool on_host = flags & HG_HOST_ROOTS;
+    if (on_host && !roots) return fail(ctx, HG_EINVAL, "HG_HOST_ROOTS applies to calls with second levels");
+    if (on_host && (flags & HG_IN_DEVICE)) return fail(ctx, HG_EINVAL, "HG_HOST_ROOTS needs a host job table");
+    if ((flags & HG_ASYNC) && !(flags & HG_IN_DEVICE) && !on_host)
+        return fail(ctx, HG_EINVAL, "HG_ASYNC requires a device job table (HG_IN_DEVICE) or HG_HOST_ROOTS");
     if (n_jobs == 0) return HG_OK;
     if (!jobs) return fail(ctx, HG_EINVAL, "jobs is NULL");
     hipStream_t st = (hipStream_t)stream;
@@ -643,9 +775,11 @@ int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t 
         HG_HIP(ctx, hipMemcpyAsync(d, jobs, (size_t)n_jobs * sizeof(hg_block_job), hipMemcpyHostToDevice, st));
         djobs = (const hg_block_job *)d;
     }
-    void *plan;
-    HG_TRY(ensure(ctx, SLOT_PLAN, hg::batch_plan_bytes(n_jobs), st, &plan));
-    HG_HIP(ctx, hg::launch_batch_plan(djobs, n_jobs, plan, st));
+    void *plan = nullptr;
+    if (leaves || !on_host) {
+        HG_TRY(ensure(ctx, SLOT_PLAN, hg::batch_plan_bytes(n_jobs), st, &plan));
+        HG_HIP(ctx, hg::launch_batch_plan(djobs, n_jobs, plan, st));
+    }
     if (leaves) {
         // A persistent grid of up to 8192 wavefronts (8 per CU) in 128-lane
         // workgroups; fewer when the host knows there are fewer segments.
@@ -657,7 +791,35 @@ int batch_call(hg_ctx *ctx, const hg_block_job *jobs, uint32_t n_jobs, uint32_t 
         if (host_table) grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(grid, (total_leaves + 63) / 64 + 1));
         HG_LAUNCH(ctx, HG_K_LEAVES_BATCH, st, hg::launch_leaves_batch(djobs, n_jobs, plan, grid, 2, boost, st));
     }
-    if (roots) HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, boost, st));
+    if (roots && on_host) {
+        // The second levels on the host's cores (Sec. 3.2.2): the digest
+        // buffers come back, the pool hashes them, longest first, and the
+        // roots go to their root_out pointers through one copy and a scatter.
+        std::vector<HostRoot> hr;
+        uint64_t stage_bytes = 0;
+        for (uint32_t i = 0; i < n_jobs; i++) {
+            const hg_block_job &j = jobs[i];
+            if (!j.root_out) continue;
+            const uint64_t bytes = (j.len ? (j.len + j.block_size - 1) / j.block_size : 0) *
+                                   (uint64_t)digest_bytes(j.digest);
+            hr.push_back(HostRoot{j.digest, (const uint8_t *)j.leaf_out, bytes, false, nullptr});
+            stage_bytes += bytes;
+        }
+        if (!hr.empty()) {
+            uint8_t *hroots, *hd;
+            HG_TRY(host_step_buffer(ctx, (size_t)n_jobs * 20, stage_bytes, &hroots, &hd));
+            for (uint32_t i = 0, k = 0; i < n_jobs; i++)
+                if (jobs[i].root_out) hr[k++].out = hroots + 20ull * i;
+            HG_TRY(host_roots(ctx, hr.data(), hr.size(), hd, st));
+            void *droots;
+            HG_TRY(ensure(ctx, SLOT_ROOTS, (size_t)n_jobs * 20, st, &droots));
+            HG_HIP(ctx, hipMemcpyAsync(droots, hroots, (size_t)n_jobs * 20, hipMemcpyHostToDevice, st));
+            HG_HIP(ctx, hipEventRecord(ctx->hstep_free, st));
+            HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_scatter(djobs, n_jobs, (const uint8_t *)droots, st));
+        }
+    } else if (roots) {
+        HG_LAUNCH(ctx, HG_K_ROOTS_BATCH, st, hg::launch_roots_batch(djobs, n_jobs, plan, boost, st));
+    }
     if (!(flags & HG_ASYNC)) HG_HIP(ctx, hipStreamSynchronize(st));
     return HG_OK;
 }

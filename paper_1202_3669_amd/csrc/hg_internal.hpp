@@ -208,6 +208,9 @@ hipError_t launch_batch_plan(const hg_block_job *jobs, uint32_t n_jobs, void *pl
 hipError_t launch_leaves_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, uint32_t waves,
                                uint32_t wg_waves, bool boost, hipStream_t s);
 hipError_t launch_roots_batch(const hg_block_job *jobs, uint32_t n_jobs, void *plan, bool boost, hipStream_t s);
+// Copies root j (20-byte records of `roots`, by job index) to jobs[j].root_out
+// for every job with a root_out (second levels computed on the host).
+hipError_t launch_roots_scatter(const hg_block_job *jobs, uint32_t n_jobs, const uint8_t *roots, hipStream_t s);
 
 // ----------------------------------------------------------- similarity --
 // Open-addressing set of A's digests (table of 2^log2_slots uint32 slots),

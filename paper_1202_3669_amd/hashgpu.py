@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 HG_MD5, HG_SHA1 = 0, 1
 HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
 HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS, HG_BACKGROUND, HG_COUNT_HOST = 1, 2, 4, 8, 16, 32
+HG_HOST_ROOTS = 64
 HG_MAX_WINDOW = 4096
 DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
 
@@ -94,6 +95,7 @@ hg_destroy = _declare("hg_destroy", None, [_vp])
 hg_strerror = _declare("hg_strerror", ctypes.c_char_p, [_int])
 hg_last_error = _declare("hg_last_error", _int, [_vp, ctypes.c_char_p, ctypes.c_size_t])
 hg_digest_size = _declare("hg_digest_size", _int, [_int])
+hg_host_hash = _declare("hg_host_hash", _int, [_int, _vp, _u64, _vp])
 hg_host_alloc = _declare("hg_host_alloc", _int, [_vp, ctypes.c_size_t, ctypes.POINTER(_vp)])
 hg_host_free = _declare("hg_host_free", _int, [_vp, _vp])
 hg_block_hash = _declare("hg_block_hash", _int, [_vp, _vp, _u64, _u64, _int, _vp, _vp, _u32, _vp])
@@ -164,7 +166,20 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
             "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset", "hg_blockmap_create",
             "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write", "hg_chunk_select",
-            "hg_chunk_digests", "hg_similarity_n"]
+            "hg_chunk_digests", "hg_similarity_n", "hg_host_hash"]
+
+
+def host_hash(digest: int, data) -> bytes:
+    """The library's host-side standard digest of a bytes-like object or
+    uint8 numpy array (hg_host_hash; no context, no GPU)."""
+    import numpy as np
+    buf = np.frombuffer(bytes(data), dtype=np.uint8) if isinstance(data, (bytes, bytearray, memoryview)) \
+        else np.ascontiguousarray(data, dtype=np.uint8).reshape(-1)
+    out = (ctypes.c_uint8 * 20)()
+    st = hg_host_hash(digest, buf.ctypes.data if buf.size else None, buf.size, ctypes.addressof(out))
+    if st != HG_OK:
+        raise HashGpuError(st, "hg_host_hash failed")
+    return bytes(out)[:hg_digest_size(digest)]
 
 
 class HashGpuError(RuntimeError):
@@ -518,15 +533,21 @@ class Context:
 
     @_on_stream
     def run_batch(self, table, n_jobs: int, which: str = "both", asynchronous: bool = True,
-                  stream=None, background: bool = False):
-        """Run a device job table (from device_job_table): which in
-        {"leaves", "roots", "both"}."""
+                  stream=None, background: bool = False, host_roots: bool = False):
+        """Run a job table: a device table (from device_job_table) or the
+        host records themselves (from batch_outputs); which in {"leaves",
+        "roots", "both"}.  host_roots (host table only): the second levels
+        on the host's cores (HG_HOST_ROOTS)."""
         fn = {"leaves": hg_leaves_batch, "roots": hg_roots_batch,
               "both": hg_block_hash_batch}[which]
-        flags = HG_IN_DEVICE | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
+        on_dev = hasattr(table, "data_ptr")
+        flags = (HG_IN_DEVICE if on_dev else 0) | HG_OUT_DEVICE | (HG_ASYNC if asynchronous else 0)
         if background:
             flags |= HG_BACKGROUND
-        self._check(fn(self.handle, table.data_ptr(), n_jobs, flags, _stream_handle(stream)))
+        if host_roots:
+            flags |= HG_HOST_ROOTS
+        ptr = table.data_ptr() if on_dev else ctypes.addressof(table)
+        self._check(fn(self.handle, ptr, n_jobs, flags, _stream_handle(stream)))
 
     @_on_stream
     def similarity(self, dig_a, dig_b, len_b=None, digest: int = HG_SHA1, stream=None,

@@ -1,7 +1,8 @@
 """GPU parity of the timed step itself: bench.py's pipeline (the 1 GiB
 input, seed 2, resident in HBM; six direct hashes through the persistent
-job tables with the 1 MiB chains batched per group, chunking round-robin
-over its chunking streams, similarity against the previous version's digests) run for more
+job tables, the 1 MiB segments in a launch of their own per step, the
+second levels on the host's cores, chunking round-robin over its chunking
+streams, similarity against the previous version's digests) run for more
 steps than its ring of output slots holds, in both chunking modes.  Every
 slot's segment digests and second levels, the chunk ends and digests of
 each chunking stream and every step's similarity equal the oracle's,
@@ -53,13 +54,13 @@ def workload():
     return data, prev_dig, ends, dig, sim, leaves, roots
 
 
-@pytest.mark.parametrize("mode,group,steps", [("single", 32, 67), ("stages", 4, 11)])
-def test_pipeline_step_outputs(hg, workload, monkeypatch, mode, group, steps):
+@pytest.mark.parametrize("mode,slots,steps", [("single", 10, 23), ("stages", 4, 11)])
+def test_pipeline_step_outputs(hg, workload, monkeypatch, mode, slots, steps):
     data_np, prev_dig, ends, dig, sim, leaves, roots = workload
     monkeypatch.setattr(bench, "CHUNK_CALLS", mode)
-    note(f"bench pipeline mode={mode} group={group} steps={steps}")
+    note(f"bench pipeline mode={mode} slots={slots} steps={steps}")
     data = torch.from_numpy(data_np).cuda()
-    pipe = bench.Pipeline(torch, hg, data, torch.from_numpy(prev_dig).cuda(), group)
+    pipe = bench.Pipeline(torch, hg, data, torch.from_numpy(prev_dig).cuda(), slots)
     pipe.sim.fill_(-1)
     torch.cuda.synchronize()
     pipe.run(0, steps)
