@@ -57,7 +57,7 @@ BLOCK_OPS = {0: 324, 1: 613}
 # Chunking streams (steps round-robin), each driven by its own host thread.
 CHUNK_STREAMS = 5
 CHUNK_CALLS = "single"
-AHEAD = 8  # stages mode: steps queued ahead of the last finished chunking
+AHEAD = 12  # steps issued ahead of the last finished chunking
 LONG_STREAMS = 3  # streams for the per-step 1 MiB segment launches (round-robin)
 ROOT_WORKERS = 2  # host threads (each with a stream) computing the second levels
 SLOTS = 10        # ring of per-step output buffers
@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=96)
     ap.add_argument("--warmup", type=int, default=12)
     ap.add_argument("--slots", type=int, default=SLOTS, help="ring of per-step output buffers (steps in flight)")
+    ap.add_argument("--ahead", type=int, default=AHEAD, help="steps issued ahead of the last finished chunking")
     ap.add_argument("--chunk-calls", choices=["single", "stages"], default=CHUNK_CALLS,
                     help="one hg_chunk per step (host threads wait on its counts), or the chunking "
                          "stages with device counts (window scans back to back on one stream)")
@@ -273,10 +274,11 @@ class Pipeline:
 
     def run(self, first, count):
         for i in range(first, first + count):
-            if self.staged and i - AHEAD in self.chunk_done:
-                # Bounded run-ahead: nothing here waits on the host otherwise,
-                # and a step queued far behind the GPU would count its queueing
-                # as latency.
+            # Bounded run-ahead: without it the host queues steps far ahead
+            # of the GPU, and a step's time in that queue counts as latency.
+            if not self.staged and i - AHEAD >= first:
+                self.futures[i - AHEAD - first].result()
+            if i - AHEAD in self.chunk_done:
                 self.chunk_done[i - AHEAD].synchronize()
             self.step(i)
         for f in self.futures:
@@ -536,11 +538,20 @@ def breakdown(torch, hg, data, host_pinned):
     ts = timed(lambda: ctx.chunk(host_pinned, 20, 1, 0xFFF, 0, 2 * KiB), reps=3)
     res["chunk_s1_with_h2d"] = {"GBps": round(n / statistics.median(ts) / 1e6, 1),
                                 "ms_p50": round(pct(ts, 50), 2)}
-    for k in (0, 1):
-        ts = timed(lambda: ctx.block_hash(host_pinned, 64 * KiB, k, root=False), reps=5)
-        res[f"{'sha1' if k else 'md5'}_64k_with_h2d"] = {
-            "GBps": round(n / statistics.median(ts) / 1e6, 1),
-            "ms_p50": round(pct(ts, 50), 2), "ms_p99": round(pct(ts, 99), 2)}
+    # Segment digests of the pinned host copy (host-to-device included), at
+    # every segment size, each digest and both in one pass; and the same
+    # with the second level.
+    for b in (4 * KiB, 64 * KiB, MiB):
+        for k in (0, 1):
+            ts = timed(lambda: ctx.block_hash(host_pinned, b, k, root=False), reps=5)
+            tr = timed(lambda: ctx.block_hash(host_pinned, b, k), reps=5)
+            res[f"{'sha1' if k else 'md5'}_{b // KiB}k_with_h2d"] = {
+                "GBps": round(n / statistics.median(ts) / 1e6, 1),
+                "ms_p50": round(pct(ts, 50), 2), "ms_p99": round(pct(ts, 99), 2),
+                "with_root_ms_p50": round(pct(tr, 50), 2), "with_root_ms_p99": round(pct(tr, 99), 2)}
+        ts = timed(lambda: ctx.block_hash_dual(host_pinned, b, root=False), reps=5)
+        res[f"md5+sha1_{b // KiB}k_with_h2d"] = {"GBps": round(n / statistics.median(ts) / 1e6, 1),
+                                                 "ms_p50": round(pct(ts, 50), 2)}
     # Measured ceilings beside the data-sheet ones.
     res["probes"] = {"int32_Tops_measured": round(ctx.probe_alu(), 2), "int32_Tops_spec": round(INT32_PEAK_TOPS, 2),
                      "hbm_read_GBps_measured": round(ctx.probe_read(data), 1), "hbm_GBps_spec": 8000.0}
@@ -859,9 +870,10 @@ def main():
     del prev
     torch.cuda.synchronize()
 
-    global CHUNK_STREAMS, CHUNK_CALLS
+    global CHUNK_STREAMS, CHUNK_CALLS, AHEAD
     CHUNK_STREAMS = args.chunk_streams
     CHUNK_CALLS = args.chunk_calls
+    AHEAD = args.ahead
     pipe = Pipeline(torch, hg, data, prev_dig, args.slots)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     pipe.run(0, args.warmup)

@@ -92,8 +92,36 @@ enum { HG_MAX_WINDOW = 4096 };
 
 /* Creates a context on HIP device `device` (that device becomes current for
  * the calling thread).  Returns HG_EDEVICE if the device does not exist or
- * is not a gfx950 GPU.  *out receives the context. */
-int hg_create(int device, hg_ctx **out);
+ * is not a gfx950 GPU, HG_ENOMEM if a pool cannot be allocated.  *out
+ * receives the context.  The paper's buffer reuse (Sec. 3.1: buffers are
+ * allocated once and reused; Sec. 3.2.3: a queue of pre-allocated buffers):
+ *   device_pool_bytes  0: the scratch of the calls on this context is
+ *                      allocated when a call first needs it and reused (and
+ *                      grown) by later calls.  > 0: one device region of that
+ *                      size is allocated now and all call scratch is carved
+ *                      from it (first fit, 64 KiB units); a call whose
+ *                      scratch does not fit fails with HG_ENOMEM, and calls
+ *                      allocate no device memory.  (Batches, chunkers and
+ *                      block maps allocate their own memory when created.)
+ *   pinned_pool_bytes  0: hg_host_alloc allocates pinned memory per call.
+ *                      > 0: one pinned region of that size is allocated now
+ *                      and hg_host_alloc carves from it (first fit, 256-byte
+ *                      units), HG_ENOMEM when no free range is large enough.
+ *                      (The context's own staging for pageable input is
+ *                      separate.) */
+int hg_create(int device, size_t device_pool_bytes, size_t pinned_pool_bytes, hg_ctx **out);
+
+/* Pool use and allocation counts of a context, e.g. to check that a
+ * steady-state loop allocates nothing. */
+typedef struct {
+    uint64_t device_pool_bytes, device_pool_used;  /* 0, 0 without a device pool */
+    uint64_t pinned_pool_bytes, pinned_pool_used;  /* 0, 0 without a pinned pool */
+    uint64_t device_allocs;  /* device allocations the context has made (the pool counts once) */
+    uint64_t pinned_allocs;  /* pinned host allocations the context has made (pool, staging,
+                                hg_host_alloc without a pool) */
+    uint64_t host_blocks;    /* hg_host_alloc blocks not yet freed */
+} hg_ctx_stats;
+int hg_ctx_stats_read(const hg_ctx *ctx, hg_ctx_stats *out);
 
 /* Synchronizes the context's work and frees everything it owns.  NULL is a
  * no-op. */
@@ -122,8 +150,13 @@ int hg_host_hash(int digest, const void *in, uint64_t len, void *out);
 
 /* Pinned (page-locked) host memory from the context, for one-copy transfers
  * (Sec. 3.1: data handed to the GPU should already sit in non-pageable
- * memory, and such buffers should be allocated once and reused).  Freed by
- * hg_host_free or by hg_destroy. */
+ * memory, and such buffers should be allocated once and reused; Sec. 3.2.4:
+ * buffers are allocated through the library).  With a pinned pool
+ * (hg_create) the block is carved from it and HG_ENOMEM means the pool has
+ * no free range that large; without one, each call allocates.  *out is NULL
+ * on failure.  hg_host_free returns a block (NULL is a no-op); a pointer
+ * that is not a live block of this context (foreign, or already freed)
+ * gives HG_EINVAL.  hg_destroy frees every block. */
 int hg_host_alloc(hg_ctx *ctx, size_t bytes, void **out);
 int hg_host_free(hg_ctx *ctx, void *p);
 

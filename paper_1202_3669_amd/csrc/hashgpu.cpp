@@ -17,11 +17,13 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
 #include "hashgpu.h"
 #include "hg_internal.hpp"
+#include "hg_ranges.hpp"
 #include "host_hash.hpp"
 
 namespace {
@@ -66,6 +68,7 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+
 struct TimedLaunch {
     int klass = -1;
     hipEvent_t a = nullptr, b = nullptr;
@@ -83,7 +86,17 @@ struct hg_ctx {
     hipEvent_t stage_free[2] = {nullptr, nullptr};
     hipEvent_t piece_ready = nullptr;
     hipStream_t copy_stream = nullptr;
-    std::unordered_set<void *> host_allocs;
+    std::unordered_set<void *> host_allocs;  // hg_host_alloc blocks without a pinned pool
+    // Pools given at hg_create: a device region that every scratch slot is
+    // carved from, and a pinned region for hg_host_alloc.
+    uint8_t *dpool = nullptr;
+    uint64_t dpool_bytes = 0, dpool_used = 0;
+    hg::Ranges dranges;
+    uint8_t *ppool = nullptr;
+    uint64_t ppool_bytes = 0, ppool_used = 0;
+    hg::Ranges pranges;
+    std::unordered_map<void *, uint64_t> pool_blocks;  // pinned-pool block -> its carved size
+    uint64_t n_device_allocs = 0, n_pinned_allocs = 0;
     // Second levels computed on the host: pinned memory for the segment
     // digests copied back and for the roots sent to device outputs, and an
     // event after the last copy out of it.
@@ -195,19 +208,38 @@ int ensure(hg_ctx *ctx, Slot s, size_t bytes, hipStream_t st, void **out) {
     if (b.bytes < bytes) {
         // The old buffer may still be read by work queued on this stream.
         HG_HIP(ctx, hipStreamSynchronize(st));
-        if (b.p) HG_HIP(ctx, hipFree(b.p));
-        b.p = nullptr;
-        b.bytes = 0;
-        size_t want = std::max(bytes, (size_t)1 << 20);
-        want = (want + ((1u << 20) - 1)) & ~(size_t)((1u << 20) - 1);
-        hipError_t e = hipMalloc(&b.p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
+        if (ctx->dpool) {
+            // Carved from the device pool (64 KiB units); nothing allocated.
+            if (b.p) {
+                ctx->dranges.give((uint64_t)((uint8_t *)b.p - ctx->dpool), b.bytes);
+                ctx->dpool_used -= b.bytes;
+            }
             b.p = nullptr;
-            return fail(ctx, HG_ENOMEM, "device allocation of %zu bytes failed: %s", want,
-                        hipGetErrorString(e));
+            b.bytes = 0;
+            const size_t want = (bytes + ((64u << 10) - 1)) & ~(size_t)((64u << 10) - 1);
+            uint64_t off;
+            if (!ctx->dranges.take(want, &off))
+                return fail(ctx, HG_ENOMEM, "device pool: no free range of %zu bytes (%llu of %llu in use)", want,
+                            (unsigned long long)ctx->dpool_used, (unsigned long long)ctx->dpool_bytes);
+            b.p = ctx->dpool + off;
+            b.bytes = want;
+            ctx->dpool_used += want;
+        } else {
+            if (b.p) HG_HIP(ctx, hipFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+            size_t want = std::max(bytes, (size_t)1 << 20);
+            want = (want + ((1u << 20) - 1)) & ~(size_t)((1u << 20) - 1);
+            hipError_t e = hipMalloc(&b.p, want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                b.p = nullptr;
+                return fail(ctx, HG_ENOMEM, "device allocation of %zu bytes failed: %s", want,
+                            hipGetErrorString(e));
+            }
+            ctx->n_device_allocs++;
+            b.bytes = want;
         }
-        b.bytes = want;
     }
     *out = b.p;
     return HG_OK;
@@ -239,6 +271,7 @@ int ensure_stage(hg_ctx *ctx) {
             (void)hipGetLastError();
             return fail(ctx, HG_ENOMEM, "pinned staging allocation failed: %s", hipGetErrorString(e));
         }
+        ctx->n_pinned_allocs++;
         HG_HIP(ctx, hipEventCreateWithFlags(&ctx->stage_free[i], hipEventDisableTiming));
         HG_HIP(ctx, hipEventRecord(ctx->stage_free[i], ctx->copy_stream));
     }
@@ -287,6 +320,36 @@ int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_
         HG_TRY(on_piece(off, len));
     }
     return HG_OK;
+}
+
+// Pieces of host input whose segments one launch takes.  A launch lasts
+// as long as one segment's chain (one lane per segment), and launches on one
+// stream run one after another, so with long segments per-piece launches
+// queue: a 1 MiB SHA-1 segment takes ~19 ms against ~1.3 ms to copy a
+// 64 MiB piece.  The group size is chosen by simulating the schedule --
+// group k starts when its last piece has landed and group k-1 has ended,
+// and takes one chain -- and taking the earliest finish (the smallest group
+// on a tie).  Estimates: one 64-byte block per lane every ~0.6 us (MD5) /
+// ~1.15 us (SHA-1) / ~1.75 us (both), ~50 GB/s of host-to-device copy.
+uint64_t pieces_per_launch(uint64_t len, uint64_t block_size, double us_per_block, uint64_t piece) {
+    const double chain = (double)((block_size + 63) / 64) * us_per_block * 1e-6;
+    const double copy = (double)piece / 50e9;
+    const uint64_t n = std::max<uint64_t>(1, (len + piece - 1) / piece);
+    if (n > 4096) return 1;  // far more copy than any chain: per piece
+    uint64_t best_g = 1;
+    double best = 0;
+    for (uint64_t g = 1; g <= n; g++) {
+        double end = 0;
+        for (uint64_t last = g; ; last = std::min(n, last + g)) {
+            end = std::max(end, (double)last * copy) + chain;
+            if (last == n) break;
+        }
+        if (g == 1 || end < best * (1 - 1e-9)) {
+            best = end;
+            best_g = g;
+        }
+    }
+    return best_g;
 }
 
 // Device view of an input argument: the pointer itself, or a device copy.
@@ -401,6 +464,7 @@ int host_step_buffer(hg_ctx *ctx, size_t roots, size_t digests, uint8_t **r, uin
             ctx->hstep = nullptr;
             return fail(ctx, HG_ENOMEM, "pinned allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
         }
+        ctx->n_pinned_allocs++;
         ctx->hstep_bytes = sz;
     }
     *r = ctx->hstep;
@@ -513,7 +577,7 @@ int hg_last_error(const hg_ctx *ctx, char *buf, size_t n) {
     return ctx->last_status;
 }
 
-int hg_create(int device, hg_ctx **out) {
+int hg_create(int device, size_t device_pool_bytes, size_t pinned_pool_bytes, hg_ctx **out) {
     if (!out) return HG_EINVAL;
     *out = nullptr;
     int n = 0;
@@ -530,8 +594,34 @@ int hg_create(int device, hg_ctx **out) {
     ctx->device = device;
     if (hipHostMalloc((void **)&ctx->host_small, 4096, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->piece_ready, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
         hg_destroy(ctx);
         return HG_EDEVICE;
+    }
+    ctx->n_pinned_allocs++;
+    if (device_pool_bytes) {
+        const uint64_t sz = (device_pool_bytes + ((64u << 10) - 1)) & ~(uint64_t)((64u << 10) - 1);
+        if (hipMalloc((void **)&ctx->dpool, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->dpool = nullptr;
+            hg_destroy(ctx);
+            return HG_ENOMEM;
+        }
+        ctx->n_device_allocs++;
+        ctx->dpool_bytes = sz;
+        ctx->dranges.init(sz);
+    }
+    if (pinned_pool_bytes) {
+        const uint64_t sz = (pinned_pool_bytes + 255) & ~(uint64_t)255;
+        if (hipHostMalloc((void **)&ctx->ppool, sz, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->ppool = nullptr;
+            hg_destroy(ctx);
+            return HG_ENOMEM;
+        }
+        ctx->n_pinned_allocs++;
+        ctx->ppool_bytes = sz;
+        ctx->pranges.init(sz);
     }
     *out = ctx;
     return HG_OK;
@@ -541,8 +631,11 @@ void hg_destroy(hg_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (auto &b : ctx->slot)
-        if (b.p) (void)hipFree(b.p);
+    if (!ctx->dpool)
+        for (auto &b : ctx->slot)
+            if (b.p) (void)hipFree(b.p);
+    if (ctx->dpool) (void)hipFree(ctx->dpool);
+    if (ctx->ppool) (void)hipHostFree(ctx->ppool);
     for (int i = 0; i < 2; i++) {
         if (ctx->stage[i]) (void)hipHostFree(ctx->stage[i]);
         if (ctx->stage_free[i]) (void)hipEventDestroy(ctx->stage_free[i]);
@@ -561,9 +654,35 @@ void hg_destroy(hg_ctx *ctx) {
     delete ctx;
 }
 
+int hg_ctx_stats_read(const hg_ctx *ctx, hg_ctx_stats *out) {
+    if (!ctx || !out) return HG_EINVAL;
+    out->device_pool_bytes = ctx->dpool_bytes;
+    out->device_pool_used = ctx->dpool_used;
+    out->pinned_pool_bytes = ctx->ppool_bytes;
+    out->pinned_pool_used = ctx->ppool_used;
+    out->device_allocs = ctx->n_device_allocs;
+    out->pinned_allocs = ctx->n_pinned_allocs;
+    out->host_blocks = ctx->ppool ? ctx->pool_blocks.size() : ctx->host_allocs.size();
+    return HG_OK;
+}
+
 int hg_host_alloc(hg_ctx *ctx, size_t bytes, void **out) {
     HG_TRY(enter(ctx));
     if (!out || bytes == 0) return fail(ctx, HG_EINVAL, "hg_host_alloc: NULL out or zero size");
+    *out = nullptr;
+    if (ctx->ppool) {
+        // First fit in 256-byte units from the pinned pool.
+        const uint64_t want = ((uint64_t)bytes + 255) & ~(uint64_t)255;
+        uint64_t off;
+        if (want < bytes || !ctx->pranges.take(want, &off))
+            return fail(ctx, HG_ENOMEM, "pinned pool: no free range of %zu bytes (%llu of %llu in use)", bytes,
+                        (unsigned long long)ctx->ppool_used, (unsigned long long)ctx->ppool_bytes);
+        void *p = ctx->ppool + off;
+        ctx->pool_blocks[p] = want;
+        ctx->ppool_used += want;
+        *out = p;
+        return HG_OK;
+    }
     void *p = nullptr;
     hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -571,6 +690,7 @@ int hg_host_alloc(hg_ctx *ctx, size_t bytes, void **out) {
         return fail(ctx, HG_ENOMEM, "pinned allocation of %zu bytes failed: %s", bytes,
                     hipGetErrorString(e));
     }
+    ctx->n_pinned_allocs++;
     ctx->host_allocs.insert(p);
     *out = p;
     return HG_OK;
@@ -579,6 +699,15 @@ int hg_host_alloc(hg_ctx *ctx, size_t bytes, void **out) {
 int hg_host_free(hg_ctx *ctx, void *p) {
     HG_TRY(enter(ctx));
     if (!p) return HG_OK;
+    if (ctx->ppool) {
+        auto it = ctx->pool_blocks.find(p);
+        if (it == ctx->pool_blocks.end())
+            return fail(ctx, HG_EINVAL, "pointer is not a live block of this context's pinned pool");
+        ctx->pranges.give((uint64_t)((uint8_t *)p - ctx->ppool), it->second);
+        ctx->ppool_used -= it->second;
+        ctx->pool_blocks.erase(it);
+        return HG_OK;
+    }
     auto it = ctx->host_allocs.find(p);
     if (it == ctx->host_allocs.end()) return fail(ctx, HG_EINVAL, "pointer not from hg_host_alloc");
     ctx->host_allocs.erase(it);
@@ -617,15 +746,19 @@ int hg_block_hash(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block_size
         void *dp;
         HG_TRY(ensure(ctx, SLOT_IN, len, st, &dp));
         uint8_t *din = (uint8_t *)dp;
-        // Pieces hold whole segments; each piece's segments are hashed as
-        // soon as the piece has landed.
+        // Pieces hold whole segments; the segments of a group of pieces are
+        // hashed as soon as the group has landed.
+        const uint64_t group = pieces_per_launch(len, block_size, digest == HG_MD5 ? 0.6 : 1.15, STAGE_PIECE);
+        uint64_t from = 0, npieces = 0;
         HG_TRY(stream_in(ctx, din, (const uint8_t *)in, len, block_size, st,
                          [&](uint64_t off, uint64_t plen) -> int {
-                             const uint64_t k0 = off / block_size;
+                             if (++npieces % group != 0 && off + plen < len) return HG_OK;
+                             const uint64_t k0 = from / block_size;
                              const uint64_t k1 = (off + plen + block_size - 1) / block_size;
                              HG_LAUNCH(ctx, HG_K_LEAVES, st,
-                                       hg::launch_leaves(digest, din + off, plen, block_size, k1 - k0,
+                                       hg::launch_leaves(digest, din + from, off + plen - from, block_size, k1 - k0,
                                                          leaves + k0 * (uint64_t)d, st));
+                             from = off + plen;
                              return HG_OK;
                          }));
     }
@@ -685,13 +818,17 @@ int hg_block_hash_dual(hg_ctx *ctx, const void *in, uint64_t len, uint64_t block
     } else {
         HG_TRY(ensure(ctx, SLOT_IN, len, st, &p));
         uint8_t *din = (uint8_t *)p;
+        const uint64_t group = pieces_per_launch(len, block_size, 1.75, STAGE_PIECE);
+        uint64_t from = 0, npieces = 0;
         HG_TRY(stream_in(ctx, din, (const uint8_t *)in, len, block_size, st,
                          [&](uint64_t off, uint64_t plen) -> int {
-                             const uint64_t k0 = off / block_size;
+                             if (++npieces % group != 0 && off + plen < len) return HG_OK;
+                             const uint64_t k0 = from / block_size;
                              const uint64_t k1 = (off + plen + block_size - 1) / block_size;
                              HG_LAUNCH(ctx, HG_K_LEAVES, st,
-                                       hg::launch_leaves_dual(din + off, plen, block_size, k1 - k0, lm + k0 * 16,
-                                                              ls + k0 * 20, st));
+                                       hg::launch_leaves_dual(din + from, off + plen - from, block_size, k1 - k0,
+                                                              lm + k0 * 16, ls + k0 * 20, st));
+                             from = off + plen;
                              return HG_OK;
                          }));
     }

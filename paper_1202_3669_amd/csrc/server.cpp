@@ -44,6 +44,7 @@
 
 #include "hashgpu.h"
 #include "hg_internal.hpp"
+#include "hg_ranges.hpp"
 
 namespace {
 
@@ -65,49 +66,6 @@ struct Req {
     Clock::time_point t_arrival;
 };
 
-// First-fit ranges over [0, size) with coalescing of returned ranges.
-class Ranges {
-  public:
-    void init(uint64_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool fits(uint64_t n) const {
-        for (const auto &kv : free_)
-            if (kv.second >= n) return true;
-        return false;
-    }
-    bool take(uint64_t n, uint64_t *off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= n) {
-                *off = it->first;
-                const uint64_t rest = it->second - n, at = it->first + n;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void give(uint64_t off, uint64_t n) {
-        auto it = free_.emplace(off, n).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<uint64_t, uint64_t> free_;
-};
 
 constexpr uint64_t STAGE_ALIGN = 256;
 constexpr size_t LAT_WINDOW = 1u << 20;  // completions the latency statistics cover
@@ -205,7 +163,7 @@ struct hg_server {
     int device = 0;
     hg_server_cfg cfg{};
     uint8_t *stage = nullptr;
-    Ranges ranges;
+    hg::Ranges ranges;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Req *> pending;
@@ -275,7 +233,7 @@ void group_free(Group &g) {
 
 int group_init(Group &g, int device, const hg_server_cfg &cfg) {
     int st;
-    if ((st = hg_create(device, &g.ctx)) != HG_OK) return st;
+    if ((st = hg_create(device, 0, 0, &g.ctx)) != HG_OK) return st;
     if (hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&g.aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&g.fork, hipEventDisableTiming) != hipSuccess ||

@@ -80,6 +80,12 @@ class hg_server_stats(ctypes.Structure):
                 ("max_ms", ctypes.c_double)]
 
 
+class hg_ctx_stats(ctypes.Structure):
+    _fields_ = [("device_pool_bytes", _u64), ("device_pool_used", _u64), ("pinned_pool_bytes", _u64),
+                ("pinned_pool_used", _u64), ("device_allocs", _u64), ("pinned_allocs", _u64),
+                ("host_blocks", _u64)]
+
+
 HG_SERVER_CB = ctypes.CFUNCTYPE(None, _u64, ctypes.c_int, _vp)
 
 
@@ -90,12 +96,13 @@ def _declare(name, restype, argtypes):
     return fn
 
 
-hg_create = _declare("hg_create", _int, [_int, ctypes.POINTER(_vp)])
+hg_create = _declare("hg_create", _int, [_int, ctypes.c_size_t, ctypes.c_size_t, ctypes.POINTER(_vp)])
 hg_destroy = _declare("hg_destroy", None, [_vp])
 hg_strerror = _declare("hg_strerror", ctypes.c_char_p, [_int])
 hg_last_error = _declare("hg_last_error", _int, [_vp, ctypes.c_char_p, ctypes.c_size_t])
 hg_digest_size = _declare("hg_digest_size", _int, [_int])
 hg_host_hash = _declare("hg_host_hash", _int, [_int, _vp, _u64, _vp])
+hg_ctx_stats_read = _declare("hg_ctx_stats_read", _int, [_vp, ctypes.POINTER(hg_ctx_stats)])
 hg_host_alloc = _declare("hg_host_alloc", _int, [_vp, ctypes.c_size_t, ctypes.POINTER(_vp)])
 hg_host_free = _declare("hg_host_free", _int, [_vp, _vp])
 hg_block_hash = _declare("hg_block_hash", _int, [_vp, _vp, _u64, _u64, _int, _vp, _vp, _u32, _vp])
@@ -166,7 +173,7 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
             "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset", "hg_blockmap_create",
             "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write", "hg_chunk_select",
-            "hg_chunk_digests", "hg_similarity_n", "hg_host_hash"]
+            "hg_chunk_digests", "hg_similarity_n", "hg_host_hash", "hg_ctx_stats_read"]
 
 
 def host_hash(digest: int, data) -> bytes:
@@ -223,13 +230,33 @@ def _on_stream(fn):
 class Context:
     """One hg_ctx on one device, used from one stream at a time."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, device_pool: int = 0, pinned_pool: int = 0):
+        """device_pool / pinned_pool: sizes of the pools hg_create allocates
+        (0: none; see hg_create)."""
         h = _vp()
-        st = hg_create(device, ctypes.byref(h))
+        st = hg_create(device, device_pool, pinned_pool, ctypes.byref(h))
         if st != HG_OK:
             raise HashGpuError(st, f"hg_create({device}) failed")
         self.handle = h
         self.device = device
+
+    def stats(self) -> dict:
+        """Pool use and allocation counts (hg_ctx_stats_read)."""
+        out = hg_ctx_stats()
+        self._check(hg_ctx_stats_read(self.handle, ctypes.byref(out)))
+        return {f[0]: int(getattr(out, f[0])) for f in hg_ctx_stats._fields_}
+
+    def host_alloc(self, nbytes: int):
+        """A pinned host block from the context (hg_host_alloc): (pointer,
+        uint8 numpy view of it)."""
+        import numpy as np
+        p = _vp()
+        self._check(hg_host_alloc(self.handle, nbytes, ctypes.byref(p)))
+        view = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(p.value))
+        return p.value, view
+
+    def host_free(self, ptr) -> None:
+        self._check(hg_host_free(self.handle, ptr))
 
     def close(self):
         if self.handle:

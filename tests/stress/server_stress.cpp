@@ -136,7 +136,7 @@ int main() {
 
     // Results against the single calls.
     hg_ctx *ctx = nullptr;
-    if ((st = hg_create(0, &ctx)) != HG_OK) return fail("hg_create", st);
+    if ((st = hg_create(0, 0, 0, &ctx)) != HG_OK) return fail("hg_create", st);
     int checked = 0;
     for (size_t i = 0; i < jobs.size(); i++) {
         Job &j = jobs[i];

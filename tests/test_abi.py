@@ -40,7 +40,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     # and every struct of the size a C compiler gives them.
     from paper_1202_3669_amd import hashgpu as hg
     structs = [hg.hg_chunk_params, hg.hg_block_job, hg.hg_batch_params, hg.hg_batch_out, hg.hg_request,
-               hg.hg_server_cfg, hg.hg_server_stats]
+               hg.hg_server_cfg, hg.hg_server_stats, hg.hg_ctx_stats]
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     expect = []
     for cls in structs:
@@ -102,7 +102,7 @@ def test_create_without_gpu_reports_edevice():
         "import torch\n"
         "if torch.cuda.device_count() > 0: sys.exit(3)\n"
         "h = ctypes.c_void_p()\n"
-        "sys.exit(0 if hg.hg_create(0, ctypes.byref(h)) == hg.HG_EDEVICE else 1)\n"
+        "sys.exit(0 if hg.hg_create(0, 0, 0, ctypes.byref(h)) == hg.HG_EDEVICE else 1)\n"
     )
     r = subprocess.run(["python", "-c", code], cwd=ROOT, capture_output=True, text=True)
     if r.returncode == 3:

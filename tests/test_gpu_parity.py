@@ -463,9 +463,31 @@ def test_block_hash_large_workload(ctx, block):
     lm, rm, ls, rs = ctx.block_hash_dual(d, block)
     torch.cuda.synchronize()
     for kind, lv, rt in ((oracle.MD5, lm, rm), (oracle.SHA1, ls, rs)):
-        exp_lv, exp_rt = _LARGE.pop((kind, block))
+        exp_lv, exp_rt = _LARGE[(kind, block)]
         assert np.array_equal(host(lv), exp_lv)
         assert bytes(host(rt)) == exp_rt
+    del lm, rm, ls, rs
+    # Host input: the 1 GiB streamed from pinned and from pageable memory
+    # (pieces copied while earlier pieces hash), each digest and both at once.
+    if "pinned" not in _LARGE:
+        _LARGE["pinned"] = torch.from_numpy(data).pin_memory()
+    for where, src in (("pinned", _LARGE["pinned"]), ("pageable", torch.from_numpy(data))):
+        for kind in KINDS:
+            note(f"block_hash 1GiB host input {where} kind={kind} B={block}")
+            lv, rt = ctx.block_hash(src, block, kind)
+            torch.cuda.synchronize()
+            exp_lv, exp_rt = _LARGE[(kind, block)]
+            assert np.array_equal(host(lv), exp_lv)
+            assert bytes(host(rt)) == exp_rt
+        note(f"block_hash_dual 1GiB host input {where} B={block}")
+        lm, rm, ls, rs = ctx.block_hash_dual(src, block)
+        torch.cuda.synchronize()
+        for kind, lv, rt in ((oracle.MD5, lm, rm), (oracle.SHA1, ls, rs)):
+            exp_lv, exp_rt = _LARGE[(kind, block)]
+            assert np.array_equal(host(lv), exp_lv)
+            assert bytes(host(rt)) == exp_rt
+    for kind in KINDS:
+        _LARGE.pop((kind, block))
 
 
 _LARGE = {}
@@ -536,7 +558,7 @@ def test_invalid_arguments(ctx, hg):
     assert hg.hg_last_error(ctx.handle, buf, 256) == hg.HG_EINVAL
     assert b"max_chunk" in buf.value
     h = ctypes.c_void_p()
-    assert hg.hg_create(99, ctypes.byref(h)) == hg.HG_EDEVICE
+    assert hg.hg_create(99, 0, 0, ctypes.byref(h)) == hg.HG_EDEVICE
 
 
 # ---------------------------------------------------------------- batches --
