@@ -261,6 +261,26 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
                    uint32_t mask, uint32_t target, int digest, uint64_t *starts,
                    uint64_t capacity, uint64_t *count, uint32_t flags, void *stream);
 
+/* hg_window_scan without any allocation, for callers that cannot allocate
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The same scan and results as hg_window_scan with
+ * HG_IN_DEVICE | HG_OUT_DEVICE | HG_ASYNC: in, starts and count are device
+ * pointers, the call returns after enqueueing on `stream`, and *count holds
+ * the full number of candidates once the stream has completed (truncation
+ * shows as *count > capacity).  Its scratch (the per-tile bookkeeping, about
+ * 80 bytes per 4096 windows for w = 20 at stride 1 or 4, up to twice that
+ * for other windows) lives in a fixed array of HG_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU until the process ends (set up by
+ * hg_create); the call allocates nothing and returns HG_EINVAL when the
+ * scan would need more (for w = 20, stride 1: inputs up to about 1.6 GiB).
+ * Every call on a GPU shares that GPU's array and leaves it holding its
+ * bookkeeping: calls that overlap on one GPU (other streams, other threads,
+ * other contexts) race and must be serialized by the caller. */
+enum { HG_NOALLOC_SCRATCH_BYTES = 32 << 20 };
+int hg_window_scan_noalloc(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, uint32_t stride,
+                           uint32_t mask, uint32_t target, int digest, uint64_t *starts,
+                           uint64_t capacity, uint64_t *count, void *stream);
+
 typedef struct {
     uint32_t window, stride, mask, target; /* as for hg_window_scan */
     uint64_t min_chunk;   /* minimum chunk size in bytes (0 = none) */

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <unordered_map>
@@ -68,6 +69,15 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Scratch of hg_window_scan_noalloc: a fixed array on every GPU the library
+// runs on, held until the process ends.  Host code never uses its name as an
+// address (that is a host-side stand-in): hg_create looks up its device
+// address once per device, and the calls pass that address to the kernels.
+constexpr size_t NOALLOC_SCRATCH = (size_t)HG_NOALLOC_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
 
 struct TimedLaunch {
     int klass = -1;
@@ -611,6 +621,25 @@ int hg_create(int device, size_t device_pool_bytes, size_t pinned_pool_bytes, hg
         ctx->dpool_bytes = sz;
         ctx->dranges.init(sz);
     }
+    if (device >= MAX_DEVICES) {
+        hg_destroy(ctx);
+        return HG_EDEVICE;
+    }
+    {
+        // Device address of this GPU's copy of the fixed scratch array, looked
+        // up once per device with the device current.
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *ptr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                hg_destroy(ctx);
+                return HG_EDEVICE;
+            }
+            g_scratch_ptr[device] = ptr;
+        }
+    }
     if (pinned_pool_bytes) {
         const uint64_t sz = (pinned_pool_bytes + 255) & ~(uint64_t)255;
         if (hipHostMalloc((void **)&ctx->ppool, sz, hipHostMallocDefault) != hipSuccess) {
@@ -1028,6 +1057,39 @@ int hg_window_scan(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, u
     return total > capacity ? fail(ctx, HG_ETRUNC, "%llu candidates, capacity %llu",
                                    (unsigned long long)total, (unsigned long long)capacity)
                             : HG_OK;
+}
+
+int hg_window_scan_noalloc(hg_ctx *ctx, const void *in, uint64_t len, uint32_t window, uint32_t stride,
+                           uint32_t mask, uint32_t target, int digest, uint64_t *starts, uint64_t capacity,
+                           uint64_t *count, void *stream) {
+    HG_TRY(enter(ctx));
+    if (digest_bytes(digest) < 0) return fail(ctx, HG_EINVAL, "unknown digest %d", digest);
+    if (window == 0 || window > HG_MAX_WINDOW)
+        return fail(ctx, HG_EINVAL, "window must be in [1, %d]", (int)HG_MAX_WINDOW);
+    if (stride == 0) return fail(ctx, HG_EINVAL, "stride must be >= 1");
+    if (!count) return fail(ctx, HG_EINVAL, "count is NULL");
+    if (capacity && !starts) return fail(ctx, HG_EINVAL, "starts is NULL with capacity > 0");
+    if (len && !in) return fail(ctx, HG_EINVAL, "in is NULL");
+    void *ws;
+    {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        ws = g_scratch_ptr[ctx->device];
+    }
+    if (!ws) return fail(ctx, HG_EDEVICE, "no scratch address for device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const hg::WsPlan plan = hg::plan_window_scan((const uint8_t *)in, len, window, stride, digest);
+    const size_t need = hg::window_scan_scratch_bytes(plan);
+    if (need > NOALLOC_SCRATCH)
+        return fail(ctx, HG_EINVAL, "scan needs %zu bytes of scratch, more than the %zu of hg_window_scan_noalloc",
+                    need, NOALLOC_SCRATCH);
+    // The same kernels as hg_window_scan (device input and outputs); every
+    // scratch word they read is written first in this call, so nothing
+    // needs clearing.
+    const uint8_t *din = (const uint8_t *)in;
+    HG_HIP(ctx, hg::launch_window_scan_tiles(plan, din, len, window, stride, mask, target, ws, st));
+    HG_HIP(ctx, hg::launch_window_scan_prefix(plan, ws, count, st));
+    HG_HIP(ctx, hg::launch_window_scan_emit(plan, din, len, window, stride, mask, target, ws, starts, capacity, st));
+    return HG_OK;
 }
 
 int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *pr, uint64_t *ends,

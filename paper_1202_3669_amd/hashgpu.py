@@ -103,6 +103,9 @@ hg_last_error = _declare("hg_last_error", _int, [_vp, ctypes.c_char_p, ctypes.c_
 hg_digest_size = _declare("hg_digest_size", _int, [_int])
 hg_host_hash = _declare("hg_host_hash", _int, [_int, _vp, _u64, _vp])
 hg_ctx_stats_read = _declare("hg_ctx_stats_read", _int, [_vp, ctypes.POINTER(hg_ctx_stats)])
+hg_window_scan_noalloc = _declare("hg_window_scan_noalloc", _int,
+                                  [_vp, _vp, _u64, _u32, _u32, _u32, _u32, _int, _vp, _u64, _vp, _vp])
+HG_NOALLOC_SCRATCH_BYTES = 32 << 20
 hg_host_alloc = _declare("hg_host_alloc", _int, [_vp, ctypes.c_size_t, ctypes.POINTER(_vp)])
 hg_host_free = _declare("hg_host_free", _int, [_vp, _vp])
 hg_block_hash = _declare("hg_block_hash", _int, [_vp, _vp, _u64, _u64, _int, _vp, _vp, _u32, _vp])
@@ -173,7 +176,8 @@ EXPORTED = ["hg_create", "hg_destroy", "hg_strerror", "hg_last_error", "hg_diges
             "hg_block_hash_dual", "hg_chunker_create", "hg_chunker_destroy", "hg_chunker_bound",
             "hg_chunker_feed", "hg_chunker_finish", "hg_chunker_reset", "hg_blockmap_create",
             "hg_blockmap_destroy", "hg_blockmap_size", "hg_blockmap_write", "hg_chunk_select",
-            "hg_chunk_digests", "hg_similarity_n", "hg_host_hash", "hg_ctx_stats_read"]
+            "hg_chunk_digests", "hg_similarity_n", "hg_host_hash", "hg_ctx_stats_read",
+            "hg_window_scan_noalloc"]
 
 
 def host_hash(digest: int, data) -> bytes:
