@@ -316,7 +316,8 @@ class Pipeline:
 # recorded with a hash of the kernel sources; stale figures are not used.
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "window_tiles_1GiB_pmc.md")
-KERNEL_SOURCES = ["paper_1202_3669_amd/csrc/window_scan.hip", "paper_1202_3669_amd/csrc/hg_device.hpp"]
+KERNEL_SOURCES = ["paper_1202_3669_amd/csrc/window_scan.hip", "paper_1202_3669_amd/csrc/hg_device.hpp",
+                  "paper_1202_3669_amd/csrc/hg_rounds.hpp"]
 
 
 def kernel_source_hash():

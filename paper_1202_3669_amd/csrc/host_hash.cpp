@@ -1,7 +1,7 @@
 // host_hash.cpp -- sequential MD5 / SHA-1 on the host and the host thread
 // pool (see host_hash.hpp).
 //
-// The round sequences are the library's own macros from hg_device.hpp
+// The round sequences are the library's own macros from hg_rounds.hpp
 // (RFC 1321 / FIPS 180-4 order and constants); here they expand with host
 // versions of the three-input boolean functions and the rotate.  SHA-1 also
 // has a path on the x86 SHA extensions: sha1rnds4 runs four rounds on the
@@ -10,7 +10,6 @@
 // schedule four words at a time.
 #include "host_hash.hpp"
 
-#include <hip/hip_runtime.h>
 #include <cpuid.h>
 #include <immintrin.h>
 
@@ -23,7 +22,7 @@
 #include <thread>
 #include <vector>
 
-#include "hg_device.hpp"
+#include "hg_rounds.hpp"
 
 namespace hg {
 namespace host {
