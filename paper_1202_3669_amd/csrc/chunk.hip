@@ -415,6 +415,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     store_digest<KIND>(out + j * (uint64_t)Hash<KIND>::DIGEST, st);
 }
 
+// The longest of the segments [ends[j-1], ends[j]), j < *n_dev <= max_n, to
+// *out (which the launcher clears first).
+__global__ __launch_bounds__(256) void max_gap_kernel(const uint64_t *__restrict__ ends, uint64_t len,
+                                                      const uint64_t *__restrict__ n_dev, uint64_t max_n,
+                                                      unsigned long long *__restrict__ out) {
+    const uint64_t n = seg_count(n_dev, max_n);
+    uint64_t m = 0;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t l = seg_len(nullptr, ends, len, t);
+        m = l > m ? l : m;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, (unsigned long long)m);
+}
+
+hipError_t launch_max_gap(const uint64_t *ends, uint64_t len, const uint64_t *n_dev, uint64_t max_n, uint64_t *out,
+                          hipStream_t s) {
+    hipError_t e = launch_fill_u32((uint32_t *)out, 2, 0, s);
+    if (e != hipSuccess || max_n == 0) return e;
+    const unsigned grid = (unsigned)std::min<uint64_t>((max_n + 255) / 256, 1024);
+    max_gap_kernel<<<grid, 256, 0, s>>>(ends, len, n_dev, max_n, (unsigned long long *)out);
+    return hipGetLastError();
+}
+
+// Digests computed elsewhere (on the host): record k of `src` (d bytes) goes
+// to out + idx[k] * d.
+__global__ __launch_bounds__(256) void digest_scatter_kernel(const uint64_t *__restrict__ idx,
+                                                             const uint8_t *__restrict__ src, uint64_t n, int d,
+                                                             uint8_t *__restrict__ out) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint8_t *o = out + idx[k] * (uint64_t)d;
+    for (int b = 0; b < d; b++) o[b] = src[k * (uint64_t)d + b];
+}
+
+hipError_t launch_digest_scatter(const uint64_t *idx, const uint8_t *src, uint64_t n, int d, uint8_t *out,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    digest_scatter_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, src, n, d, out);
+    return hipGetLastError();
+}
+
 size_t segment_digest_scratch_bytes(uint64_t max_n) {
     return SEG_CLASSES * 4 + ((max_n * 4 + 255) & ~(uint64_t)255) + 256;
 }

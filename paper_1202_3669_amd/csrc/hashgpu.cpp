@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +50,7 @@ enum Slot {
     SLOT_AUX,      // shifted candidate starts (streaming chunker)
     SLOT_TLEAF,    // segment digests of two-level chunk digests
     SLOT_ROOTS,    // second levels computed on the host, on their way to root_out
+    SLOT_SPLIT,    // chunk digests split with the host: starts, indices, host digests
     N_SLOTS
 };
 
@@ -113,6 +115,10 @@ struct hg_ctx {
     uint8_t *hstep = nullptr;
     size_t hstep_bytes = 0;
     hipEvent_t hstep_free = nullptr;
+    // Chunk digests split with the host: the input is ready, and one event
+    // per group of long chunks copied back.
+    hipEvent_t split_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> split_groups;
     // Kernel timing (hg_timing_*).
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -440,9 +446,10 @@ int small_words(hg_ctx *ctx, hipStream_t st, uint64_t **out) {
     return HG_OK;
 }
 
-// Reads one device uint64 (synchronizes the stream).
-int read_u64(hg_ctx *ctx, const uint64_t *dev, hipStream_t st, uint64_t *v) {
-    HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, dev, 8, hipMemcpyDeviceToHost, st));
+// Reads one device uint64 (synchronizes the stream); with words = 2 the
+// next word too, left in host_small[1].
+int read_u64(hg_ctx *ctx, const uint64_t *dev, hipStream_t st, uint64_t *v, int words = 1) {
+    HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, dev, 8 * (size_t)words, hipMemcpyDeviceToHost, st));
     HG_HIP(ctx, hipStreamSynchronize(st));
     *v = ctx->host_small[0];
     return HG_OK;
@@ -512,6 +519,140 @@ int host_roots(hg_ctx *ctx, HostRoot *roots, size_t n, uint8_t *stage, hipStream
         const HostRoot &r = roots[order[k]];
         hg::host::digest(r.kind, r.digests, r.bytes, r.out);
     });
+    return HG_OK;
+}
+
+// Longest chunk from which hg_chunk considers hashing chunks on the host.
+constexpr uint64_t HOST_CHUNK_MIN = 64u << 10;
+
+// Standard chunk digests with the longest chunks hashed on the host: each
+// digest is one sequential chain, which one GPU lane runs at ~55 MB/s
+// (SHA-1) and a CPU core at 0.5-2 GB/s.  The host reads the nc chunk ends,
+// picks the k longest chunks by a cost model (the host's copy and hash time
+// against the GPU's longest remaining chain), and hashes them on the host
+// pool -- from the caller's host input if there is one, else from a copy
+// made on the copy stream -- while the GPU hashes the others (the long ones
+// get an empty range there); a scatter then puts the host digests in place.
+// *split = false when the model keeps everything on the GPU (nothing done).
+int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t *hin, uint64_t len,
+                        const uint64_t *dends, const uint64_t *n_dev, uint64_t nc, uint8_t *ddig, hipStream_t st,
+                        bool *split) {
+    *split = false;
+    std::vector<uint64_t> ends(nc);
+    HG_HIP(ctx, hipMemcpyAsync(ends.data(), dends, nc * 8, hipMemcpyDeviceToHost, st));
+    HG_HIP(ctx, hipStreamSynchronize(st));
+    std::vector<uint64_t> lens(nc), order(nc);
+    for (uint64_t j = 0; j < nc; j++) lens[j] = ends[j] - (j ? ends[j - 1] : 0);
+    std::iota(order.begin(), order.end(), (uint64_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return lens[a] > lens[b]; });
+    const double lane = kind == HG_MD5 ? 110e6 : 55e6;
+    const double core = kind == HG_MD5 ? 0.5e9 : (hg::host::sha1_accelerated() ? 1.5e9 : 0.5e9);
+    const double cores = (double)hg::host::pool_threads() + 1;
+    const double copy = hin ? 0.0 : 1.0 / 40e9;
+    uint64_t best_k = 0, bytes = 0;
+    double best = (double)lens[order[0]] / lane;
+    const uint64_t kmax = std::min<uint64_t>(nc, 1u << 16);
+    for (uint64_t k = 1; k <= kmax; k++) {
+        bytes += lens[order[k - 1]];
+        const double host_t = (double)bytes * copy + std::max((double)lens[order[0]] / core, (double)bytes / (core * cores));
+        const double gpu_t = k < nc ? (double)lens[order[k]] / lane : 0.0;
+        const double t = std::max(host_t, gpu_t);
+        if (t < best) {
+            best = t;
+            best_k = k;
+        }
+        if (gpu_t < 1e-4) break;  // the rest are short: nothing more to gain
+    }
+    if (best_k == 0) return HG_OK;
+    const uint64_t k = best_k;
+    std::vector<uint8_t> is_long(nc, 0);
+    uint64_t host_bytes = 0;
+    for (uint64_t i = 0; i < k; i++) {
+        is_long[order[i]] = 1;
+        host_bytes += lens[order[i]];
+    }
+    // Long chunks in position order, and the contiguous runs they form.
+    std::vector<uint64_t> idx;
+    idx.reserve(k);
+    for (uint64_t j = 0; j < nc; j++)
+        if (is_long[j]) idx.push_back(j);
+    const int d = digest_bytes(kind);
+    // Device and pinned host alike: indices (k), host digests (k * 20),
+    // GPU-side starts (nc); then, pinned only, the long chunks' bytes.
+    const size_t ibytes = (k * 8 + 255) & ~(size_t)255, gbytes = (k * 20 + 255) & ~(size_t)255, sbytes = nc * 8;
+    void *dsplit;
+    HG_TRY(ensure(ctx, SLOT_SPLIT, ibytes + gbytes + sbytes, st, &dsplit));
+    uint64_t *didx = (uint64_t *)dsplit;
+    uint8_t *ddg = (uint8_t *)dsplit + ibytes;
+    uint64_t *dstarts = (uint64_t *)(ddg + gbytes);
+    uint8_t *hr, *hbytes;
+    HG_TRY(host_step_buffer(ctx, ibytes + gbytes + sbytes, hin ? 0 : host_bytes, &hr, &hbytes));
+    memcpy(hr, idx.data(), k * 8);
+    uint8_t *hdig = hr + ibytes;
+    uint64_t *hstarts = (uint64_t *)(hdig + gbytes);
+    for (uint64_t j = 0; j < nc; j++) hstarts[j] = is_long[j] ? ends[j] : (j ? ends[j - 1] : 0);
+    for (int i = 0; i < 2; i++)
+        if (!ctx->split_ev[i]) HG_HIP(ctx, hipEventCreateWithFlags(&ctx->split_ev[i], hipEventDisableTiming));
+    // Host order: longest first (the longest chain sets the host's time).
+    std::vector<uint64_t> by_len(k);
+    std::iota(by_len.begin(), by_len.end(), (uint64_t)0);
+    std::stable_sort(by_len.begin(), by_len.end(),
+                     [&](uint64_t a, uint64_t b) { return lens[idx[a]] > lens[idx[b]]; });
+    std::vector<const uint8_t *> src(k);
+    std::vector<uint32_t> group(k, 0);
+    uint32_t n_groups = 0;
+    if (!hin) {
+        // The long chunks' bytes come back on the copy stream (the input is
+        // complete on st) in host order, in groups of ~16 MiB with an event
+        // each, so that hashing starts as soon as the first group has landed
+        // and overlaps the rest of the copy -- and the GPU's share runs
+        // meanwhile.
+        HG_TRY(ensure_copy_stream(ctx));
+        HG_HIP(ctx, hipEventRecord(ctx->split_ev[0], st));
+        HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->split_ev[0], 0));
+        uint64_t off = 0, in_group = 0;
+        for (uint64_t t = 0; t < k; t++) {
+            const uint64_t i = by_len[t], j = idx[i], a = j ? ends[j - 1] : 0;
+            src[i] = hbytes + off;
+            group[i] = n_groups;
+            HG_HIP(ctx, hipMemcpyAsync(hbytes + off, din + a, lens[j], hipMemcpyDeviceToHost, ctx->copy_stream));
+            off += lens[j];
+            in_group += lens[j];
+            if (in_group >= (16u << 20) || t + 1 == k) {
+                if (ctx->split_groups.size() <= n_groups) {
+                    hipEvent_t e;
+                    HG_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                    ctx->split_groups.push_back(e);
+                }
+                HG_HIP(ctx, hipEventRecord(ctx->split_groups[n_groups], ctx->copy_stream));
+                n_groups++;
+                in_group = 0;
+            }
+        }
+    } else {
+        for (uint64_t i = 0; i < k; i++) src[i] = hin + (idx[i] ? ends[idx[i] - 1] : 0);
+    }
+    // The GPU's share: the long chunks are empty ranges there.
+    HG_HIP(ctx, hipMemcpyAsync(dstarts, hstarts, sbytes, hipMemcpyHostToDevice, st));
+    void *segs;
+    HG_TRY(ensure(ctx, SLOT_SEG, hg::segment_digest_scratch_bytes(nc), st, &segs));
+    HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st,
+              hg::launch_segment_digests(kind, din, len, dstarts, dends, n_dev, nc, ddig, segs, st));
+    // The host's share, longest first, each chunk once its group has landed.
+    std::atomic<int> copy_err{0};
+    hg::host::parallel_for(k, [&](uint64_t t) {
+        const uint64_t i = by_len[t];
+        if (!hin && hipEventSynchronize(ctx->split_groups[group[i]]) != hipSuccess) {
+            copy_err.store(1);
+            return;
+        }
+        hg::host::digest(kind, src[i], lens[idx[i]], hdig + i * (uint64_t)d);
+    });
+    if (copy_err.load()) return fail(ctx, HG_EDEVICE, "copy of long chunks to the host failed");
+    HG_HIP(ctx, hipMemcpyAsync(didx, hr, ibytes + k * 20, hipMemcpyHostToDevice, st));
+    HG_HIP(ctx, hipEventRecord(ctx->hstep_free, st));
+    HG_LAUNCH(ctx, HG_K_CHUNK_DIGESTS, st, hg::launch_digest_scatter(didx, ddg, k, d, ddig, st));
+    *split = true;
     return HG_OK;
 }
 
@@ -678,6 +819,9 @@ void hg_destroy(hg_ctx *ctx) {
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
     if (ctx->hstep) (void)hipHostFree(ctx->hstep);
     if (ctx->hstep_free) (void)hipEventDestroy(ctx->hstep_free);
+    for (hipEvent_t e : ctx->split_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->split_groups) (void)hipEventDestroy(e);
     if (ctx->piece_ready) (void)hipEventDestroy(ctx->piece_ready);
     if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     delete ctx;
@@ -1151,8 +1295,13 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
                                           pr->min_chunk, sel, (uint64_t *)dends, n_cand + 1, &small[1], st));
     }
     // The chunk count sizes the outputs; the digests are enqueued after it.
-    uint64_t nc;
-    HG_TRY(read_u64(ctx, &small[1], st, &nc));
+    // With standard chunk digests the longest chunk comes back with it: long
+    // chunks are hashed on the host (chunk_digests_split).
+    const bool may_split = chunk_digests && pr->chunk_segment == 0 && len >= HOST_CHUNK_MIN;
+    if (may_split) HG_HIP(ctx, hg::launch_max_gap((const uint64_t *)dends, len, &small[1], bound, &small[2], st));
+    uint64_t nc, longest = 0;
+    HG_TRY(read_u64(ctx, &small[1], st, &nc, may_split ? 2 : 1));
+    if (may_split) longest = ctx->host_small[1];
     const uint64_t k = std::min(nc, capacity);
     if (!ends_direct) HG_TRY(copy_out(ctx, ends, dends, k * 8, out_dev, st));
     if (chunk_digests) {
@@ -1160,7 +1309,12 @@ int hg_chunk(hg_ctx *ctx, const void *in, uint64_t len, const hg_chunk_params *p
         const bool direct = out_dev && capacity >= nc;
         void *ddig = chunk_digests;
         if (!direct) HG_TRY(ensure(ctx, SLOT_DIG, (nc + 1) * (uint64_t)dd, st, &ddig));
-        HG_TRY(chunk_digests_of(ctx, *pr, din, len, (const uint64_t *)dends, &small[1], nc, (uint8_t *)ddig, st));
+        bool split = false;
+        if (longest >= HOST_CHUNK_MIN)
+            HG_TRY(chunk_digests_split(ctx, pr->chunk_digest, din, in_dev ? nullptr : (const uint8_t *)in, len,
+                                       (const uint64_t *)dends, &small[1], nc, (uint8_t *)ddig, st, &split));
+        if (!split)
+            HG_TRY(chunk_digests_of(ctx, *pr, din, len, (const uint64_t *)dends, &small[1], nc, (uint8_t *)ddig, st));
         if (!direct) HG_TRY(copy_out(ctx, chunk_digests, ddig, k * (uint64_t)dd, out_dev, st));
     }
     if (out_dev && !count_host) HG_TRY(copy_out(ctx, n_chunks, &small[1], 8, true, st));

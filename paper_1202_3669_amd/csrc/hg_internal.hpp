@@ -121,6 +121,13 @@ hipError_t launch_chunk_select(const uint64_t *starts, const uint64_t *n_starts_
 // each segment reads only its own bytes (len is then unused).  Scratch is
 // segment_digest_scratch_bytes(max_n).
 size_t segment_digest_scratch_bytes(uint64_t max_n);
+// out[0] = the longest of the segments [ends[j-1], ends[j]) of a buffer of
+// len bytes, j < *n_dev <= max_n (0 when there are none).
+hipError_t launch_max_gap(const uint64_t *ends, uint64_t len, const uint64_t *n_dev, uint64_t max_n, uint64_t *out,
+                          hipStream_t s);
+// Record k (d bytes) of src to out + idx[k] * d, k < n.
+hipError_t launch_digest_scatter(const uint64_t *idx, const uint8_t *src, uint64_t n, int d, uint8_t *out,
+                                 hipStream_t s);
 hipError_t launch_segment_digests(int kind, const uint8_t *in, uint64_t len, const uint64_t *starts,
                                   const uint64_t *ends, const uint64_t *n_dev, uint64_t max_n, uint8_t *out,
                                   void *scratch, hipStream_t s);

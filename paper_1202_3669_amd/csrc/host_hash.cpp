@@ -215,8 +215,9 @@ struct Job {
 class Pool {
   public:
     Pool() {
+        // One thread per host core but the caller's, at most 15.
         const unsigned hw = std::thread::hardware_concurrency();
-        const int n = (int)std::max(1u, std::min(8u, hw ? hw : 1u));
+        const int n = (int)std::max(1u, std::min(15u, hw > 1 ? hw - 1 : 1u));
         for (int i = 0; i < n; i++) threads_.emplace_back([this] { work(); });
     }
     ~Pool() {
