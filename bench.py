@@ -61,6 +61,9 @@ AHEAD = 12  # steps issued ahead of the last finished chunking
 LONG_STREAMS = 3  # streams for the per-step 1 MiB segment launches (round-robin)
 ROOT_WORKERS = 2  # host threads (each with a stream) computing the second levels
 SLOTS = 10        # ring of per-step output buffers
+SERVE_SLOTS = 4        # serving: workers (groups in flight)
+SERVE_GROUP_MIB = 2048  # serving: payload bytes per group
+SERVE_GROUP_REQ = 2048  # serving: requests per group
 
 
 def padded_blocks(n):
@@ -95,6 +98,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-file batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-slots", type=int, default=SERVE_SLOTS, help="serving: workers (groups in flight)")
+    ap.add_argument("--serve-group-mib", type=int, default=SERVE_GROUP_MIB, help="serving: MiB per group")
     ap.add_argument("--no-sweep", action="store_true", help="skip the similarity workload and block-size sweep")
     ap.add_argument("--no-dedup", action="store_true", help="skip the block-map write path over versions")
     ap.add_argument("--leaf-probe", action="store_true",
@@ -520,7 +525,9 @@ def breakdown(torch, hg, data, host_pinned):
                 outs = []
                 for a in range(0, n, 64 * MiB):
                     piece = src[a:a + 64 * MiB] if where == "device" else src[a:a + 64 * MiB].numpy()
-                    outs.append(ch.feed(piece, asynchronous=bool(mode)))
+                    # the resident input is complete: device feeds need not
+                    # wait for the previous feed's digests (HG_IN_READY)
+                    outs.append(ch.feed(piece, asynchronous=bool(mode), ready=where == "device"))
                 outs.append(ch.finish(asynchronous=bool(mode)))
                 return outs
             stream_all()  # warm-up: scratch sized once
@@ -778,7 +785,8 @@ def serving(torch, hg, inputs, data, host_pinned, n_req):
     total = float(sizes.sum())
     mean = total / n_req
     rs = hg.RequestSet(data.data_ptr(), True, specs)
-    srv = hg.Server(0, slots=3, max_requests=1024, device_budget=4 * GiB, max_group_bytes=1 * GiB)
+    srv = hg.Server(0, slots=SERVE_SLOTS, max_requests=SERVE_GROUP_REQ, device_budget=4 * GiB,
+                    max_group_bytes=SERVE_GROUP_MIB * MiB)
     zeros = np.zeros(n_req)
     srv.play(rs, zeros)  # warm-up: every group's buffers touched once
 
@@ -791,7 +799,8 @@ def serving(torch, hg, inputs, data, host_pinned, n_req):
         return total / wall / 1e9, srv.stats()
 
     peak, st = burst(rs)
-    res = {"requests": n_req, "bytes": int(total), "mean_request_bytes": int(mean),
+    res = {"requests": n_req, "bytes": int(total), "mean_request_bytes": int(mean), "workers": SERVE_SLOTS,
+           "max_group_bytes": SERVE_GROUP_MIB * MiB, "max_group_requests": SERVE_GROUP_REQ,
            "peak_GBps": round(peak, 1), "peak_groups": int(st["groups"]), "loads": []}
 
     def at_load(load, reqs=rs, ref=None):
@@ -880,7 +889,7 @@ def main():
     # Many concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
     # chunking streams + window + SB + S1 streams + root streams + default
-    queues = max(8, args.chunk_streams + 3 + LONG_STREAMS + ROOT_WORKERS)
+    queues = min(32, max(8, args.chunk_streams + 3 + LONG_STREAMS + ROOT_WORKERS, 2 * args.serve_slots + 2))
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import numpy as np
@@ -920,7 +929,8 @@ def main():
     del prev
     torch.cuda.synchronize()
 
-    global CHUNK_STREAMS, CHUNK_CALLS, AHEAD
+    global CHUNK_STREAMS, CHUNK_CALLS, AHEAD, SERVE_SLOTS, SERVE_GROUP_MIB
+    SERVE_SLOTS, SERVE_GROUP_MIB = args.serve_slots, args.serve_group_mib
     CHUNK_STREAMS = args.chunk_streams
     CHUNK_CALLS = args.chunk_calls
     AHEAD = args.ahead

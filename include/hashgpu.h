@@ -74,7 +74,8 @@ enum {
 
 /* Flags.  HG_LEN_ENDS applies to hg_similarity and hg_blockmap_write only; HG_BACKGROUND to the
  * batch calls only; HG_COUNT_HOST to hg_chunk and the chunker's feed and finish only;
- * HG_HOST_ROOTS to hg_roots_batch and hg_block_hash_batch only. */
+ * HG_HOST_ROOTS to hg_roots_batch and hg_block_hash_batch only; HG_IN_READY to the chunker's
+ * feed only. */
 enum {
     HG_IN_DEVICE = 1u,
     HG_OUT_DEVICE = 2u,
@@ -82,7 +83,8 @@ enum {
     HG_LEN_ENDS = 8u,
     HG_BACKGROUND = 16u,
     HG_COUNT_HOST = 32u,
-    HG_HOST_ROOTS = 64u
+    HG_HOST_ROOTS = 64u,
+    HG_IN_READY = 128u
 };
 
 /* Limits of the sliding-window primitive. */
@@ -442,9 +444,16 @@ int hg_chunker_bound(const hg_chunker *c, uint64_t len, uint64_t *bound);
  * and the cuts decided, and ends[], the digests and a device *n_chunks are
  * written in stream order on `stream`, valid after it synchronizes.  The
  * input may be reused when the call returns; the outputs may not be read
- * or reused before the stream synchronizes.  The digests left running are
- * then overlapped with the next feed's host-to-device copy.  HG_EINVAL when
- * capacity < hg_chunker_bound, or HG_ASYNC without HG_OUT_DEVICE. */
+ * or reused before the stream synchronizes.  A feed's copy, window scan
+ * and boundary decision run on a stream of the chunker's own and end with
+ * one host wait; its ends, digests and count are written on `stream`, so
+ * with HG_ASYNC the digests left running overlap the next feed's copy and
+ * window scan.  Device input is read after the work already queued on
+ * `stream` (which may produce it) -- that includes the previous feed's
+ * digests -- unless the caller passes HG_IN_READY: the device input is
+ * complete when the call is made (nothing pending on `stream` writes it).
+ * HG_EINVAL when capacity < hg_chunker_bound, or HG_ASYNC without
+ * HG_OUT_DEVICE. */
 int hg_chunker_feed(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends,
                     uint64_t capacity, uint64_t *n_chunks, void *chunk_digests, void *stream);
 
@@ -526,11 +535,15 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
  * buffer).  A worker that becomes idle takes the waiting requests from the
  * head of the queue, in arrival order, while they fit its group and the
  * device staging budget, and runs them as one group: one persistent launch
- * for the segment digests of all its block requests, the second levels in
- * one launch, and the sliding-window chunking of all its chunk requests
+ * for the segment digests of all its block requests (their second levels
+ * then on the host's cores, as Sec. 3.2.2 places them, from the digests
+ * copied back), and the sliding-window chunking of all its chunk requests
  * through one tile map.  Groups of different workers overlap on the device;
  * a request that arrives while groups run joins the next group that frees
- * up, without waiting for the others to drain.
+ * up, without waiting for the others to drain.  A request that does not fit
+ * an empty group -- and a chunk request of more than 32 MiB, whose boundary
+ * decision the single call makes faster -- is served alone by a worker
+ * through the single-call entry point.
  *
  * Admission by device memory: a payload in host memory is admitted only
  * when its bytes fit the staging region (device_budget bytes, allocated once

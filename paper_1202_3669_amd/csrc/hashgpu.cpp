@@ -2033,24 +2033,42 @@ struct hg_chunker {
     int cur = 0;            // buffer holding [cur_start, pos)
     uint64_t cur_start = 0; // absolute offset of buf[cur][0]
     bool finished = false;
+    // A feed's front half (copy, window scan, boundary decision) runs on the
+    // chunker's own stream and ends with one host wait; its back half (ends,
+    // chunk digests, counts) on the caller's stream, so that it overlaps
+    // the next feed's front half.  Per buffer b: the cut list (rel[b]), the
+    // device words of the decision (state + 8 * b), and an event after the
+    // back half that last read buffer b.
+    hipStream_t front = nullptr;
+    hipEvent_t ev_entry = nullptr, ev_front = nullptr, ev_dig[2] = {nullptr, nullptr};
+    uint64_t *rel[2] = {nullptr, nullptr};
+    uint64_t relcap[2] = {0, 0};
+    uint64_t *state = nullptr;  // 32 device words
 };
 
 namespace {
 
-int chunker_grow(hg_chunker *c, int i, uint64_t bytes, hipStream_t st) {
-    if (c->cap[i] >= bytes) return HG_OK;
+// Grows chunker buffer `i` (the working bytes, or with `ends` its cut list)
+// to `bytes`: both streams are drained first, since the front stream writes
+// it and the caller's stream may still read it.
+int chunker_grow(hg_chunker *c, int i, uint64_t bytes, hipStream_t st, bool ends = false) {
+    uint64_t &cap = ends ? c->relcap[i] : c->cap[i];
+    if (cap >= bytes) return HG_OK;
     const uint64_t want = std::max<uint64_t>(bytes + bytes / 4, 1 << 20);
     HG_HIP(c->ctx, hipStreamSynchronize(st));
-    if (c->buf[i]) HG_HIP(c->ctx, hipFree(c->buf[i]));
-    c->buf[i] = nullptr;
-    c->cap[i] = 0;
+    HG_HIP(c->ctx, hipStreamSynchronize(c->front));
+    void *&ptr = ends ? (void *&)c->rel[i] : (void *&)c->buf[i];
+    if (ptr) HG_HIP(c->ctx, hipFree(ptr));
+    ptr = nullptr;
+    cap = 0;
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
         (void)hipGetLastError();
         return fail(c->ctx, HG_ENOMEM, "chunker buffer of %llu bytes", (unsigned long long)want);
     }
-    c->buf[i] = (uint8_t *)p;
-    c->cap[i] = want;
+    c->ctx->n_device_allocs++;
+    ptr = p;
+    cap = want;
     return HG_OK;
 }
 
@@ -2061,13 +2079,23 @@ uint64_t chunker_bound(const hg_chunker *c, uint64_t len) {
     return span / step + 2 + (c->p.max_chunk ? span / c->p.max_chunk + 1 : 0);
 }
 
+// Room for a feed's candidates before it learns their number: twice the
+// expectation for random bytes (mask bits) plus slack, at most one per
+// window; a feed that finds more is redone with exact room.
+uint64_t chunker_cand_room(const hg_chunk_params &p, uint64_t nwin) {
+    const int bits = __builtin_popcount(p.mask);
+    const uint64_t expect = bits >= 63 ? 0 : (nwin >> bits);
+    return std::min<uint64_t>(nwin, 2 * expect + 4096);
+}
+
 int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, uint64_t *ends, uint64_t capacity,
                  uint64_t *n_out, void *digests, void *stream, bool final) {
     hg_ctx *ctx = c->ctx;
     HG_TRY(enter(ctx));
     const bool count_host = flags & HG_COUNT_HOST;
     const bool async = flags & HG_ASYNC;
-    flags &= ~(uint32_t)(HG_COUNT_HOST | HG_ASYNC);
+    const bool ready = flags & HG_IN_READY;
+    flags &= ~(uint32_t)(HG_COUNT_HOST | HG_ASYNC | HG_IN_READY);
     HG_TRY(check_flags(ctx, flags, false));
     if (async && !(flags & HG_OUT_DEVICE)) return fail(ctx, HG_EINVAL, "HG_ASYNC requires HG_OUT_DEVICE");
     if (c->finished) return fail(ctx, HG_EINVAL, "the stream is finished (hg_chunker_reset starts a new one)");
@@ -2078,39 +2106,49 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         return fail(ctx, HG_EINVAL, "capacity %llu below the bound %llu (hg_chunker_bound)",
                     (unsigned long long)capacity, (unsigned long long)bound);
     if (!ends) return fail(ctx, HG_EINVAL, "ends is NULL");
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = (hipStream_t)stream, F = c->front;
     const bool in_dev = flags & HG_IN_DEVICE, out_dev = flags & HG_OUT_DEVICE;
     const hg_chunk_params &p = c->p;
     // The working buffer: carry [base, pos) then the new bytes.
     const uint64_t carry = c->pos - c->base, wlen = carry + len;
     const int nxt = 1 - c->cur;
     HG_TRY(chunker_grow(c, nxt, wlen, st));
+    HG_TRY(chunker_grow(c, nxt, bound * 8, st, true));
     uint8_t *W = c->buf[nxt];
-    if (carry) HG_HIP(ctx, hipMemcpyAsync(W, c->buf[c->cur] + (c->base - c->cur_start), carry,
-                                           hipMemcpyDeviceToDevice, st));
+    uint64_t *rel = c->rel[nxt], *sw = c->state + 8 * nxt;
+    // Buffer nxt, its cut list and its state words were last read by the
+    // back half of the feed before the previous one.
+    HG_HIP(ctx, hipStreamWaitEvent(F, c->ev_dig[nxt], 0));
+    // Device input may be written by work still pending on the caller's
+    // stream, unless the caller declares it ready.
     const bool host_in = len && !in_dev;
-    if (len && in_dev) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, hipMemcpyDeviceToDevice, st));
+    if (len && in_dev && !ready) {
+        HG_HIP(ctx, hipEventRecord(c->ev_entry, st));
+        HG_HIP(ctx, hipStreamWaitEvent(F, c->ev_entry, 0));
+    }
+    if (carry) HG_HIP(ctx, hipMemcpyAsync(W, c->buf[c->cur] + (c->base - c->cur_start), carry,
+                                           hipMemcpyDeviceToDevice, F));
+    if (len && in_dev) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, hipMemcpyDeviceToDevice, F));
     const uint64_t a0 = c->base, last0 = c->last - a0;
     // Windows on the stream's stride grid: the first at an absolute multiple
     // of the stride at or after a0.
     const uint64_t s_ = p.stride, b0 = (s_ - a0 % s_) % s_;
-    uint64_t *small;
-    HG_TRY(small_words(ctx, st, &small));
-    uint64_t n_cand = 0;
-    void *cand = nullptr;
-    if (wlen >= b0 + p.window) {
-        const hg::WsPlan plan = hg::plan_window_scan(W + b0, wlen - b0, p.window, s_, p.window_digest);
-        void *ws;
-        HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), st, &ws));
+    const uint64_t step = p.min_chunk ? p.min_chunk : 1;
+    const bool has_windows = wlen >= b0 + p.window;
+    const bool parallel = p.max_chunk == 0 && (step >= p.window || last0 == 0);
+    hg::WsPlan plan{};
+    void *ws = nullptr, *cand = nullptr;
+    if (has_windows) {
+        plan = hg::plan_window_scan(W + b0, wlen - b0, p.window, s_, p.window_digest);
+        HG_TRY(ensure(ctx, SLOT_WS, hg::window_scan_scratch_bytes(plan), F, &ws));
         if (host_in) {
-            // Host bytes arrive in pieces; the tiles whose windows have
-            // landed run while later pieces are copied.  The copies land in
-            // this feed's buffer past the carry, which no pending work on
-            // st reads (the previous feed's digests, left running by
-            // HG_ASYNC, read the other buffer; everything before them ended
-            // at that feed's cut decision), so they need not wait for st.
+            // Host bytes arrive in pieces on the copy stream (after the back
+            // half that last read this buffer); the tiles whose windows have
+            // landed run while later pieces are copied.
+            HG_TRY(ensure_copy_stream(ctx));
+            HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, c->ev_dig[nxt], 0));
             uint64_t t_done = 0;
-            HG_TRY(stream_in(ctx, W + carry, (const uint8_t *)data, len, 1, st,
+            HG_TRY(stream_in(ctx, W + carry, (const uint8_t *)data, len, 1, F,
                              [&](uint64_t off, uint64_t plen) -> int {
                                  const uint64_t avail = carry + off + plen;
                                  uint64_t t_end = plan.n_tiles;
@@ -2120,70 +2158,85 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                                      t_end = std::min<uint64_t>(nw / plan.tile_windows, plan.n_tiles);
                                  }
                                  if (t_end > t_done) {
-                                     HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
+                                     HG_LAUNCH(ctx, HG_K_WINDOW_TILES, F,
                                                hg::launch_window_scan_tile_range(plan, W + b0, wlen - b0, p.window,
                                                                                  s_, p.mask, p.target, ws, t_done,
-                                                                                 t_end, st));
+                                                                                 t_end, F));
                                      t_done = t_end;
                                  }
                                  return HG_OK;
                              },
                              SCAN_PIECE, false));
         } else {
-            HG_LAUNCH(ctx, HG_K_WINDOW_TILES, st,
-                      hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, st));
+            HG_LAUNCH(ctx, HG_K_WINDOW_TILES, F,
+                      hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, F));
         }
-        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st, hg::launch_window_scan_prefix(plan, ws, &small[0], st));
-        HG_TRY(read_u64(ctx, &small[0], st, &n_cand));
-        if (n_cand >= hg::MAX_LANES)
+        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, F, hg::launch_window_scan_prefix(plan, ws, &sw[0], F));
+    } else {
+        if (host_in) {
+            HG_TRY(ensure_copy_stream(ctx));
+            HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, c->ev_dig[nxt], 0));
+            HG_TRY(stream_in(ctx, W + carry, (const uint8_t *)data, len, 1, F,
+                             [](uint64_t, uint64_t) { return (int)HG_OK; }, SCAN_PIECE, false));
+        }
+        HG_HIP(ctx, hg::launch_fill_u32((uint32_t *)&sw[0], 2, 0, F));
+    }
+    // The rest of the front half with candidate room from the expectation
+    // (counts stay on the device); one host wait at the end reads the
+    // candidate total and the decision.  With more candidates than room the
+    // decision is redone with exact room.
+    uint64_t room = has_windows ? chunker_cand_room(p, plan.nwin) : 0;
+    uint64_t k = 0, last_w = 0;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(room, 1) * 8, F, &cand));
+        if (has_windows)
+            HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, F,
+                      hg::launch_window_scan_emit(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws,
+                                                  (uint64_t *)cand, room, F));
+        // sw[6] = min(total, room), sw[7] = total > room
+        HG_HIP(ctx, hg::launch_count_clamp(&sw[0], room, &sw[6], F));
+        if (parallel) {
+            // The parallel boundary decision, on the candidates that can
+            // still be cuts, shifted so that the carried cut is offset 0;
+            // its final chunk is provisional unless the stream ends here.
+            // (With step >= w no window that starts before the carried cut
+            // can still be a cut, so the shifted starts stay non-negative;
+            // otherwise the walk below decides.)
+            HG_HIP(ctx, hg::launch_stream_drop((const uint64_t *)cand, &sw[6], b0, p.window, last0 + step, &sw[4], F));
+            void *shifted, *sel;
+            HG_TRY(ensure(ctx, SLOT_AUX, std::max<uint64_t>(room, 1) * 8, F, &shifted));
+            HG_HIP(ctx, hg::launch_stream_shift((const uint64_t *)cand, &sw[4], room, b0, last0, (uint64_t *)shifted,
+                                                F));
+            HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(room), F, &sel));
+            HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, F,
+                      hg::launch_chunk_select((const uint64_t *)shifted, &sw[5], room, p.window, wlen - last0,
+                                              p.min_chunk, sel, rel, bound, &sw[1], F));
+            HG_HIP(ctx, hg::launch_stream_tail(&sw[1], rel, final, last0, &sw[2], F));
+        } else {
+            HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, F,
+                      hg::launch_stream_walk((const uint64_t *)cand, &sw[6], b0, p.window, wlen, last0, p.min_chunk,
+                                             p.max_chunk, final, rel, bound, &sw[2], F));
+        }
+        HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, sw, 32, hipMemcpyDeviceToHost, F));
+        HG_HIP(ctx, hipStreamSynchronize(F));
+        const uint64_t total = ctx->host_small[0];
+        k = ctx->host_small[2];
+        last_w = ctx->host_small[3];
+        if (total >= hg::MAX_LANES)
             return fail(ctx, HG_EINVAL, "%llu candidates in one feed (limit 2^31): feed smaller pieces",
-                        (unsigned long long)n_cand);
-        HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(n_cand, 1) * 8, st, &cand));
-        HG_LAUNCH(ctx, HG_K_WINDOW_EMIT, st,
-                  hg::launch_window_scan_emit(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws,
-                                              (uint64_t *)cand, n_cand, st));
-    } else {
-        if (host_in) HG_HIP(ctx, hipMemcpyAsync(W + carry, data, len, hipMemcpyHostToDevice, st));
-        HG_TRY(ensure(ctx, SLOT_CAND, 8, st, &cand));
-        HG_HIP(ctx, hg::launch_fill_u32((uint32_t *)&small[0], 2, 0, st));
+                        (unsigned long long)total);
+        if (total <= room) break;
+        room = total;  // more candidates than expected: once more with exact room
     }
-    void *rel;
-    HG_TRY(ensure(ctx, SLOT_ENDS, bound * 8, st, &rel));
-    const uint64_t step = p.min_chunk ? p.min_chunk : 1;
-    if (p.max_chunk == 0 && n_cand > 0 && (step >= p.window || last0 == 0)) {
-        // The parallel boundary decision, on the candidates that can still
-        // be cuts, shifted so that the carried cut is offset 0; its final
-        // chunk is provisional unless the stream ends here.  (With step >= w
-        // no window that starts before the carried cut can still be a cut,
-        // so the shifted starts stay non-negative; otherwise the walk below
-        // decides.)
-        HG_HIP(ctx, hg::launch_stream_drop((const uint64_t *)cand, &small[0], b0, p.window, last0 + step, &small[4],
-                                           st));
-        uint64_t kept;
-        HG_TRY(read_u64(ctx, &small[5], st, &kept));
-        void *shifted, *sel;
-        HG_TRY(ensure(ctx, SLOT_AUX, std::max<uint64_t>(kept, 1) * 8, st, &shifted));
-        HG_HIP(ctx, hg::launch_stream_shift((const uint64_t *)cand, &small[4], kept, b0, last0, (uint64_t *)shifted,
-                                            st));
-        HG_TRY(ensure(ctx, SLOT_SEL, hg::chunk_select_scratch_bytes(kept), st, &sel));
-        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
-                  hg::launch_chunk_select((const uint64_t *)shifted, &small[5], kept, p.window, wlen - last0,
-                                          p.min_chunk, sel, (uint64_t *)rel, bound, &small[6], st));
-        HG_HIP(ctx, hg::launch_stream_tail(&small[6], (const uint64_t *)rel, final, last0, &small[2], st));
-    } else {
-        HG_LAUNCH(ctx, HG_K_CHUNK_SELECT, st,
-                  hg::launch_stream_walk((const uint64_t *)cand, &small[0], b0, p.window, wlen, last0, p.min_chunk,
-                                         p.max_chunk, final, (uint64_t *)rel, bound, &small[2], st));
-    }
-    HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, &small[2], 16, hipMemcpyDeviceToHost, st));
-    HG_HIP(ctx, hipStreamSynchronize(st));
-    const uint64_t k = ctx->host_small[0], last_w = ctx->host_small[1];
     if (k > bound) return fail(ctx, HG_EDEVICE, "internal: %llu cuts above the bound", (unsigned long long)k);
-    // Outputs: absolute ends, digests of the completed chunks.
+    // Back half on the caller's stream: absolute ends, digests of the
+    // completed chunks, the count.
+    HG_HIP(ctx, hipEventRecord(c->ev_front, F));
+    HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
     const uint64_t abs_add = a0 + last0;
     if (k) {
         if (out_dev) {
-            HG_HIP(ctx, hg::launch_add_u64(ends, (const uint64_t *)rel, &small[2], bound, abs_add, st));
+            HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], bound, abs_add, st));
         } else {
             HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
         }
@@ -2191,13 +2244,13 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
             const int dd = digest_bytes(p.chunk_digest);
             void *ddig = digests;
             if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
-            HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, (const uint64_t *)rel, &small[2], k,
-                                    (uint8_t *)ddig, st));
+            HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], k, (uint8_t *)ddig, st));
             if (!out_dev) HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
         }
     }
-    if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &small[2], 8, hipMemcpyDeviceToDevice, st));
+    if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
     else *n_out = k;
+    HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
     if (!async) HG_HIP(ctx, hipStreamSynchronize(st));
     if (!out_dev)
         for (uint64_t i = 0; i < k; i++) ends[i] += abs_add;
@@ -2231,6 +2284,20 @@ int hg_chunker_create(hg_ctx *ctx, const hg_chunk_params *params, hg_chunker **o
     hg_chunker *c = new hg_chunker();
     c->ctx = ctx;
     c->p = p;
+    bool ok = hipStreamCreateWithFlags(&c->front, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_entry, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_front, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_dig[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_dig[1], hipEventDisableTiming) == hipSuccess &&
+              hipMalloc((void **)&c->state, 32 * 8) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        hg_chunker_destroy(c);
+        return fail(ctx, HG_EDEVICE, "chunker stream, events or state could not be created");
+    }
+    ctx->n_device_allocs++;
+    // Both buffers start "read": the first waits on them are immediate.
+    for (hipEvent_t e : c->ev_dig) HG_HIP(ctx, hipEventRecord(e, c->front));
     *out = c;
     return HG_OK;
 }
@@ -2264,8 +2331,15 @@ void hg_chunker_destroy(hg_chunker *c) {
     if (!c) return;
     (void)hipSetDevice(c->ctx->device);
     (void)hipDeviceSynchronize();
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 2; i++) {
         if (c->buf[i]) (void)hipFree(c->buf[i]);
+        if (c->rel[i]) (void)hipFree(c->rel[i]);
+        if (c->ev_dig[i]) (void)hipEventDestroy(c->ev_dig[i]);
+    }
+    if (c->state) (void)hipFree(c->state);
+    if (c->ev_entry) (void)hipEventDestroy(c->ev_entry);
+    if (c->ev_front) (void)hipEventDestroy(c->ev_front);
+    if (c->front) (void)hipStreamDestroy(c->front);
     delete c;
 }
 

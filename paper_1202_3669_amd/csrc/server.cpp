@@ -11,16 +11,18 @@
 // staging region, and enqueues the whole group:
 //   - host payloads are copied into the staging region (device-memory
 //     admission: a request waits at the head until its bytes fit);
-//   - block requests: one job table, one persistent segment-digest launch
-//     for all of them (MD5 and SHA-1 mixed), one launch for the second
-//     levels -- on the helper stream;
+//   - block requests: one job table and one persistent segment-digest
+//     launch for all of them (MD5 and SHA-1 mixed) on the helper stream;
+//     their segment digests come back whole and the worker computes the
+//     second levels on the host pool (Sec. 3.2.2);
 //   - chunk requests (same parameters within a group): one tile map over
 //     all payloads, the window scan, per-file boundary selection, compaction
 //     and the chunk digests -- on the main stream;
 //   - one copy of the results back to the pinned buffer.
 // While a worker waits for its group, the other workers form and launch
 // theirs, so requests that arrive meanwhile overlap on the device with the
-// groups in flight.  A request that does not fit an empty group runs alone
+// groups in flight.  A request that does not fit an empty group (or a chunk
+// request of more than SOLO_CHUNK_BYTES) runs alone
 // through the single-call entry points on the worker's context.
 //
 // Payload addressing in a group: chunk payloads are described as offsets
@@ -45,6 +47,7 @@
 #include "hashgpu.h"
 #include "hg_internal.hpp"
 #include "hg_ranges.hpp"
+#include "host_hash.hpp"
 
 namespace {
 
@@ -73,6 +76,12 @@ constexpr size_t LAT_WINDOW = 1u << 20;  // completions the latency statistics c
 // bytes (a group's segment-digest slots are sized for it); smaller segments
 // run alone.
 constexpr uint64_t TL_MIN_SEGMENT = 4096;
+// Chunk requests longer than this are served alone: a group decides each
+// file's boundaries with one wavefront walking its candidates cut by cut
+// (~0.1 us a cut: ~5 ms for 256 MiB at the configured parameters, on the
+// group's critical path), while the single call's parallel speculative
+// selection takes well under a millisecond.
+constexpr uint64_t SOLO_CHUNK_BYTES = 32ull << 20;
 
 int dbytes(int d) { return d == HG_MD5 ? 16 : (d == HG_SHA1 ? 20 : -1); }
 uint64_t up256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -125,7 +134,7 @@ struct Group {
     std::vector<void *> dev_allocs;
     hg_block_job *d_jobs = nullptr;
     void *d_plan = nullptr, *d_ws = nullptr, *d_seg = nullptr;
-    uint8_t *d_leaves = nullptr, *d_roots = nullptr, *d_cdig = nullptr;
+    uint8_t *d_leaves = nullptr, *d_cdig = nullptr;
     uint64_t *d_off = nullptr, *d_len = nullptr, *d_first_tile = nullptr;
     hg::FileTile *d_tiles = nullptr;
     uint64_t *d_cand = nullptr, *d_slots = nullptr, *d_seg_start = nullptr, *d_seg_end = nullptr;
@@ -140,7 +149,7 @@ struct Group {
     uint64_t *h_off = nullptr, *h_len = nullptr, *h_first_tile = nullptr;
     hg::FileTile *h_tiles = nullptr;
     uint64_t *h_status = nullptr, *h_chunk_off = nullptr, *h_ends = nullptr;
-    uint8_t *h_leaves = nullptr, *h_roots = nullptr, *h_cdig = nullptr;
+    uint8_t *h_leaves = nullptr, *h_cdig = nullptr;
     // the group being served
     std::vector<Req *> blocks, chunks, failed;
     Req *solo = nullptr;
@@ -258,7 +267,6 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
     GA(d_jobs, hg_block_job *, (size_t)g.R * sizeof(hg_block_job));
     GA(d_plan, void *, hg::batch_plan_bytes(g.R));
     GA(d_leaves, uint8_t *, g.leaf_cap);
-    GA(d_roots, uint8_t *, (size_t)g.R * 20);
     GA(d_off, uint64_t *, (size_t)g.R * 8);
     GA(d_len, uint64_t *, (size_t)g.R * 8);
     GA(d_first_tile, uint64_t *, (size_t)(g.R + 1) * 8);
@@ -279,7 +287,7 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
     GA(d_status, uint64_t *, 64);
 #undef GA
     // Pinned host buffer, carved in 256-byte aligned pieces.
-    const uint64_t sizes[11] = {(uint64_t)g.R * sizeof(hg_block_job),
+    const uint64_t sizes[10] = {(uint64_t)g.R * sizeof(hg_block_job),
                                 (uint64_t)g.R * 8,
                                 (uint64_t)g.R * 8,
                                 (uint64_t)(g.R + 1) * 8,
@@ -287,7 +295,6 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
                                 64,
                                 (uint64_t)(g.R + 1) * 8,
                                 g.leaf_cap,
-                                (uint64_t)g.R * 20,
                                 g.max_chunks * 8,
                                 g.max_chunks * 20};
     uint64_t total = 0;
@@ -297,9 +304,9 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
         g.h = nullptr;
         return HG_ENOMEM;
     }
-    uint8_t *piece[11];
+    uint8_t *piece[10];
     uint8_t *q = g.h;
-    for (int i = 0; i < 11; i++) {
+    for (int i = 0; i < 10; i++) {
         piece[i] = q;
         q += up256(sizes[i]);
     }
@@ -311,9 +318,8 @@ int group_init(Group &g, int device, const hg_server_cfg &cfg) {
     g.h_status = (uint64_t *)piece[5];
     g.h_chunk_off = (uint64_t *)piece[6];
     g.h_leaves = piece[7];
-    g.h_roots = piece[8];
-    g.h_ends = (uint64_t *)piece[9];
-    g.h_cdig = piece[10];
+    g.h_ends = (uint64_t *)piece[8];
+    g.h_cdig = piece[9];
     return HG_OK;
 }
 
@@ -329,7 +335,8 @@ bool fits(const Group &g, const hg_server_cfg &cfg, const Req *q) {
     // A maximum chunk size needs per-file room for forced cuts, and two-level
     // chunk digests with short segments more slots than a group holds: such
     // requests are served alone.
-    if (r.chunk.max_chunk != 0 || (r.chunk.chunk_segment != 0 && r.chunk.chunk_segment < TL_MIN_SEGMENT))
+    if (r.chunk.max_chunk != 0 || (r.chunk.chunk_segment != 0 && r.chunk.chunk_segment < TL_MIN_SEGMENT) ||
+        r.len > SOLO_CHUNK_BYTES)
         return false;
     if (!g.chunks.empty() && !same_chunk_params(g.cp, r.chunk)) return false;
     return g.tiles + n.tiles <= g.tile_cap && g.cand + n.cand <= g.cand_cap;
@@ -400,10 +407,13 @@ int stage_in(Group &g, const Req *q) {
     return HG_OK;
 }
 
-// The direct hash of every block request of the group (helper stream).
-// Segment digests and second levels are laid out in member order; the job
-// table lists the members longest first, so that the persistent workers
-// start on the longest chains.
+// The segment digests of every block request of the group (helper stream),
+// laid out in member order and copied back whole; the second levels are
+// computed on the host from that copy once the group is done (Sec. 3.2.2
+// places that step on the CPU; a core runs the chain far faster than a GPU
+// lane, and the worker waits for the group anyway).  The job table lists
+// the members longest first, so that the persistent workers start on the
+// longest chains.
 int enqueue_blocks(Group &g, bool boost) {
     const uint32_t n = (uint32_t)g.blocks.size();
     std::vector<uint64_t> lofs(n);
@@ -426,7 +436,7 @@ int enqueue_blocks(Group &g, bool boost) {
         j.len = q->r.len;
         j.block_size = q->r.block_size;
         j.leaf_out = g.d_leaves + lofs[i];
-        j.root_out = q->r.root_out ? g.d_roots + (uint64_t)i * 20 : nullptr;
+        j.root_out = nullptr;
         j.digest = q->r.digest;
         j.reserved = 0;
     }
@@ -435,9 +445,7 @@ int enqueue_blocks(Group &g, bool boost) {
     SV_HIP(hg::launch_batch_plan(g.d_jobs, n, g.d_plan, st));
     const uint32_t grid = (uint32_t)std::max<uint64_t>(2, std::min<uint64_t>(8192, (total_leaves + 63) / 64 + 1));
     SV_HIP(hg::launch_leaves_batch(g.d_jobs, n, g.d_plan, grid, 2, boost, st));
-    SV_HIP(hg::launch_roots_batch(g.d_jobs, n, g.d_plan, boost, st));
     if (leaf_off) SV_HIP(hipMemcpyAsync(g.h_leaves, g.d_leaves, leaf_off, hipMemcpyDeviceToHost, st));
-    SV_HIP(hipMemcpyAsync(g.h_roots, g.d_roots, (size_t)n * 20, hipMemcpyDeviceToHost, st));
     return HG_OK;
 }
 
@@ -535,18 +543,29 @@ void execute(Group &g, bool boost) {
         for (Req *q : all) q->status = st;
         return;
     }
-    // Block results, in member order.
+    // Block results, in member order; the second levels on the host pool,
+    // longest first.
+    std::vector<uint64_t> lofs(g.blocks.size());
     uint64_t leaf_off = 0;
     for (size_t i = 0; i < g.blocks.size(); i++) {
         Req *q = g.blocks[i];
         const hg_request &r = q->r;
-        const int d = dbytes(r.digest);
-        const uint64_t lb = n_leaves(r) * (uint64_t)d;
+        const uint64_t lb = n_leaves(r) * (uint64_t)dbytes(r.digest);
+        lofs[i] = leaf_off;
         if (r.leaf_out && lb) memcpy(r.leaf_out, g.h_leaves + leaf_off, lb);
-        if (r.root_out) memcpy(r.root_out, g.h_roots + i * 20, (size_t)d);
         leaf_off += lb;
         q->status = HG_OK;
     }
+    std::vector<size_t> by_len(g.blocks.size());
+    std::iota(by_len.begin(), by_len.end(), (size_t)0);
+    std::stable_sort(by_len.begin(), by_len.end(),
+                     [&](size_t a, size_t b) { return g.blocks[a]->r.len > g.blocks[b]->r.len; });
+    hg::host::parallel_for(by_len.size(), [&](uint64_t t) {
+        const hg_request &r = g.blocks[by_len[t]]->r;
+        if (r.root_out)
+            hg::host::digest(r.digest, g.h_leaves + lofs[by_len[t]], n_leaves(r) * (uint64_t)dbytes(r.digest),
+                             (uint8_t *)r.root_out);
+    });
     if (g.chunks.empty()) return;
     const uint64_t total = g.h_chunk_off[g.chunks.size()];
     if (g.h_status[2] != 0 || total > g.max_chunks) {

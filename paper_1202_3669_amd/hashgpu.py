@@ -25,6 +25,7 @@ HG_MD5, HG_SHA1 = 0, 1
 HG_OK, HG_EINVAL, HG_ENOMEM, HG_EDEVICE, HG_ETRUNC, HG_EBUSY = 0, -1, -2, -3, -4, -5
 HG_IN_DEVICE, HG_OUT_DEVICE, HG_ASYNC, HG_LEN_ENDS, HG_BACKGROUND, HG_COUNT_HOST = 1, 2, 4, 8, 16, 32
 HG_HOST_ROOTS = 64
+HG_IN_READY = 128
 HG_MAX_WINDOW = 4096
 DIGEST_SIZE = {HG_MD5: 16, HG_SHA1: 20}
 
@@ -878,7 +879,7 @@ class Chunker:
             return data.contiguous().numpy()
         return data
 
-    def _call(self, fn, data, stream):
+    def _call(self, fn, data, stream, ready=False):
         import numpy as np
         data = self._host_view(data)
         n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
@@ -893,7 +894,8 @@ class Chunker:
         cnt = _u64(0)
         if fn == "feed":
             ptr = (data.data_ptr() if is_dev else data.ctypes.data) if n else None
-            st = hg_chunker_feed(self.handle, ptr, n, HG_IN_DEVICE if is_dev else 0, ends.ctypes.data, cap,
+            fl = (HG_IN_DEVICE | (HG_IN_READY if ready else 0)) if is_dev else 0
+            st = hg_chunker_feed(self.handle, ptr, n, fl, ends.ctypes.data, cap,
                                  ctypes.byref(cnt), dig.ctypes.data, _stream_handle(stream))
         else:
             st = hg_chunker_finish(self.handle, 0, ends.ctypes.data, cap, ctypes.byref(cnt), dig.ctypes.data,
@@ -902,7 +904,7 @@ class Chunker:
         k = int(cnt.value)
         return ends[:k].copy(), dig[:k].copy()
 
-    def _call_async(self, fn, data, stream):
+    def _call_async(self, fn, data, stream, ready=False):
         import torch
         data = self._host_view(data)
         n = 0 if data is None else (data.numel() if hasattr(data, "numel") else data.size)
@@ -919,7 +921,8 @@ class Chunker:
             if n and not is_dev and not (data.flags["C_CONTIGUOUS"] and data.dtype.itemsize == 1):
                 raise ValueError("host input must be a contiguous uint8 array")
             ptr = (data.data_ptr() if is_dev else data.ctypes.data) if n else None
-            st = hg_chunker_feed(self.handle, ptr, n, flags | (HG_IN_DEVICE if is_dev else 0), ends.data_ptr(), cap,
+            fl = flags | ((HG_IN_DEVICE | (HG_IN_READY if ready else 0)) if is_dev else 0)
+            st = hg_chunker_feed(self.handle, ptr, n, fl, ends.data_ptr(), cap,
                                  cnt.data_ptr(), dig.data_ptr(), _stream_handle(stream))
         else:
             st = hg_chunker_finish(self.handle, flags, ends.data_ptr(), cap, cnt.data_ptr(), dig.data_ptr(),
@@ -928,8 +931,12 @@ class Chunker:
         return ends, dig, cnt
 
     @_on_stream
-    def feed(self, data, stream=None, asynchronous=False):
-        return self._call_async("feed", data, stream) if asynchronous else self._call("feed", data, stream)
+    def feed(self, data, stream=None, asynchronous=False, ready=False):
+        """ready: a CUDA tensor whose bytes are complete now (HG_IN_READY: the
+        feed need not wait for work pending on the stream before reading it)."""
+        if asynchronous:
+            return self._call_async("feed", data, stream, ready)
+        return self._call("feed", data, stream, ready)
 
     @_on_stream
     def finish(self, stream=None, asynchronous=False):

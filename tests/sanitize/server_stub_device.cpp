@@ -1,7 +1,8 @@
 // Stub device layer for the serving loop's ThreadSanitizer build: the
 // library calls server.cpp makes, with outputs that identify the request
 // they belong to.  A block job's segment digests are filled with the byte
-// (len * 7 + block_size) & 0xff and its root with (len * 13) & 0xff; chunk
+// (len * 7 + block_size) & 0xff and, when it runs alone, its root with
+// (len * 13) & 0xff; chunk
 // requests find no candidates (each is one chunk ending at its length when
 // run alone, none in a group, which the driver accounts for).
 #include <hip/hip_runtime.h>

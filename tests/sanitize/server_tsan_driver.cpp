@@ -5,7 +5,9 @@
 // throughout, injected failures, host payloads competing for a small
 // staging budget, requests larger than a group (served alone), and a stop
 // with requests still queued.  Every request's status and outputs are
-// checked against what the stub layer writes for it.
+// checked against what the stub layer writes for it (and, for the second
+// levels the worker computes on the host, against the host digest of the
+// segment digests).
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
@@ -16,6 +18,7 @@
 #include <vector>
 
 #include "hashgpu.h"
+#include "host_hash.hpp"
 
 namespace {
 
@@ -80,11 +83,19 @@ void check(const Out &o) {
                 g_bad++;
                 return;
             }
-        for (int i = 0; i < d; i++)
-            if (o.root[i] != (uint8_t)((r.len * 13) & 0xff)) {
-                g_bad++;
-                return;
-            }
+        // Grouped requests get their second level from the host hash of the
+        // segment digests; a request larger than a group runs alone through
+        // the stub's hg_block_hash, which writes a pattern.
+        uint8_t want[20];
+        if (r.len > (1u << 20)) {
+            memset(want, (uint8_t)((r.len * 13) & 0xff), sizeof want);
+        } else {
+            hg::host::digest(r.digest, o.leaves.data(), nl * d, want);
+        }
+        if (memcmp(o.root.data(), want, (size_t)d) != 0) {
+            g_bad++;
+            return;
+        }
     } else {
         // grouped: no candidates, no chunks; alone: one chunk ending at len
         if (!(o.n_chunks == 0 || (o.n_chunks == 1 && r.len && o.ends[0] == r.len))) g_bad++;

@@ -5,6 +5,7 @@ one-shot chunking of the whole stream (bit-exact ends and digests), for
 several window/stride/minimum/maximum settings.  Inputs: seeded uniform
 bytes, and bytes with long runs of zeros (no candidates for long stretches,
 so the carry grows and forced cuts happen)."""
+import hashlib
 import os
 import sys
 
@@ -171,7 +172,7 @@ ASYNC_CASES = [  # (length, w, s, mask, target, min, max, segment)
 
 
 @pytest.mark.parametrize("case", ASYNC_CASES)
-@pytest.mark.parametrize("where", ["device", "pinned", "pageable", "torch_pinned"])
+@pytest.mark.parametrize("where", ["device", "device_ready", "pinned", "pageable", "torch_pinned"])
 def test_stream_async_feeds(ctx, hg, case, where):
     # HG_ASYNC: every feed returns once its cuts are decided, its digests
     # still running; host input comes through ONE staging array that is
@@ -189,17 +190,19 @@ def test_stream_async_feeds(ctx, hg, case, where):
         stage = stage_t.numpy()
     else:
         stage = np.empty(max(big, 1), dtype=np.uint8)
-    dev = torch.from_numpy(data).cuda() if where == "device" else None
+    dev = torch.from_numpy(data).cuda() if where.startswith("device") else None
     ch = hg.Chunker(ctx, w, s, mask, target, mn, mx, chunk_segment=seg)
     outs = []
     for a, b in splits:
-        if where == "device":
+        if where.startswith("device"):
             piece = dev[a:b]
         else:
             stage[:b - a] = data[a:b]
             piece = stage_t[:b - a] if where == "torch_pinned" else stage[:b - a]  # CPU tensor or array
-        outs.append(ch.feed(piece, asynchronous=True))
-        if where != "device":
+        # device_ready: HG_IN_READY, the feed reads its input without waiting
+        # for the previous feed's digests on the stream
+        outs.append(ch.feed(piece, asynchronous=True, ready=where == "device_ready"))
+        if not where.startswith("device"):
             stage[:] = 0xA5  # the call has read its input
     outs.append(ch.finish(asynchronous=True))
     torch.cuda.synchronize()
@@ -261,3 +264,41 @@ def test_stream_async_reset_with_digests_pending(ctx, hg):
     got2_e = np.concatenate([e[:k].cpu().numpy().astype(np.uint64) for e, _, k in outs])
     got2_d = np.concatenate([d[:k].cpu().numpy() for _, d, k in outs])
     assert np.array_equal(got2_e, exp_ends) and np.array_equal(got2_d, exp_dig)
+
+
+def _candidate_window(seed):
+    # a 20-byte window whose MD5 has its low 12 bits (first word, little
+    # endian) zero: the boundary predicate holds for it
+    rng = np.random.default_rng(seed)
+    while True:
+        w = rng.integers(0, 256, 20, dtype=np.uint8).tobytes()
+        d = hashlib.md5(w).digest()
+        if int.from_bytes(d[:4], "little") & 0xFFF == 0:
+            return np.frombuffer(w, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("where", ["device", "pinned"])
+def test_stream_dense_candidates_redo(ctx, hg, where):
+    # A candidate window repeated: every 20th window is a candidate, far
+    # more than the room a feed sets aside for a 12-bit mask on random
+    # bytes, so each feed redoes its decision with exact room.  The stream
+    # still equals the one-shot result.
+    w0 = _candidate_window(560)
+    data = np.tile(w0, (3 * MiB) // 20 + 1)[:3 * MiB + 7].copy()
+    data[-7:] = 1
+    exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, 0)
+    assert exp_ends.size > 1000
+    note(f"dense candidates, {where} input")
+    src = torch.from_numpy(data).cuda() if where == "device" else torch.from_numpy(data).pin_memory()
+    ch = hg.Chunker(ctx)
+    outs = []
+    for a in range(0, data.size, MiB):
+        piece = src[a:a + MiB] if where == "device" else src[a:a + MiB].numpy()
+        outs.append(ch.feed(piece, asynchronous=True))
+    outs.append(ch.finish(asynchronous=True))
+    torch.cuda.synchronize()
+    got_e = np.concatenate([e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in outs])
+    got_d = np.concatenate([d[:int(c.item())].cpu().numpy() for _, d, c in outs])
+    ch.close()
+    assert np.array_equal(got_e, exp_ends)
+    assert np.array_equal(got_d, exp_dig)

@@ -110,7 +110,8 @@ def _build_server_driver(tmp_path, name, flags):
     subprocess.run([GXX, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", *flags,
                     "-I", os.path.join(stub, "stub"), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                     "-o", str(exe), os.path.join(stub, "server_tsan_driver.cpp"),
-                    os.path.join(stub, "server_stub_device.cpp"), os.path.join(CSRC, "server.cpp"), "-pthread"],
+                    os.path.join(stub, "server_stub_device.cpp"), os.path.join(CSRC, "server.cpp"),
+                    os.path.join(CSRC, "host_hash.cpp"), "-pthread"],
                    check=True)
     return exe
 
