@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--serve-group-mib", type=int, default=SERVE_GROUP_MIB, help="serving: MiB per group")
     ap.add_argument("--no-sweep", action="store_true", help="skip the similarity workload and block-size sweep")
     ap.add_argument("--no-dedup", action="store_true", help="skip the block-map write path over versions")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="only run the step's 4 KiB / 64 KiB segment batch five times (for rocprofv3 counters)")
     ap.add_argument("--leaf-probe", action="store_true",
                     help="only hash the 1 GiB input with one lane per segment (MD5/SHA-1, 4 KiB and "
                          "64 KiB segments, 3 launches each, no second level), for counter runs")
@@ -560,6 +562,19 @@ def breakdown(torch, hg, data, host_pinned):
         ts = timed(lambda: ctx.block_hash_dual(host_pinned, b, root=False), reps=5)
         res[f"md5+sha1_{b // KiB}k_with_h2d"] = {"GBps": round(n / statistics.median(ts) / 1e6, 1),
                                                  "ms_p50": round(pct(ts, 50), 2)}
+    # The step's persistent segment batch alone (4 KiB and 64 KiB segments,
+    # MD5 and SHA-1: four jobs in one launch), against the algorithmic work.
+    specs = [(data, b, k) for k, b in (BLOCK_JOBS[j] for j in SHORT)]
+    # (the leaf tensors stay referenced while the records point at them)
+    recs, leaves, _ = ctx.batch_outputs(specs, roots=False)
+    table = ctx.device_job_table(recs)
+    t = kernel_ms(lambda: ctx.run_batch(table, len(SHORT), "leaves"), name="leaves_batch")
+    ops = sum((n // b) * padded_blocks(b) * BLOCK_OPS[k] for _, b, k in specs)
+    singles = sum(res[f"{'sha1' if k else 'md5'}_{b // KiB}k"]["leaves_ms"] for _, b, k in specs)
+    res["segment_batch_4k_64k"] = {"kernel_ms": round(t, 3), "alu_frac": round(ops / (t / 1e3) / peak, 4),
+                                   "single_kernels_ms": round(singles, 3)}
+    torch.cuda.synchronize()
+    del table, recs, leaves
     # Measured ceilings beside the data-sheet ones.
     res["probes"] = {"int32_Tops_measured": round(ctx.probe_alu(), 2), "int32_Tops_spec": round(INT32_PEAK_TOPS, 2),
                      "hbm_read_GBps_measured": round(ctx.probe_read(data), 1), "hbm_GBps_spec": 8000.0}
@@ -698,7 +713,8 @@ def similarity_sweep(torch, hg, inputs):
         # Each fixed block direct-hashed by the two-level construction (4 KiB
         # segments): one batched call over all blocks, the roots are the ids.
         specs = [(b[o:o + size], 4 * KiB, hg.HG_SHA1) for o in range(0, nb, size)]
-        recs, _, roots_b = ctx.batch_outputs(specs)
+        # (leaves_b stays referenced: the records point at it)
+        recs, leaves_b, roots_b = ctx.batch_outputs(specs)
         table = ctx.device_job_table(recs)
         ctx.run_batch(table, len(specs), asynchronous=False)
         _, roots_a = ctx.block_hash_batch([(a[o:o + size], 4 * KiB, hg.HG_SHA1)
@@ -909,6 +925,20 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] pmc probe done; kernel_source_sha256: {kernel_source_hash()}",
               file=sys.stderr, flush=True)
+        return
+    if args.batch_probe:
+        # The step's persistent segment batch (4 KiB / 64 KiB, MD5 and
+        # SHA-1) five times, back to back on one stream, for counters.
+        data = torch.from_numpy(data_np).cuda()
+        with hg.Context(0) as c:
+            recs, leaves, _ = c.batch_outputs([(data, b, k) for k, b in (BLOCK_JOBS[j] for j in SHORT)],
+                                              roots=False)
+            table = c.device_job_table(recs)
+            for _ in range(5):
+                c.run_batch(table, len(SHORT), "leaves")
+            torch.cuda.synchronize()
+            del table, recs, leaves
+        print("[bench] batch probe done", file=sys.stderr, flush=True)
         return
     if args.leaf_probe:
         data = torch.from_numpy(data_np).cuda()

@@ -28,6 +28,29 @@
 
 namespace hg {
 
+// 64- and 128-byte loads (load_block, load_pair) through the global address
+// space, for pointers read from memory (job records): the compiler cannot
+// tell that such a generic pointer addresses global memory and would issue
+// flat loads, which may complete out of order, so that every wait on one of
+// them waits for all loads in flight.  Global loads complete in order and let a loop wait for the older
+// of two line buffers only.  p: any alignment, global (device or mapped
+// host) memory.
+typedef uint32_t hg_u32x4u __attribute__((ext_vector_type(4), aligned(1)));
+typedef const __attribute__((address_space(1))) hg_u32x4u *hg_gptr4;
+
+__device__ __forceinline__ void load_words_g(const uint8_t *p, uint32_t *X, int n16) {
+#pragma unroll
+    for (int i = 0; i < n16; i++) {
+        const hg_u32x4u v = ((hg_gptr4)p)[i];
+        X[4 * i] = v.x;
+        X[4 * i + 1] = v.y;
+        X[4 * i + 2] = v.z;
+        X[4 * i + 3] = v.w;
+    }
+}
+__device__ __forceinline__ void load_block_g(const uint8_t *p, uint32_t X[16]) { load_words_g(p, X, 4); }
+__device__ __forceinline__ void load_pair_g(const uint8_t *p, uint32_t X[32]) { load_words_g(p, X, 8); }
+
 struct Plan {
     uint32_t n_cls[2];           // jobs per digest kind
     uint32_t pad0[2];
@@ -197,8 +220,8 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                     done = 0;
                     phase = 0;
                     Hash<KIND>::init(st);
-                    if (n >= 128) load_pair(p, Y);
-                    else if (n >= 64) load_block(p, Y);
+                    if (n >= 128) load_pair_g(p, Y);
+                    else if (n >= 64) load_block_g(p, Y);
                 } else {
                     phase = 3;
                 }
@@ -215,7 +238,11 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
         // Fast path: every active lane has at least m full blocks left (the
         // next two already in Y), so m / 2 pair iterations need no tail
         // handling.  Lanes without work do not limit m; a lane in its tail
-        // makes m 0.
+        // makes m 0.  The loop alternates two line buffers (Y, Z) so that no
+        // buffer is copied per pair, and every lane loads unconditionally:
+        // a working lane's next pair, clamped to its last full pair (the
+        // surplus load of the last iteration is not used), an idle lane the
+        // start of the plan record (in bounds, not used).
         {
             const uint64_t fb = phase == 0 ? (n - done) >> 6 : (phase == 1 ? 0 : ~0ull);
             uint64_t m = fb;
@@ -225,23 +252,42 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                 m = o < m ? o : m;
             }
             const uint64_t m2 = m == ~0ull ? 0 : m >> 1;
-            for (uint64_t k = 0; k < m2; k++) {
-                uint32_t X[32];
-#pragma unroll
-                for (int i = 0; i < 32; i++) X[i] = Y[i];
-                if (phase == 0) {
-                    const uint64_t left = fb - 2 * (k + 1);  // full blocks after this pair
-                    const uint8_t *q = p + done + 128 * (k + 1);
-                    if (left >= 2) load_pair(q, Y);
-                    else if (left == 1) load_block(q, Y);
+            if (m2 > 0) {
+                const uint8_t *q = phase == 0 ? p + done + 128 : (const uint8_t *)plan;
+                const uint8_t *last = phase == 0 ? p + done + ((fb >> 1) - 1) * 128 : q;
+                const uint64_t step = phase == 0 ? 128 : 0;
+                uint32_t Z[32];
+                uint64_t k = 0;
+                // Y's loads complete here, so that inside the loop each
+                // buffer's first use waits only for its own loads.
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                for (; k + 2 <= m2; k += 2) {
+                    load_pair_g(q < last ? q : last, Z);
+                    q += step;
+                    __builtin_amdgcn_sched_barrier(0);
+                    Hash<KIND>::block(st, Y);
+                    Hash<KIND>::block(st, Y + 16);
+                    load_pair_g(q < last ? q : last, Y);
+                    q += step;
+                    __builtin_amdgcn_sched_barrier(0);
+                    Hash<KIND>::block(st, Z);
+                    Hash<KIND>::block(st, Z + 16);
                 }
-                // Keep the loads ahead of the rounds (the scheduler would
-                // otherwise sink them next to their use).
-                __builtin_amdgcn_sched_barrier(0);
-                Hash<KIND>::block(st, X);
-                Hash<KIND>::block(st, X + 16);
+                if (k < m2) {
+                    load_pair_g(q < last ? q : last, Z);
+                    __builtin_amdgcn_sched_barrier(0);
+                    Hash<KIND>::block(st, Y);
+                    Hash<KIND>::block(st, Y + 16);
+#pragma unroll
+                    for (int i = 0; i < 32; i++) Y[i] = Z[i];
+                }
+                if (phase == 0) {
+                    done += 128 * m2;
+                    // One full block left: Y holds a stale pair; the single-
+                    // block path below expects that block in Y[0..15].
+                    if (fb - 2 * m2 == 1) load_block_g(p + done, Y);
+                }
             }
-            if (phase == 0) done += 128 * m2;
         }
         if (phase < 2) {
             uint32_t X[16];
@@ -261,7 +307,7 @@ __device__ void leaves_worker(const hg_block_job *__restrict__ jobs, uint32_t n_
                     Y[i] = Y[i + 16];
                 }
                 done += 64;
-                if (avail >= 3) load_block(p + done + 64, Y + 16);
+                if (avail >= 3) load_block_g(p + done + 64, Y + 16);
             } else {
                 const int rem = (int)(n - done);
                 load_tail(p + done, rem, end, X);

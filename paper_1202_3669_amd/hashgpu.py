@@ -542,6 +542,9 @@ class Context:
                                    rt.data_ptr() if rt is not None else None, digest, 0)
             leaves.append(lv)
             rts.append(rt)
+        # The records hold raw pointers: they keep the tensors they point at
+        # (inputs and outputs) alive for as long as they exist.
+        recs._hg_keep = (leaves, rts, [s[0] for s in specs])
         return recs, leaves, rts
 
     @staticmethod
@@ -550,7 +553,9 @@ class Context:
         HG_IN_DEVICE / HG_ASYNC use)."""
         torch = _torch()
         raw = bytes(memoryview(recs).cast("B"))
-        return torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+        table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).cuda()
+        table._hg_keep = recs  # and through them the tensors they point at
+        return table
 
     @_on_stream
     def block_hash_batch(self, specs, roots: bool = True, stream=None):

@@ -134,7 +134,7 @@ def test_batch_host_roots(ctx, hg, asynchronous):
 
 def test_host_roots_flag_errors(ctx, hg):
     data = torch.zeros(4096, dtype=torch.uint8, device="cuda")
-    recs, _, _ = ctx.batch_outputs([(data, 64, 0)])
+    recs, leaves, _ = ctx.batch_outputs([(data, 64, 0)])  # leaves: referenced while the records point at it
     table = ctx.device_job_table(recs)
     with pytest.raises(hg.HashGpuError) as e:
         ctx.run_batch(table, 1, "roots", host_roots=True)

@@ -601,6 +601,45 @@ def test_leaves_and_roots_batches_from_device_table(ctx, hg):
         assert bytes(host(rt)) == oracle.root(kind, exp)
 
 
+def test_leaves_batch_odd_block_counts(ctx, hg):
+    # Segments of odd and even numbers of 64-byte blocks, with and without a
+    # partial last block, in one launch: lanes of a wavefront leave the
+    # two-block loop with 0, 1 or more full blocks left, at different times.
+    data = inputs.uniform_bytes(722, 3 * MiB + 777)
+    d = dev(data, 5)
+    blocks = [192, 320, 448, 4160, 8256, 65600, 200, 130, 65535, 129 * 64 + 1]
+    specs = [(d, b, k) for b in blocks for k in (0, 1)]
+    recs, leaves, _ = ctx.batch_outputs(specs, roots=False)
+    table = ctx.device_job_table(recs)
+    note("leaves batch, odd block counts")
+    ctx.run_batch(table, len(specs), "leaves", asynchronous=False)
+    for (_, block, kind), lv in zip(specs, leaves):
+        assert np.array_equal(host(lv), oracle.leaves(kind, data, block)), (block, kind)
+
+
+def test_job_table_keeps_its_tensors(ctx, hg):
+    # Job records hold raw pointers: the records and a device table made
+    # from them keep the tensors they point at alive, so that dropping the
+    # caller's references cannot let a later allocation take their memory
+    # while the batch writes to it.
+    data = inputs.uniform_bytes(723, 2 * MiB + 11)
+    d = dev(data)
+    specs = [(d, 4096, 0), (d, 65536, 1)]
+    recs, leaves, _ = ctx.batch_outputs(specs, roots=False)
+    ptrs = [lv.data_ptr() for lv in leaves]
+    del leaves
+    table = ctx.device_job_table(recs)
+    del recs
+    junk = [torch.zeros(n, dtype=torch.uint8, device="cuda") for n in (512, 40960, 196608, 655360)]
+    note("leaves batch from a table whose records' outputs the caller dropped")
+    ctx.run_batch(table, len(specs), "leaves", asynchronous=False)
+    kept = table._hg_keep._hg_keep[0]
+    assert [lv.data_ptr() for lv in kept] == ptrs
+    for (_, block, kind), lv in zip(specs, kept):
+        assert np.array_equal(host(lv), oracle.leaves(kind, data, block)), (block, kind)
+    assert all(int(j.sum()) == 0 for j in junk)
+
+
 # ------------------------------------------------------------------ probes --
 def test_probes_report_plausible_ceilings(ctx, hg):
     note("ALU and HBM probes")
