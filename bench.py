@@ -16,11 +16,11 @@ Workload (one step = one pass of the whole path over one input):
   Input bytes are resident in HBM when the timed region starts.
 
 Pipelining (the paper's stream of jobs with overlap, Sec. 3.2.3 / 4.1):
-per step, chunking runs on stream SA[step % 5] (the window scan is the
+per step, chunking runs on stream SA[step % 7] (the window scan is the
 throughput engine; while one stream waits for its counts or runs its chunk
 digests, the others' window scans run), the 4 KiB / 64 KiB segments on
 stream SB, and the 1 MiB segments -- 2048 sequential chains that each take
-longer than a step -- on stream S1[step % 3], as the step's first launch.
+longer than a step -- on stream S1[step % 5], as the step's first launch.
 The second levels run on the host's cores, where the paper computes them
 (Sec. 3.2.2): a root worker thread takes the 4 KiB / 64 KiB jobs' digests
 as soon as their segments are done (while the 1 MiB chains still run), then
@@ -55,10 +55,10 @@ WINDOW_OPS = 19 * 5 + 42 * 4
 # swaps + 5 final additions.
 BLOCK_OPS = {0: 324, 1: 613}
 # Chunking streams (steps round-robin), each driven by its own host thread.
-CHUNK_STREAMS = 5
+CHUNK_STREAMS = 7
 CHUNK_CALLS = "single"
 AHEAD = 12  # steps issued ahead of the last finished chunking
-LONG_STREAMS = 3  # streams for the per-step 1 MiB segment launches (round-robin)
+LONG_STREAMS = 5  # streams for the per-step 1 MiB segment launches (round-robin)
 ROOT_WORKERS = 2  # host threads (each with a stream) computing the second levels
 SLOTS = 10        # ring of per-step output buffers
 SERVE_SLOTS = 4        # serving: workers (groups in flight)
@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--chunk-calls", choices=["single", "stages"], default=CHUNK_CALLS,
                     help="one hg_chunk per step (host threads wait on its counts), or the chunking "
                          "stages with device counts (window scans back to back on one stream)")
+    ap.add_argument("--long-streams", type=int, default=LONG_STREAMS,
+                    help="streams for the per-step 1 MiB segment launches (round-robin)")
     ap.add_argument("--chunk-streams", type=int, default=CHUNK_STREAMS,
                     help="chunking streams (steps go round-robin over them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -905,7 +907,7 @@ def main():
     # Many concurrently busy streams: give HIP enough hardware queues before
     # its runtime starts (it shares four among all streams by default).
     # chunking streams + window + SB + S1 streams + root streams + default
-    queues = min(32, max(8, args.chunk_streams + 3 + LONG_STREAMS + ROOT_WORKERS, 2 * args.serve_slots + 2))
+    queues = min(32, max(8, args.chunk_streams + 3 + args.long_streams + ROOT_WORKERS, 2 * args.serve_slots + 2))
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(queues)
     import numpy as np
@@ -959,9 +961,10 @@ def main():
     del prev
     torch.cuda.synchronize()
 
-    global CHUNK_STREAMS, CHUNK_CALLS, AHEAD, SERVE_SLOTS, SERVE_GROUP_MIB
+    global CHUNK_STREAMS, CHUNK_CALLS, AHEAD, SERVE_SLOTS, SERVE_GROUP_MIB, LONG_STREAMS
     SERVE_SLOTS, SERVE_GROUP_MIB = args.serve_slots, args.serve_group_mib
     CHUNK_STREAMS = args.chunk_streams
+    LONG_STREAMS = args.long_streams
     CHUNK_CALLS = args.chunk_calls
     AHEAD = args.ahead
     pipe = Pipeline(torch, hg, data, prev_dig, args.slots)
