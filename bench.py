@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--no-dedup", action="store_true", help="skip the block-map write path over versions")
     ap.add_argument("--batch-probe", action="store_true",
                     help="only run the step's 4 KiB / 64 KiB segment batch five times (for rocprofv3 counters)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only run the streaming chunker over the 1 GiB input in 64 MiB device feeds, four times "
+                         "(for a rocprofv3 kernel trace)")
     ap.add_argument("--leaf-probe", action="store_true",
                     help="only hash the 1 GiB input with one lane per segment (MD5/SHA-1, 4 KiB and "
                          "64 KiB segments, 3 launches each, no second level), for counter runs")
@@ -941,6 +944,22 @@ def main():
             torch.cuda.synchronize()
             del table, recs, leaves
         print("[bench] batch probe done", file=sys.stderr, flush=True)
+        return
+    if args.stream_probe:
+        # The streaming chunker fed the 1 GiB in 64 MiB device pieces
+        # (HG_ASYNC), four times, for a kernel trace.
+        data = torch.from_numpy(data_np).cuda()
+        with hg.Context(0) as c:
+            ch = hg.Chunker(c)
+            for r in range(4):
+                ch.reset()
+                outs = [ch.feed(data[a:a + 64 * MiB], asynchronous=True, ready=True)
+                        for a in range(0, data.numel(), 64 * MiB)]
+                outs.append(ch.finish(asynchronous=True))
+                torch.cuda.synchronize()
+                del outs
+            ch.close()
+        print("[bench] stream probe done", file=sys.stderr, flush=True)
         return
     if args.leaf_probe:
         data = torch.from_numpy(data_np).cuda()
