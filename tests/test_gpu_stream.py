@@ -213,6 +213,45 @@ def test_stream_async_feeds(ctx, hg, case, where):
     assert np.array_equal(np.concatenate(got_d).reshape(-1, 20), exp_dig)
 
 
+@pytest.mark.parametrize("mode", ["sync", "async", "async_ready"])
+def test_stream_large_device_feeds_produced_on_the_stream(ctx, hg, mode):
+    # Device feeds of 20-27 MiB (several window-tile launch ranges' worth),
+    # each produced on the stream just before the feed: without HG_IN_READY
+    # the feed's copy must wait for that work.
+    length = 56 * MiB + 13
+    data = inputs.uniform_bytes(560, length)
+    exp_ends, exp_dig = one_shot(data, 20, 1, 0xFFF, 0, 2048, 0)
+    splits = [(0, 20 * MiB + 3), (20 * MiB + 3, 20 * MiB + 3), (20 * MiB + 3, 47 * MiB + 1), (47 * MiB + 1, length)]
+    note(f"device feeds of up to {27 * MiB} bytes, mode={mode}")
+    src = torch.from_numpy(data).cuda()
+    ch = hg.Chunker(ctx, 20, 1, 0xFFF, 0, 2048, 0)
+    got_e, got_d, outs, keep = [], [], [], []
+    for a, b in splits:
+        piece = torch.empty(b - a, dtype=torch.uint8, device="cuda")
+        piece.copy_(src[a:b], non_blocking=True)  # produced on the stream the feed runs on
+        keep.append(piece)
+        if mode == "async_ready":
+            torch.cuda.synchronize()  # HG_IN_READY: the input is complete when the feed is made
+        if mode == "sync":
+            e, d = ch.feed(piece)
+            got_e.append(e)
+            got_d.append(d)
+        else:
+            outs.append(ch.feed(piece, asynchronous=True, ready=mode == "async_ready"))
+    if mode == "sync":
+        e, d = ch.finish()
+        got_e.append(e)
+        got_d.append(d)
+    else:
+        outs.append(ch.finish(asynchronous=True))
+        torch.cuda.synchronize()
+        got_e = [e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in outs]
+        got_d = [d[:int(c.item())].cpu().numpy() for _, d, c in outs]
+    ch.close()
+    assert np.array_equal(np.concatenate(got_e), exp_ends)
+    assert np.array_equal(np.concatenate(got_d).reshape(-1, 20), exp_dig)
+
+
 def test_stream_async_needs_device_outputs(ctx, hg):
     import ctypes
     ch = hg.Chunker(ctx)
