@@ -808,8 +808,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 }
 
 __global__ void add_u64_kernel(uint64_t *__restrict__ dst, const uint64_t *__restrict__ src,
-                               const uint64_t *__restrict__ n_dev, uint64_t add) {
-    const uint64_t n = *n_dev;
+                               const uint64_t *__restrict__ n_dev, uint64_t max_n, uint64_t add) {
+    const uint64_t n = *n_dev < max_n ? *n_dev : max_n;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = src[i] + add;
 }
@@ -819,7 +819,7 @@ hipError_t launch_add_u64(uint64_t *dst, const uint64_t *src, const uint64_t *n_
     if (max_n == 0) return hipSuccess;
     uint64_t blocks = (max_n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    add_u64_kernel<<<(unsigned)blocks, 256, 0, s>>>(dst, src, n_dev, add);
+    add_u64_kernel<<<(unsigned)blocks, 256, 0, s>>>(dst, src, n_dev, max_n, add);
     return hipGetLastError();
 }
 

@@ -2072,6 +2072,11 @@ int chunker_grow(hg_chunker *c, int i, uint64_t bytes, hipStream_t st, bool ends
     return HG_OK;
 }
 
+// Largest cut bound for which an asynchronous feed with device outputs
+// enqueues its back half before the host wait (the back half's launches and
+// scratch are then sized by the bound, not by the cut count).
+constexpr uint64_t EARLY_BACK_MAX = 1u << 20;
+
 // Cuts one call can emit for `len` new bytes.
 uint64_t chunker_bound(const hg_chunker *c, uint64_t len) {
     const uint64_t span = (c->pos - c->last) + len;
@@ -2187,6 +2192,26 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     // decision is redone with exact room.
     uint64_t room = has_windows ? chunker_cand_room(p, plan.nwin) : 0;
     uint64_t k = 0, last_w = 0;
+    const uint64_t abs_add = a0 + last0;
+    // With HG_ASYNC, device outputs and a device count, the back half does
+    // not need the cut count on the host: it is enqueued on the caller's
+    // stream before the host wait (sized by the bound, the count read on the
+    // device), so that the host issues it while the front half runs.  If the
+    // candidates exceed their room, the redone front half is followed by a
+    // back half of its own, which overwrites these outputs in stream order.
+    const bool early_back = async && out_dev && !count_host && bound <= EARLY_BACK_MAX;
+    auto back_half = [&](uint64_t max_n) -> int {
+        HG_HIP(ctx, hipEventRecord(c->ev_front, F));
+        HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
+        if (max_n) {
+            HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], max_n, abs_add, st));
+            if (digests)
+                HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], max_n, (uint8_t *)digests, st));
+        }
+        HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
+        HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
+        return HG_OK;
+    };
     for (int attempt = 0; attempt < 2; attempt++) {
         HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(room, 1) * 8, F, &cand));
         if (has_windows)
@@ -2217,6 +2242,7 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                       hg::launch_stream_walk((const uint64_t *)cand, &sw[6], b0, p.window, wlen, last0, p.min_chunk,
                                              p.max_chunk, final, rel, bound, &sw[2], F));
         }
+        if (early_back) HG_TRY(back_half(bound));
         HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, sw, 32, hipMemcpyDeviceToHost, F));
         HG_HIP(ctx, hipStreamSynchronize(F));
         const uint64_t total = ctx->host_small[0];
@@ -2229,28 +2255,30 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         room = total;  // more candidates than expected: once more with exact room
     }
     if (k > bound) return fail(ctx, HG_EDEVICE, "internal: %llu cuts above the bound", (unsigned long long)k);
-    // Back half on the caller's stream: absolute ends, digests of the
-    // completed chunks, the count.
-    HG_HIP(ctx, hipEventRecord(c->ev_front, F));
-    HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
-    const uint64_t abs_add = a0 + last0;
-    if (k) {
-        if (out_dev) {
-            HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], bound, abs_add, st));
-        } else {
-            HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
+    if (!early_back) {
+        // Back half on the caller's stream, sized by the cut count: absolute
+        // ends, digests of the completed chunks, the count.
+        HG_HIP(ctx, hipEventRecord(c->ev_front, F));
+        HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
+        if (k) {
+            if (out_dev) {
+                HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], bound, abs_add, st));
+            } else {
+                HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
+            }
+            if (digests) {
+                const int dd = digest_bytes(p.chunk_digest);
+                void *ddig = digests;
+                if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
+                HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], k, (uint8_t *)ddig, st));
+                if (!out_dev)
+                    HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
+            }
         }
-        if (digests) {
-            const int dd = digest_bytes(p.chunk_digest);
-            void *ddig = digests;
-            if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
-            HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], k, (uint8_t *)ddig, st));
-            if (!out_dev) HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
-        }
+        if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
+        else *n_out = k;
+        HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
     }
-    if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
-    else *n_out = k;
-    HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
     if (!async) HG_HIP(ctx, hipStreamSynchronize(st));
     if (!out_dev)
         for (uint64_t i = 0; i < k; i++) ends[i] += abs_add;
