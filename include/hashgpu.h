@@ -448,9 +448,7 @@ int hg_chunker_bound(const hg_chunker *c, uint64_t len, uint64_t *bound);
  * and boundary decision run on a stream of the chunker's own and end with
  * one host wait; its ends, digests and count are written on `stream`, so
  * with HG_ASYNC the digests left running overlap the next feed's copy and
- * window scan (with HG_ASYNC and a device count they are enqueued before
- * that wait, sized by hg_chunker_bound, so that the host issues them while
- * the scan runs).  Device input is read after the work already queued on
+ * window scan.  Device input is read after the work already queued on
  * `stream` (which may produce it) -- that includes the previous feed's
  * digests -- unless the caller passes HG_IN_READY: the device input is
  * complete when the call is made (nothing pending on `stream` writes it).

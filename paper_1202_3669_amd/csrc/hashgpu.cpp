@@ -301,7 +301,8 @@ int ensure_stage(hg_ctx *ctx) {
 // the caller's unit (e.g. the segment size).
 template <class F>
 int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_t align,
-              hipStream_t st, F on_piece, uint64_t piece = STAGE_PIECE, bool after_stream = true) {
+              hipStream_t st, F on_piece, uint64_t piece = STAGE_PIECE, bool after_stream = true,
+              bool taper = false) {
     if (n == 0) return HG_OK;
     HG_TRY(ensure_copy_stream(ctx));
     const bool pinned = is_pinned_host(src);
@@ -319,9 +320,14 @@ int stream_in(hg_ctx *ctx, uint8_t *dst, const uint8_t *src, uint64_t n, uint64_
         HG_HIP(ctx, hipEventRecord(ctx->piece_ready, st));
         HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->piece_ready, 0));
     }
+    // taper (with align 1): the last piece's bytes go in quarters, so that
+    // the work left after the last byte lands -- the last piece's share --
+    // is short.
     int k = 0;
-    for (uint64_t off = 0; off < n; off += piece, k ^= 1) {
-        const uint64_t len = std::min(piece, n - off);
+    uint64_t len = 0;
+    for (uint64_t off = 0; off < n; off += len, k ^= 1) {
+        len = std::min(piece, n - off);
+        if (taper && align == 1 && n - off <= piece && piece >= 4) len = std::min(n - off, piece / 4);
         if (pinned) {
             HG_HIP(ctx, hipMemcpyAsync(dst + off, src + off, len, hipMemcpyHostToDevice, ctx->copy_stream));
         } else {
@@ -419,7 +425,7 @@ int scan_tiles_from(hg_ctx *ctx, const void *in, uint64_t len, bool in_dev, uint
                              }
                              return HG_OK;
                          },
-                         SCAN_PIECE));
+                         SCAN_PIECE, true, true));
     }
     *din_out = din;
     *plan_out = plan;
@@ -2072,11 +2078,6 @@ int chunker_grow(hg_chunker *c, int i, uint64_t bytes, hipStream_t st, bool ends
     return HG_OK;
 }
 
-// Largest cut bound for which an asynchronous feed with device outputs
-// enqueues its back half before the host wait (the back half's launches and
-// scratch are then sized by the bound, not by the cut count).
-constexpr uint64_t EARLY_BACK_MAX = 1u << 20;
-
 // Cuts one call can emit for `len` new bytes.
 uint64_t chunker_bound(const hg_chunker *c, uint64_t len) {
     const uint64_t span = (c->pos - c->last) + len;
@@ -2171,7 +2172,7 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                                  }
                                  return HG_OK;
                              },
-                             SCAN_PIECE, false));
+                             SCAN_PIECE, false, true));
         } else {
             HG_LAUNCH(ctx, HG_K_WINDOW_TILES, F,
                       hg::launch_window_scan_tiles(plan, W + b0, wlen - b0, p.window, s_, p.mask, p.target, ws, F));
@@ -2192,26 +2193,6 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
     // decision is redone with exact room.
     uint64_t room = has_windows ? chunker_cand_room(p, plan.nwin) : 0;
     uint64_t k = 0, last_w = 0;
-    const uint64_t abs_add = a0 + last0;
-    // With HG_ASYNC, device outputs and a device count, the back half does
-    // not need the cut count on the host: it is enqueued on the caller's
-    // stream before the host wait (sized by the bound, the count read on the
-    // device), so that the host issues it while the front half runs.  If the
-    // candidates exceed their room, the redone front half is followed by a
-    // back half of its own, which overwrites these outputs in stream order.
-    const bool early_back = async && out_dev && !count_host && bound <= EARLY_BACK_MAX;
-    auto back_half = [&](uint64_t max_n) -> int {
-        HG_HIP(ctx, hipEventRecord(c->ev_front, F));
-        HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
-        if (max_n) {
-            HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], max_n, abs_add, st));
-            if (digests)
-                HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], max_n, (uint8_t *)digests, st));
-        }
-        HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
-        HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
-        return HG_OK;
-    };
     for (int attempt = 0; attempt < 2; attempt++) {
         HG_TRY(ensure(ctx, SLOT_CAND, std::max<uint64_t>(room, 1) * 8, F, &cand));
         if (has_windows)
@@ -2242,7 +2223,6 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
                       hg::launch_stream_walk((const uint64_t *)cand, &sw[6], b0, p.window, wlen, last0, p.min_chunk,
                                              p.max_chunk, final, rel, bound, &sw[2], F));
         }
-        if (early_back) HG_TRY(back_half(bound));
         HG_HIP(ctx, hipMemcpyAsync(ctx->host_small, sw, 32, hipMemcpyDeviceToHost, F));
         HG_HIP(ctx, hipStreamSynchronize(F));
         const uint64_t total = ctx->host_small[0];
@@ -2255,30 +2235,28 @@ int chunker_step(hg_chunker *c, const void *data, uint64_t len, uint32_t flags, 
         room = total;  // more candidates than expected: once more with exact room
     }
     if (k > bound) return fail(ctx, HG_EDEVICE, "internal: %llu cuts above the bound", (unsigned long long)k);
-    if (!early_back) {
-        // Back half on the caller's stream, sized by the cut count: absolute
-        // ends, digests of the completed chunks, the count.
-        HG_HIP(ctx, hipEventRecord(c->ev_front, F));
-        HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
-        if (k) {
-            if (out_dev) {
-                HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], bound, abs_add, st));
-            } else {
-                HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
-            }
-            if (digests) {
-                const int dd = digest_bytes(p.chunk_digest);
-                void *ddig = digests;
-                if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
-                HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], k, (uint8_t *)ddig, st));
-                if (!out_dev)
-                    HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
-            }
+    // Back half on the caller's stream: absolute ends, digests of the
+    // completed chunks, the count.
+    HG_HIP(ctx, hipEventRecord(c->ev_front, F));
+    HG_HIP(ctx, hipStreamWaitEvent(st, c->ev_front, 0));
+    const uint64_t abs_add = a0 + last0;
+    if (k) {
+        if (out_dev) {
+            HG_HIP(ctx, hg::launch_add_u64(ends, rel, &sw[2], bound, abs_add, st));
+        } else {
+            HG_HIP(ctx, hipMemcpyAsync(ends, rel, k * 8, hipMemcpyDeviceToHost, st));
         }
-        if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
-        else *n_out = k;
-        HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
+        if (digests) {
+            const int dd = digest_bytes(p.chunk_digest);
+            void *ddig = digests;
+            if (!out_dev) HG_TRY(ensure(ctx, SLOT_DIG, k * (uint64_t)dd, st, &ddig));
+            HG_TRY(chunk_digests_of(ctx, p, W + last0, wlen - last0, rel, &sw[2], k, (uint8_t *)ddig, st));
+            if (!out_dev) HG_HIP(ctx, hipMemcpyAsync(digests, ddig, k * (uint64_t)dd, hipMemcpyDeviceToHost, st));
+        }
     }
+    if (out_dev && !count_host) HG_HIP(ctx, hipMemcpyAsync(n_out, &sw[2], 8, hipMemcpyDeviceToDevice, st));
+    else *n_out = k;
+    HG_HIP(ctx, hipEventRecord(c->ev_dig[nxt], st));
     if (!async) HG_HIP(ctx, hipStreamSynchronize(st));
     if (!out_dev)
         for (uint64_t i = 0; i < k; i++) ends[i] += abs_add;
