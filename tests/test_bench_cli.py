@@ -1,8 +1,9 @@
 """CPU checks of bench.py's contract that need no GPU: more than one GPU is
 refused with a message, the recorded HBM traffic is only reported while the
 profiled kernel sources are unchanged, the percentile helper is the
-nearest-rank one, and the timed steps issue exactly the work the reported
-value counts (with stand-ins for torch and the library)."""
+nearest-rank one, the timed steps issue exactly the work the reported
+value counts (with stand-ins for torch and the library), and the sections
+after the timed step run in child processes of their own."""
 import ctypes
 import os
 import subprocess
@@ -164,3 +165,57 @@ def test_timed_steps_issue_exactly_the_counted_work():
         assert covered == sorted(bench.BLOCK_JOBS * steps)
         assert sum(e[0] == "chunk" for e in log) == steps
         assert sum(e[0] == "similarity" for e in log) == steps
+
+
+def test_sections_run_in_child_processes(monkeypatch):
+    # Each measurement section after the timed step runs as `bench.py
+    # --section NAME` in a child process with the serving parameters passed
+    # on; its last JSON line is the result, and a failing child is an error.
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--serve-requests", "123", "--serve-slots", "5"])
+    args = bench.parse()
+    calls = []
+
+    class Done:
+        def __init__(self, rc, out):
+            self.returncode, self.stdout = rc, out
+
+    def fake_run(cmd, **kw):
+        calls.append(cmd)
+        return Done(0, '[bench] noise\n{"section": "serving", "result": {"peak_GBps": 1.5}}\n')
+
+    monkeypatch.setattr(subprocess, "run", fake_run)
+    assert bench.run_section("serving", args) == {"peak_GBps": 1.5}
+    cmd = calls[0]
+    assert cmd[0] == sys.executable and cmd[1].endswith("bench.py")
+    assert cmd[cmd.index("--section") + 1] == "serving"
+    assert cmd[cmd.index("--serve-requests") + 1] == "123" and cmd[cmd.index("--serve-slots") + 1] == "5"
+    monkeypatch.setattr(subprocess, "run", lambda cmd, **kw: Done(1, ""))
+    try:
+        bench.run_section("batched", args)
+    except RuntimeError as e:
+        assert "batched" in str(e)
+    else:
+        raise AssertionError("a failing section was not reported")
+
+
+def test_default_run_composes_the_children(monkeypatch, capsys):
+    # The default run: the step and each section from its child process,
+    # one JSON line with the step's latency and ALU figures last.
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--no-cpu-baseline", "--no-sweep"])
+    seen = []
+
+    def fake_section(name, args):
+        seen.append(name)
+        if name == "step":
+            return {"metric": "m", "value": 1.0, "step_alu": {"frac": 0.5}, "latency_ms": {"step_p50": 2.0}}
+        return {"from": name}
+
+    monkeypatch.setattr(bench, "run_section", fake_section)
+    bench.main()
+    out = capsys.readouterr().out.strip().splitlines()
+    import json
+    line = json.loads(out[-1])
+    assert seen == ["step", "breakdown", "batched", "dedup", "serving"]
+    assert line["breakdown"] == {"from": "breakdown"} and line["serving"] == {"from": "serving"}
+    assert "similarity_sweep" not in line and "cpu_baseline" not in line
+    assert list(line)[-2:] == ["step_alu", "latency_ms"]

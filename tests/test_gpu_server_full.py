@@ -4,7 +4,7 @@ sizes 4 KiB-256 MiB with median 1 MiB and sigma 1.85, mix 50% block SHA-1 /
 30% block MD5 with 64 KiB segments and second levels / 20% chunking with
 MD5 w=20, stride 1, low 12 bits, min 2 KiB, SHA-1 chunk digests), payloads
 sliced from the 1 GiB input (seed 2) at the benchmark's seeded offsets,
-through a server configured as the benchmark's (4 workers, 2048 requests
+through a server configured as the benchmark's (6 workers, 2048 requests
 and 2 GiB per group, 4 GiB of staging).  Every request's outputs equal the
 same request run alone through the single-call entry points, bit for bit,
 with device payloads in a burst and with pinned host payloads at Poisson
@@ -97,7 +97,7 @@ def test_full_stream_device_payloads_burst(hg, workload):
     assert min(sizes) == 4 * KiB and max(sizes) == 256 * MiB  # the stream spans the whole size range
     rs = hg.RequestSet(dev.data_ptr(), True, specs)
     note(f"serving {len(specs)} requests ({sum(sizes) / 1e9:.2f} GB), burst, device payloads")
-    with hg.Server(0, slots=4, max_requests=2048, device_budget=4 * GiB, max_group_bytes=2 * GiB) as srv:
+    with hg.Server(0, slots=6, max_requests=2048, device_budget=4 * GiB, max_group_bytes=2 * GiB) as srv:
         lat, sts = srv.play(rs, np.zeros(len(specs)))
         st = srv.stats()
     assert st["completed"] == len(specs) and st["failed"] == 0
@@ -118,7 +118,7 @@ def test_stream_slice_pinned_host_payloads_poisson(hg, workload):
     total = sum(s[2] for s in sub)
     arr = (arr1[lo:lo + 400] - arr1[lo]) * (total / len(sub)) / 25e9
     note(f"serving {len(sub)} requests with host payloads, Poisson arrivals over {arr[-1]:.2f} s")
-    with hg.Server(0, slots=4, max_requests=2048, device_budget=4 * GiB, max_group_bytes=2 * GiB) as srv:
+    with hg.Server(0, slots=6, max_requests=2048, device_budget=4 * GiB, max_group_bytes=2 * GiB) as srv:
         lat, sts = srv.play(rs, arr)
         st = srv.stats()
     assert st["completed"] == len(sub) and st["failed"] == 0
