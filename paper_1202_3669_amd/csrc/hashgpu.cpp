@@ -560,7 +560,13 @@ int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t
     const uint64_t kmax = std::min<uint64_t>(nc, 1u << 16);
     for (uint64_t k = 1; k <= kmax; k++) {
         bytes += lens[order[k - 1]];
-        const double host_t = (double)bytes * copy + std::max((double)lens[order[0]] / core, (double)bytes / (core * cores));
+        // The copy (in groups of ~16 MiB) and the hashing overlap: the host
+        // is done after the whole copy and the last group's hashing, or
+        // after the first group's copy and all the hashing (the longest
+        // chunk on one core), whichever is later.
+        const double group = std::min<double>((double)bytes, (double)(16u << 20));
+        const double hash_all = std::max((double)lens[order[0]] / core, (double)bytes / (core * cores));
+        const double host_t = std::max((double)bytes * copy + group / (core * cores), group * copy + hash_all);
         const double gpu_t = k < nc ? (double)lens[order[k]] / lane : 0.0;
         const double t = std::max(host_t, gpu_t);
         if (t < best) {
