@@ -341,3 +341,63 @@ def test_stream_dense_candidates_redo(ctx, hg, where):
     ch.close()
     assert np.array_equal(got_e, exp_ends)
     assert np.array_equal(got_d, exp_dig)
+
+
+def _candidate_window_w(seed, w):
+    # a w-byte window whose MD5 has its low 12 bits (first word, little
+    # endian) zero
+    rng = np.random.default_rng(seed)
+    while True:
+        x = rng.integers(0, 256, w, dtype=np.uint8).tobytes()
+        if int.from_bytes(hashlib.md5(x).digest()[:4], "little") & 0xFFF == 0:
+            return np.frombuffer(x, dtype=np.uint8)
+
+
+SPLIT_CASES = {  # name: (w, s, mask, target, min, max)
+    # a candidate window tiled: every 11th window of the stride-3 grid is a
+    # candidate, far above the room set aside for a 12-bit mask (redo)
+    "dense_w33_s3": (33, 3, 0xFFF, 0, 2048, 0),
+    # minimum below the window: the boundary decision walks
+    "min_below_w_s3": (33, 3, 0x3F, 1, 10, 0),
+    "max_chunk": (20, 1, 0xFFF, 0, 2048, 8192),
+}
+
+
+@pytest.mark.parametrize("ready", [False, True])
+@pytest.mark.parametrize("case", sorted(SPLIT_CASES))
+def test_stream_large_device_feeds_stride_dense_max(ctx, hg, case, ready):
+    # Device pieces of 16 MiB and more (several window-tile launch ranges),
+    # with a carry into the second large piece and none into the first,
+    # around a tiny and an empty piece, at stride 3 with a 33-byte window,
+    # with dense candidates, a minimum below the window and a maximum; the
+    # pieces produced on the stream or declared ready: the stream equals the
+    # one-shot result.
+    w, s, mask, target, mn, mx = SPLIT_CASES[case]
+    length = 40 * MiB + 11
+    if case == "dense_w33_s3":
+        w0 = _candidate_window_w(570, 33)
+        data = np.tile(w0, length // 33 + 1)[:length].copy()
+        data[-11:] = 1
+    else:
+        data = inputs.uniform_bytes(571, length)
+    exp_ends, exp_dig = one_shot(data, w, s, mask, target, mn, mx)
+    cuts = [0, 16 * MiB, 16 * MiB + 3, 16 * MiB + 3, 33 * MiB + 1, length]
+    note(f"large device feeds: {case}, ready={ready}")
+    src = torch.from_numpy(data).cuda()
+    ch = hg.Chunker(ctx, w, s, mask, target, mn, mx)
+    outs, keep = [], []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        piece = torch.empty(b - a, dtype=torch.uint8, device="cuda")
+        piece.copy_(src[a:b], non_blocking=True)
+        keep.append(piece)
+        if ready:
+            torch.cuda.synchronize()
+        outs.append(ch.feed(piece, asynchronous=True, ready=ready))
+    outs.append(ch.finish(asynchronous=True))
+    torch.cuda.synchronize()
+    got_e = np.concatenate([e[:int(c.item())].cpu().numpy().astype(np.uint64) for e, _, c in outs])
+    got_d = np.concatenate([d[:int(c.item())].cpu().numpy() for _, d, c in outs])
+    ch.close()
+    assert got_e.size > 1000
+    assert np.array_equal(got_e, exp_ends)
+    assert np.array_equal(got_d.reshape(-1, 20), exp_dig)
