@@ -23,7 +23,9 @@
 // theirs, so requests that arrive meanwhile overlap on the device with the
 // groups in flight.  A request that does not fit an empty group (or a chunk
 // request of more than SOLO_CHUNK_BYTES) runs alone
-// through the single-call entry points on the worker's context.
+// through the single-call entry points on the worker's context; such a chunk
+// request in device memory does not close the group being formed (it waits
+// at its place for the next idle worker, and later requests that fit join).
 //
 // Payload addressing in a group: chunk payloads are described as offsets
 // from the staging region's base taken modulo 2^64, so that payloads in the
@@ -357,6 +359,14 @@ void add(Group &g, Req *q) {
     }
 }
 
+// Chunk requests served alone by their parameters or size (whatever the
+// group holds).
+bool solo_chunk(const hg_request &r) {
+    return r.kind != HG_REQ_BLOCK &&
+           (r.chunk.max_chunk != 0 || (r.chunk.chunk_segment != 0 && r.chunk.chunk_segment < TL_MIN_SEGMENT) ||
+            r.len > SOLO_CHUNK_BYTES);
+}
+
 bool admissible(const hg_server *s, const Req *q) {
     return (q->r.flags & HG_REQ_FAIL_INJECT) || q->stage_bytes == 0 || s->ranges.fits(q->stage_bytes);
 }
@@ -364,20 +374,30 @@ bool admissible(const hg_server *s, const Req *q) {
 // Takes requests from the head of the queue into g (lock held).
 void form(hg_server *s, Group &g) {
     g.clear();
-    while (!s->pending.empty()) {
-        Req *q = s->pending.front();
+    auto it = s->pending.begin();
+    while (it != s->pending.end()) {
+        Req *q = *it;
         if (q->r.flags & HG_REQ_FAIL_INJECT) {
-            s->pending.pop_front();
+            it = s->pending.erase(it);
             g.failed.push_back(q);
             continue;
         }
         bool alone = false;
         if (!fits(g, s->cfg, q)) {
-            if (!g.empty()) break;
+            if (!g.empty()) {
+                // A chunk request that is served alone anyway stays queued
+                // for the next idle worker; the requests behind it that fit
+                // still join this group.
+                if (solo_chunk(q->r) && !q->stage_bytes) {
+                    ++it;
+                    continue;
+                }
+                break;
+            }
             alone = true;  // does not fit even an empty group
         }
         if (q->stage_bytes && !s->ranges.take(q->stage_bytes, &q->stage_off)) break;
-        s->pending.pop_front();
+        it = s->pending.erase(it);
         q->dev_in = q->stage_bytes ? s->stage + q->stage_off : (const uint8_t *)q->r.payload;
         if (alone) {
             g.solo = q;
