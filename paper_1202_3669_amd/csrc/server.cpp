@@ -8,11 +8,17 @@
 // max_requests requests and max_group_bytes payload bytes, and one pinned
 // host buffer for uploads and results.  An idle worker takes requests from
 // the head of the queue, in arrival order, while they fit its group and the
-// staging region, and enqueues the whole group:
+// staging region, and enqueues the whole group.  A group holds one kind of
+// request: block requests, whose groups are bound by their chains, or chunk
+// requests, whose groups are window scans; requests in device memory of the
+// other kind stay queued for the next idle worker, so that the two kinds
+// run side by side in different groups instead of the chains holding up a
+// mixed group after its scans are done.
 //   - host payloads are copied into the staging region (device-memory
 //     admission: a request waits at the head until its bytes fit);
 //   - block requests: one job table and one persistent segment-digest
-//     launch for all of them (MD5 and SHA-1 mixed) on the helper stream;
+//     launch for all of them (MD5 and SHA-1 mixed) on the helper stream
+//     (a group of host payloads may hold both kinds);
 //     their segment digests come back whole and the worker computes the
 //     second levels on the host pool (Sec. 3.2.2);
 //   - chunk requests (same parameters within a group): one tile map over
@@ -383,6 +389,12 @@ void form(hg_server *s, Group &g) {
             continue;
         }
         bool alone = false;
+        // One kind per group: a request in device memory of the other kind
+        // stays queued for the next idle worker.
+        if (!g.empty() && !q->stage_bytes && (q->r.kind == HG_REQ_BLOCK) != !g.blocks.empty()) {
+            ++it;
+            continue;
+        }
         if (!fits(g, s->cfg, q)) {
             if (!g.empty()) {
                 // A chunk request that is served alone anyway stays queued
