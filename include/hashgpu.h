@@ -543,13 +543,13 @@ int hg_batch_tune(hg_batch *b, const void *arena, const hg_batch_out *out, void 
  * up, without waiting for the others to drain.  A request that does not fit
  * an empty group -- and a chunk request of more than 32 MiB, whose boundary
  * decision the single call makes faster -- is served alone by a worker
- * through the single-call entry point.  A group holds one kind of request
- * (block or chunk) when its payloads are in device memory: requests of the
- * other kind, and chunk requests served alone for their size or parameters,
- * do not close the group being formed -- they stay at their place in the
- * queue for the next idle worker, and the requests behind them that fit
- * join the group.  (Host payloads keep strict arrival order, since they are
- * admitted by staging room at the head of the queue.)
+ * through the single-call entry point.  A request in device memory whose
+ * kind (block or chunk) differs from the group's, or a chunk request in
+ * device memory served alone for its size or parameters, does not close the
+ * group being formed: it stays at its place in the queue for the next idle
+ * worker, and the requests behind it that fit join the group -- so groups
+ * of device payloads hold one kind.  (Host payloads keep strict arrival
+ * order: they are admitted by staging room at the head of the queue.)
  *
  * Admission by device memory: a payload in host memory is admitted only
  * when its bytes fit the staging region (device_budget bytes, allocated once
