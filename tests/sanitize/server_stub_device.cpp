@@ -1,4 +1,5 @@
-// Stub device layer for the serving loop's ThreadSanitizer build: the
+// Stub device layer for the serving loop's sanitizer builds and its
+// group-formation test: the
 // library calls server.cpp makes, with outputs that identify the request
 // they belong to.  A block job's segment digests are filled with the byte
 // (len * 7 + block_size) & 0xff and, when it runs alone, its root with
@@ -7,11 +8,25 @@
 // run alone, none in a group, which the driver accounts for).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <thread>
+
 #include "hashgpu.h"
 #include "hg_internal.hpp"
 
 namespace {
 int db(int d) { return d == HG_MD5 ? 16 : 20; }
+}  // namespace
+
+// Test hook of the group-formation driver: a single chunk call on a payload
+// of exactly hold_len bytes waits, once it has set `entered`, until
+// `released` is set (0: no call waits).
+namespace stubhook {
+std::atomic<uint64_t> hold_len{0};
+std::atomic<int> entered{0}, released{0};
+}  // namespace stubhook
+
+namespace {
 uint8_t leaf_byte(uint64_t len, uint64_t block) { return (uint8_t)((len * 7 + block) & 0xff); }
 uint8_t root_byte(uint64_t len) { return (uint8_t)((len * 13) & 0xff); }
 }  // namespace
@@ -100,6 +115,10 @@ int hg_block_hash(hg_ctx *, const void *, uint64_t len, uint64_t block_size, int
 }
 int hg_chunk(hg_ctx *, const void *, uint64_t len, const hg_chunk_params *, uint64_t *ends, uint64_t capacity,
              uint64_t *n_chunks, void *, uint32_t, void *) {
+    if (len && len == stubhook::hold_len.load()) {
+        stubhook::entered.store(1);
+        while (!stubhook::released.load()) std::this_thread::yield();
+    }
     *n_chunks = len ? 1 : 0;
     if (len && capacity) ends[0] = len;
     return len && !capacity ? HG_ETRUNC : HG_OK;
