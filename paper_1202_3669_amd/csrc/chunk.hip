@@ -443,6 +443,35 @@ hipError_t launch_max_gap(const uint64_t *ends, uint64_t len, const uint64_t *n_
     return hipGetLastError();
 }
 
+// Chunks hashed on the host leave the device as one packed buffer.  Each
+// table record is a slice of at most a few tens of KiB (so that long chunks
+// spread over many workgroups) whose destination has its source's address
+// modulo 16: the head bytes up to a 16-byte boundary go one by one, the
+// body in 16-byte words, then the tail.
+__global__ __launch_bounds__(256) void gather_ranges_kernel(const uint8_t *__restrict__ src,
+                                                            const uint64_t *__restrict__ tab, uint64_t k,
+                                                            uint8_t *__restrict__ dst) {
+    for (uint64_t r = blockIdx.x; r < k; r += gridDim.x) {
+        const uint8_t *a = src + tab[3 * r];
+        const uint64_t n = tab[3 * r + 1];
+        uint8_t *b = dst + tab[3 * r + 2];
+        const uint64_t mis = (uint64_t)((uintptr_t)a & 15);
+        const uint64_t head = n < ((16 - mis) & 15) ? n : ((16 - mis) & 15);
+        const uint64_t nv = (n - head) / 16;
+        if (threadIdx.x < head) b[threadIdx.x] = a[threadIdx.x];
+        const uint4 *av = (const uint4 *)(a + head);
+        uint4 *bv = (uint4 *)(b + head);
+        for (uint64_t i = threadIdx.x; i < nv; i += blockDim.x) bv[i] = av[i];
+        for (uint64_t i = head + nv * 16 + threadIdx.x; i < n; i += blockDim.x) b[i] = a[i];
+    }
+}
+
+hipError_t launch_gather_ranges(const uint8_t *src, const uint64_t *tab, uint64_t k, uint8_t *dst, hipStream_t s) {
+    if (k == 0) return hipSuccess;
+    gather_ranges_kernel<<<(unsigned)std::min<uint64_t>(k, 8192), 256, 0, s>>>(src, tab, k, dst);
+    return hipGetLastError();
+}
+
 // Digests computed elsewhere (on the host): record k of `src` (d bytes) goes
 // to out + idx[k] * d.
 __global__ __launch_bounds__(256) void digest_scatter_kernel(const uint64_t *__restrict__ idx,

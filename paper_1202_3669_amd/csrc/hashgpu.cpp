@@ -544,38 +544,67 @@ int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t
                         const uint64_t *dends, const uint64_t *n_dev, uint64_t nc, uint8_t *ddig, hipStream_t st,
                         bool *split) {
     *split = false;
+    if (nc == 0) return HG_OK;
     std::vector<uint64_t> ends(nc);
     HG_HIP(ctx, hipMemcpyAsync(ends.data(), dends, nc * 8, hipMemcpyDeviceToHost, st));
     HG_HIP(ctx, hipStreamSynchronize(st));
-    std::vector<uint64_t> lens(nc), order(nc);
+    std::vector<uint64_t> lens(nc), order;
     for (uint64_t j = 0; j < nc; j++) lens[j] = ends[j] - (j ? ends[j - 1] : 0);
-    std::iota(order.begin(), order.end(), (uint64_t)0);
-    std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return lens[a] > lens[b]; });
     const double lane = kind == HG_MD5 ? 110e6 : 55e6;
     const double core = kind == HG_MD5 ? 0.5e9 : (hg::host::sha1_accelerated() ? 1.5e9 : 0.5e9);
     const double cores = (double)hg::host::pool_threads() + 1;
     const double copy = hin ? 0.0 : 1.0 / 40e9;
-    uint64_t best_k = 0, bytes = 0;
-    double best = (double)lens[order[0]] / lane;
     const uint64_t kmax = std::min<uint64_t>(nc, 1u << 16);
-    for (uint64_t k = 1; k <= kmax; k++) {
-        bytes += lens[order[k - 1]];
-        // The copy (in groups of ~16 MiB) and the hashing overlap: the host
-        // is done after the whole copy and the last group's hashing, or
-        // after the first group's copy and all the hashing (the longest
-        // chunk on one core), whichever is later.
-        const double group = std::min<double>((double)bytes, (double)(16u << 20));
-        const double hash_all = std::max((double)lens[order[0]] / core, (double)bytes / (core * cores));
-        const double host_t = std::max((double)bytes * copy + group / (core * cores), group * copy + hash_all);
-        const double gpu_t = k < nc ? (double)lens[order[k]] / lane : 0.0;
-        const double t = std::max(host_t, gpu_t);
-        if (t < best) {
-            best = t;
-            best_k = k;
+    // Chunks longest first (ties by position).  The cost model below only
+    // walks the head of that order -- the host's time never falls as it
+    // takes more chunks, so the walk ends once that time alone reaches the
+    // best split so far -- so only a prefix is selected and sorted (a full
+    // sort of tens of thousands of chunks costs milliseconds), and widened
+    // if the walk runs past it.
+    std::vector<std::pair<uint64_t, uint64_t>> key(nc);
+    for (uint64_t j = 0; j < nc; j++) key[j] = {lens[j], j};
+    const auto longer = [](const std::pair<uint64_t, uint64_t> &a, const std::pair<uint64_t, uint64_t> &b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;
+    };
+    uint64_t best_k = 0;
+    double best = 0;
+    for (uint64_t m = std::min<uint64_t>(nc, 2048);; m = std::min<uint64_t>(nc, m * 8)) {
+        std::nth_element(key.begin(), key.begin() + (m - 1), key.end(), longer);
+        std::sort(key.begin(), key.begin() + m, longer);
+        best_k = 0;
+        best = (double)key[0].first / lane;
+        uint64_t bytes = 0;
+        bool done = false;
+        // k chunks on the host needs the (k+1)-th longest for the GPU's time.
+        const uint64_t kend = std::min<uint64_t>(kmax, m == nc ? nc : m - 1);
+        for (uint64_t k = 1; k <= kend; k++) {
+            bytes += key[k - 1].first;
+            // The copy (in groups of ~16 MiB) and the hashing overlap: the
+            // host is done after the whole copy and the last group's
+            // hashing, or after the first group's copy and all the hashing
+            // (the longest chunk on one core), whichever is later.
+            const double group = std::min<double>((double)bytes, (double)(16u << 20));
+            const double hash_all = std::max((double)key[0].first / core, (double)bytes / (core * cores));
+            const double host_t =
+                std::max((double)bytes * copy + group / (core * cores), group * copy + hash_all);
+            const double gpu_t = k < nc ? (double)key[k].first / lane : 0.0;
+            const double t = std::max(host_t, gpu_t);
+            if (t < best) {
+                best = t;
+                best_k = k;
+            }
+            // Past the best for good, or the rest are short: nothing more
+            // to gain.
+            if (host_t >= best || gpu_t < 1e-4) {
+                done = true;
+                break;
+            }
         }
-        if (gpu_t < 1e-4) break;  // the rest are short: nothing more to gain
+        if (done || m == nc || kend == kmax) break;
     }
     if (best_k == 0) return HG_OK;
+    order.resize(best_k);
+    for (uint64_t i = 0; i < best_k; i++) order[i] = key[i].second;
     const uint64_t k = best_k;
     std::vector<uint8_t> is_long(nc, 0);
     uint64_t host_bytes = 0;
@@ -590,18 +619,32 @@ int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t
         if (is_long[j]) idx.push_back(j);
     const int d = digest_bytes(kind);
     // Device and pinned host alike: indices (k), host digests (k * 20),
-    // GPU-side starts (nc); then, pinned only, the long chunks' bytes.
-    const size_t ibytes = (k * 8 + 255) & ~(size_t)255, gbytes = (k * 20 + 255) & ~(size_t)255, sbytes = nc * 8;
+    // GPU-side starts (nc), and for device input the gather table (k
+    // records: source offset, length, packed offset); then, pinned only,
+    // the long chunks' bytes (and on the device, packed the same way).
+    // Device input: slices of GATHER_SLICE bytes, and up to 15 bytes of
+    // padding per chunk so that each packed chunk keeps its source's address
+    // modulo 16.
+    constexpr uint64_t GATHER_SLICE = 64u << 10;
+    uint64_t n_slices = 0;
+    if (!hin)
+        for (uint64_t i = 0; i < k; i++) n_slices += (lens[idx[i]] + GATHER_SLICE - 1) / GATHER_SLICE;
+    const size_t ibytes = (k * 8 + 255) & ~(size_t)255, gbytes = (k * 20 + 255) & ~(size_t)255,
+                 sbytes = (nc * 8 + 255) & ~(size_t)255, tbytes = hin ? 0 : (n_slices * 24 + 255) & ~(size_t)255;
+    const size_t pbytes = hin ? 0 : host_bytes + 16 * k;
     void *dsplit;
-    HG_TRY(ensure(ctx, SLOT_SPLIT, ibytes + gbytes + sbytes, st, &dsplit));
+    HG_TRY(ensure(ctx, SLOT_SPLIT, ibytes + gbytes + sbytes + tbytes + pbytes, st, &dsplit));
     uint64_t *didx = (uint64_t *)dsplit;
     uint8_t *ddg = (uint8_t *)dsplit + ibytes;
     uint64_t *dstarts = (uint64_t *)(ddg + gbytes);
+    uint64_t *dtab = (uint64_t *)((uint8_t *)dstarts + sbytes);
+    uint8_t *dpacked = (uint8_t *)dtab + tbytes;
     uint8_t *hr, *hbytes;
-    HG_TRY(host_step_buffer(ctx, ibytes + gbytes + sbytes, hin ? 0 : host_bytes, &hr, &hbytes));
+    HG_TRY(host_step_buffer(ctx, ibytes + gbytes + sbytes + tbytes, pbytes, &hr, &hbytes));
     memcpy(hr, idx.data(), k * 8);
     uint8_t *hdig = hr + ibytes;
     uint64_t *hstarts = (uint64_t *)(hdig + gbytes);
+    uint64_t *htab = (uint64_t *)((uint8_t *)hstarts + sbytes);
     for (uint64_t j = 0; j < nc; j++) hstarts[j] = is_long[j] ? ends[j] : (j ? ends[j - 1] : 0);
     for (int i = 0; i < 2; i++)
         if (!ctx->split_ev[i]) HG_HIP(ctx, hipEventCreateWithFlags(&ctx->split_ev[i], hipEventDisableTiming));
@@ -615,22 +658,38 @@ int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t
     uint32_t n_groups = 0;
     if (!hin) {
         // The long chunks' bytes come back on the copy stream (the input is
-        // complete on st) in host order, in groups of ~16 MiB with an event
-        // each, so that hashing starts as soon as the first group has landed
-        // and overlaps the rest of the copy -- and the GPU's share runs
-        // meanwhile.
+        // complete on st): packed on the device in host order by one
+        // kernel, then copied in groups of ~16 MiB with an event each, so
+        // that hashing starts as soon as the first group has landed and
+        // overlaps the rest of the copy -- and the GPU's share runs
+        // meanwhile.  (One copy per chunk costs far more: each small copy
+        // has a fixed cost of its own.)
         HG_TRY(ensure_copy_stream(ctx));
-        HG_HIP(ctx, hipEventRecord(ctx->split_ev[0], st));
-        HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->split_ev[0], 0));
-        uint64_t off = 0, in_group = 0;
+        uint64_t off = 0, ns = 0;
         for (uint64_t t = 0; t < k; t++) {
             const uint64_t i = by_len[t], j = idx[i], a = j ? ends[j - 1] : 0;
+            off += (((uintptr_t)(din + a) & 15) - off) & 15;  // same address modulo 16
             src[i] = hbytes + off;
-            group[i] = n_groups;
-            HG_HIP(ctx, hipMemcpyAsync(hbytes + off, din + a, lens[j], hipMemcpyDeviceToHost, ctx->copy_stream));
+            for (uint64_t q = 0; q < lens[j]; q += GATHER_SLICE, ns++) {
+                htab[3 * ns] = a + q;
+                htab[3 * ns + 1] = std::min<uint64_t>(GATHER_SLICE, lens[j] - q);
+                htab[3 * ns + 2] = off + q;
+            }
             off += lens[j];
-            in_group += lens[j];
+        }
+        HG_HIP(ctx, hipEventRecord(ctx->split_ev[0], st));
+        HG_HIP(ctx, hipStreamWaitEvent(ctx->copy_stream, ctx->split_ev[0], 0));
+        HG_HIP(ctx, hipMemcpyAsync(dtab, htab, ns * 24, hipMemcpyHostToDevice, ctx->copy_stream));
+        HG_HIP(ctx, hg::launch_gather_ranges(din, dtab, ns, dpacked, ctx->copy_stream));
+        uint64_t g0 = 0, in_group = 0;
+        for (uint64_t t = 0; t < k; t++) {
+            const uint64_t i = by_len[t];
+            group[i] = n_groups;
+            in_group += lens[idx[i]];
             if (in_group >= (16u << 20) || t + 1 == k) {
+                const uint64_t g1 = (uint64_t)(src[i] - hbytes) + lens[idx[i]];
+                HG_HIP(ctx, hipMemcpyAsync(hbytes + g0, dpacked + g0, g1 - g0, hipMemcpyDeviceToHost,
+                                           ctx->copy_stream));
                 if (ctx->split_groups.size() <= n_groups) {
                     hipEvent_t e;
                     HG_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -639,6 +698,7 @@ int chunk_digests_split(hg_ctx *ctx, int kind, const uint8_t *din, const uint8_t
                 HG_HIP(ctx, hipEventRecord(ctx->split_groups[n_groups], ctx->copy_stream));
                 n_groups++;
                 in_group = 0;
+                g0 = g1;
             }
         }
     } else {

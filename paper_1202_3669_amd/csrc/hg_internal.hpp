@@ -125,6 +125,11 @@ size_t segment_digest_scratch_bytes(uint64_t max_n);
 // len bytes, j < *n_dev <= max_n (0 when there are none).
 hipError_t launch_max_gap(const uint64_t *ends, uint64_t len, const uint64_t *n_dev, uint64_t max_n, uint64_t *out,
                           hipStream_t s);
+// Packs k byte ranges of src into dst: range r is tab[3r + 1] bytes from
+// src + tab[3r] to dst + tab[3r + 2], where dst + tab[3r + 2] and
+// src + tab[3r] are equal modulo 16 and dst is 16-byte aligned (one
+// workgroup per range at a time: the caller cuts long ranges into slices).
+hipError_t launch_gather_ranges(const uint8_t *src, const uint64_t *tab, uint64_t k, uint8_t *dst, hipStream_t s);
 // Record k (d bytes) of src to out + idx[k] * d, k < n.
 hipError_t launch_digest_scatter(const uint64_t *idx, const uint8_t *src, uint64_t n, int d, uint8_t *out,
                                  hipStream_t s);

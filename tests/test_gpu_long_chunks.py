@@ -5,7 +5,8 @@ block-size sweep's content-based configurations on the 256 MiB version of
 the similarity workload (MD5 w=20, stride 1, mask of log2(B) bits, min B/4,
 max 4B, for B = 1 MiB and 4 MiB), from device memory and from pinned and
 pageable host memory; MD5 chunk digests; an input whose long zero run has
-no candidate (one chunk of tens of MiB); truncated output and HG_ASYNC.
+no candidate (one chunk of tens of MiB); stride 4 with hundreds of chunks
+above 64 KiB; truncated output and HG_ASYNC.
 Inputs: seeded uniform bytes (seed 3) and zero runs."""
 import os
 import sys
@@ -61,6 +62,22 @@ def test_sweep_configuration_device_and_host_input(ctx, version_a, size):
     for where, src in (("device", d), ("pinned", pinned), ("pageable", torch.from_numpy(version_a))):
         note(f"long chunks B={size // KiB}k from {where}")
         ends, dig = ctx.chunk(src, 20, 1, mask, 0, mn, max_chunk=mx)
+        torch.cuda.synchronize()
+        assert np.array_equal(ends.cpu().numpy().astype(np.uint64), xe), where
+        assert np.array_equal(dig.cpu().numpy(), xd), where
+
+
+def test_many_medium_long_chunks_at_stride_4(ctx, version_a):
+    # Stride 4 with the similarity workload's parameters (low 12 bits, min
+    # 2 KiB): chunks of 18 KiB on average and a few hundred above 64 KiB,
+    # so the host takes many chunks at once (packed on the device and copied
+    # back in groups); from device and from pageable host memory.
+    _, xe, xd = oracle.chunk(oracle.MD5, oracle.SHA1, version_a, 20, 4, 0xFFF, 0, 2 * KiB, THREADS)
+    lens = np.diff(xe, prepend=np.uint64(0))
+    assert (lens >= 64 * KiB).sum() > 100
+    for where, src in (("device", torch.from_numpy(version_a).cuda()), ("pageable", torch.from_numpy(version_a))):
+        note(f"stride 4, {int((lens >= 64 * KiB).sum())} chunks of 64 KiB and more, from {where}")
+        ends, dig = ctx.chunk(src, 20, 4, 0xFFF, 0, 2 * KiB)
         torch.cuda.synchronize()
         assert np.array_equal(ends.cpu().numpy().astype(np.uint64), xe), where
         assert np.array_equal(dig.cpu().numpy(), xd), where
