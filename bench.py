@@ -57,7 +57,7 @@ BLOCK_OPS = {0: 324, 1: 613}
 # Chunking streams (steps round-robin), each driven by its own host thread.
 CHUNK_STREAMS = 7
 CHUNK_CALLS = "single"
-AHEAD = 8  # steps issued ahead of the last finished chunking
+AHEAD = 12  # steps issued ahead of the last finished chunking
 LONG_STREAMS = 5  # streams for the per-step 1 MiB segment launches (round-robin)
 ROOT_WORKERS = 2  # host threads (each with a stream) computing the second levels
 SLOTS = 10        # ring of per-step output buffers
